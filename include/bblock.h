@@ -1,0 +1,156 @@
+/*
+ * bblock.h -- C ABI of libbblock.so: baryon blocks of the stochastic LapH
+ * method on AMD Instinct MI355X (gfx950).
+ *
+ * Operation (paper "Performance Optimization of Baryon-block Construction in
+ * the Stochastic LapH Method", Sec. 2, eq. (3), written with the
+ * reconstructed quark fields of eq. (2)):
+ *
+ *   B[p][d1][d2][d3] = sum_x exp(-i p.x) eps_abc q1[x][a][d1] q2[x][b][d2] q3[x][c][d3]
+ *
+ * per timeslice, for a set of integer momenta n with p = 2 pi n / L.  Spin
+ * projection and noise bookkeeping stay with the caller (Sec. 2, after
+ * eq. (1)); the kernel is called many times with the same momentum set
+ * (Sec. 2, after eq. (3); Sec. 3 on reusing the precomputed phase).
+ *
+ * Conventions
+ *   - site index x = ix + L*(iy + L*iz), 0 <= ix,iy,iz < L, V = L^3;
+ *   - phase exp(-i p.x) = exp(-2 pi i k / L) with k = (n.x) mod L (exact);
+ *   - eps_012 = +1; dilution indices are 0-based.
+ *
+ * Layouts (row-major, complex interleaved (re, im)):
+ *   quark field  q[t][x][colour 0..2][d], complex128 or complex64 (in_dtype)
+ *   output       B[t][p][d1][d2][d3], complex128, always OVERWRITTEN
+ *   momenta      host int32 [n_mom][3]; components may be any integers
+ *                (reduced mod L).
+ *
+ * Ownership: the caller owns every quark-field and output buffer (device
+ * memory, e.g. torch tensors) and keeps it alive until the work enqueued on
+ * the handle's stream has completed.  The handle owns its workspace (split-K
+ * partials, phase roots, descriptor and tile tables, work counters, captured
+ * graphs, tuned plans).
+ *
+ * Errors: every entry point validates its arguments on the host before it
+ * enqueues anything; on failure it returns a non-zero status, enqueues
+ * nothing and records a message readable with bblock_last_error().  Nothing
+ * is thrown across the ABI.  Work is asynchronous on the handle's stream: a
+ * device-side failure is reported as BBLOCK_EHIP by a later call or by
+ * bblock_sync().  A handle is not thread-safe; distinct handles are
+ * independent.
+ */
+#ifndef BBLOCK_H
+#define BBLOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bblock_s *bblock_t;
+
+typedef enum {
+    BBLOCK_OK = 0,
+    BBLOCK_EINVAL = 1,       /* bad argument (null pointer, size out of range, misalignment) */
+    BBLOCK_ENOMEM = 2,       /* device or host allocation failed, or workspace cap too small */
+    BBLOCK_EHIP = 3,         /* HIP runtime error (launch failure, device fault) */
+    BBLOCK_ENODEV = 4,       /* no usable gfx950 device */
+    BBLOCK_EUNSUPPORTED = 5  /* valid request this build does not implement */
+} bblock_status;
+
+/* Arithmetic of the contraction.  FP64: complex double end to end (MFMA f64).
+ * FP32: products and per-split accumulation on FP32 MFMA.  BF16X3: each FP32
+ * operand split into bf16 hi + lo, three bf16 MFMA products (hi*hi, hi*lo,
+ * lo*hi) accumulated in FP32.  For FP32 and BF16X3 the cross-split reduction
+ * and the final block sum are FP64. */
+typedef enum { BBLOCK_FP64 = 0, BBLOCK_FP32 = 1, BBLOCK_BF16X3 = 2 } bblock_prec;
+
+/* Element type of the quark fields. */
+typedef enum { BBLOCK_C128 = 0, BBLOCK_C64 = 1 } bblock_dtype;
+
+/* One block of a grouped launch: one timeslice, one spin-component triple,
+ * one noise triple (the caller's labels).  q1, q2, q3 point at a single
+ * timeslice [V][3][n_i] of in_dtype; out at [n_mom][n1][n2][n3] complex128. */
+typedef struct {
+    const void *q1, *q2, *q3;
+    int32_t n1, n2, n3;
+    int32_t reserved;
+    void *out;
+} bblock_desc;
+
+/* Launch plan of one block shape (see bblock_set_plan). */
+typedef struct {
+    int32_t nb;          /* MFMA column fragments per wave (N tile = nb * fragment width) */
+    int32_t splits;      /* split-K count over sites (>= 1); 0 = planner chooses */
+    int32_t persistent;  /* 1: persistent workgroups pull tiles from an atomic counter */
+    int32_t grid;        /* persistent grid size; 0 = planner chooses */
+} bblock_plan;
+
+/* Create a handle bound to the current HIP device.
+ *   L               lattice extent, 1 <= L <= 256 (V = L^3 sites per timeslice)
+ *   prec            bblock_prec
+ *   in_dtype        bblock_dtype of the quark fields
+ *   max_ndil        largest dilution size any call will use, 1..4096
+ *   workspace_cap   bytes of split-K workspace the handle may allocate
+ *                   (0 = 8 GiB); batches needing more run in sub-batches
+ *   hip_stream      hipStream_t to enqueue on (NULL = the null stream)
+ * Returns BBLOCK_ENODEV when no gfx950 device is current. */
+bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_dtype,
+                            int32_t max_ndil, size_t workspace_cap, void *hip_stream);
+
+/* Compute the blocks of timeslices [t_begin, t_end) of Q1, Q2, Q3
+ * ([T][V][3][n_i] device buffers) into B ([t_end - t_begin][n_mom][n1][n2][n3]
+ * complex128 device buffer).  All timeslices go through one grouped launch.
+ * Buffers must be 16-byte aligned.  n_i in 1..max_ndil, 1 <= n_mom <= 128,
+ * 0 <= t_begin < t_end. */
+bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const void *Q3,
+                             int32_t n1, int32_t n2, int32_t n3,
+                             const int32_t *mom, int32_t n_mom,
+                             int32_t t_begin, int32_t t_end, void *B);
+
+/* Grouped launch over n_desc independent blocks (uneven dilution sizes
+ * allowed), one momentum set.  The tile schedule of a batch structure is
+ * captured into a hipGraph on first use and replayed when the same structure
+ * (count, shapes, momentum count) comes back; only the descriptor table is
+ * re-uploaded.  desc is host memory, read before the call returns. */
+bblock_status bblock_compute_batch(bblock_t h, const bblock_desc *desc, int32_t n_desc,
+                                   const int32_t *mom, int32_t n_mom);
+
+/* Enable (1) or disable (0) hipGraph capture and replay in bblock_compute_batch
+ * and bblock_compute (default: enabled). */
+bblock_status bblock_set_graph(bblock_t h, int32_t enable);
+
+/* Autotune the launch plan for one block shape: times the candidate plans
+ * (column fragments per wave, split count, persistent or not) on synthetic
+ * data with HIP events, checks each candidate's result against the first
+ * candidate's, keeps the fastest, and appends it to the file named by the
+ * BBLOCK_TUNE_CACHE environment variable when that is set.  Synchronous. */
+bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom);
+
+/* Force (or, with plan == NULL, forget) the plan used for one block shape. */
+bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom,
+                              const bblock_plan *plan);
+
+/* The plan the handle would use for one block shape (forced, tuned or default). */
+bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom,
+                              bblock_plan *plan);
+
+/* Block until the handle's stream has drained; reports device-side errors. */
+bblock_status bblock_sync(bblock_t h);
+
+/* Release the handle (synchronises its stream first).  NULL is accepted. */
+bblock_status bblock_destroy(bblock_t h);
+
+/* Message of the last failure on h; with h == NULL, of the calling thread's
+ * last failed bblock_create.  Never NULL; valid until the next call on h. */
+const char *bblock_last_error(bblock_t h);
+
+/* Library version string. */
+const char *bblock_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBLOCK_H */

@@ -1,0 +1,221 @@
+"""Thin ctypes binding of libbblock.so (argument marshalling only).
+
+Every function here has the name and arguments of the C entry point declared
+in include/bblock.h; the computation runs entirely in the library's HIP
+kernels.  Device buffers are passed as torch tensors (their data pointers);
+torch only provides device memory and streams.  There is no fallback: when the
+library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbblock.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+C128, C64 = 0, 1
+PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+DTYPE = {"c128": C128, "c64": C64}
+STATUS = {0: "BBLOCK_OK", 1: "BBLOCK_EINVAL", 2: "BBLOCK_ENOMEM", 3: "BBLOCK_EHIP", 4: "BBLOCK_ENODEV",
+          5: "BBLOCK_EUNSUPPORTED"}
+
+# Every symbol include/bblock.h declares.
+EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_batch", "bblock_set_graph", "bblock_tune",
+           "bblock_set_plan", "bblock_get_plan", "bblock_sync", "bblock_destroy", "bblock_last_error",
+           "bblock_version")
+
+
+class BBlockError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class bblock_desc(ctypes.Structure):
+    _fields_ = [("q1", ctypes.c_void_p), ("q2", ctypes.c_void_p), ("q3", ctypes.c_void_p),
+                ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("out", ctypes.c_void_p)]
+
+
+class bblock_plan(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int32), ("splits", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("grid", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbblock.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libbblock.so not found at %s: build it with __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    h = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    vp = ctypes.c_void_p
+    ip = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "bblock_create": ([ctypes.POINTER(h), i32, i32, i32, i32, ctypes.c_size_t, vp], ctypes.c_int),
+        "bblock_compute": ([h, vp, vp, vp, i32, i32, i32, ip, i32, i32, i32, vp], ctypes.c_int),
+        "bblock_compute_batch": ([h, ctypes.POINTER(bblock_desc), i32, ip, i32], ctypes.c_int),
+        "bblock_set_graph": ([h, i32], ctypes.c_int),
+        "bblock_tune": ([h, i32, i32, i32, i32], ctypes.c_int),
+        "bblock_set_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
+        "bblock_get_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
+        "bblock_sync": ([h], ctypes.c_int),
+        "bblock_destroy": ([h], ctypes.c_int),
+        "bblock_last_error": ([h], ctypes.c_char_p),
+        "bblock_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(handle, status: int):
+    if status != 0:
+        msg = load().bblock_last_error(handle)
+        raise BBlockError(status, msg.decode() if msg else "")
+
+
+def _momenta(mom):
+    m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+# ------------------------------------------------------------- C names ---
+def bblock_create(L: int, prec: int, in_dtype: int, max_ndil: int, workspace_cap: int = 0, hip_stream: int = 0):
+    h = ctypes.c_void_p()
+    _check(None, load().bblock_create(ctypes.byref(h), L, prec, in_dtype, max_ndil, workspace_cap, hip_stream))
+    return h
+
+
+def bblock_compute(h, Q1, Q2, Q3, n1, n2, n3, mom, t_begin, t_end, B):
+    m, mp = _momenta(mom)
+    _check(h, load().bblock_compute(h, _ptr(Q1), _ptr(Q2), _ptr(Q3), n1, n2, n3, mp, m.shape[0], t_begin, t_end,
+                                    _ptr(B)))
+
+
+def bblock_compute_batch(h, descs, mom):
+    """descs: sequence of (q1, q2, q3, out) torch tensors (or bblock_desc)."""
+    arr = (bblock_desc * len(descs))()
+    for i, d in enumerate(descs):
+        if isinstance(d, bblock_desc):
+            arr[i] = d
+        else:
+            q1, q2, q3, out = d
+            arr[i] = bblock_desc(_ptr(q1), _ptr(q2), _ptr(q3), q1.shape[-1], q2.shape[-1], q3.shape[-1], 0,
+                                 _ptr(out))
+    m, mp = _momenta(mom)
+    _check(h, load().bblock_compute_batch(h, arr, len(descs), mp, m.shape[0]))
+
+
+def bblock_set_graph(h, enable: bool):
+    _check(h, load().bblock_set_graph(h, 1 if enable else 0))
+
+
+def bblock_tune(h, n1, n2, n3, n_mom):
+    _check(h, load().bblock_tune(h, n1, n2, n3, n_mom))
+
+
+def bblock_set_plan(h, n1, n2, n3, n_mom, plan):
+    """plan: dict(nb=, splits=, persistent=, grid=) or None to forget a forced plan."""
+    p = None if plan is None else ctypes.byref(bblock_plan(plan.get("nb", 0), plan.get("splits", 0),
+                                                           plan.get("persistent", 0), plan.get("grid", 0)))
+    _check(h, load().bblock_set_plan(h, n1, n2, n3, n_mom, p))
+
+
+def bblock_get_plan(h, n1, n2, n3, n_mom) -> dict:
+    p = bblock_plan()
+    _check(h, load().bblock_get_plan(h, n1, n2, n3, n_mom, ctypes.byref(p)))
+    return dict(nb=p.nb, splits=p.splits, persistent=p.persistent, grid=p.grid)
+
+
+def bblock_sync(h):
+    _check(h, load().bblock_sync(h))
+
+
+def bblock_destroy(h):
+    _check(None, load().bblock_destroy(h))
+
+
+def bblock_last_error(h) -> str:
+    return load().bblock_last_error(h).decode()
+
+
+def bblock_version() -> str:
+    return load().bblock_version().decode()
+
+
+# ------------------------------------------------------- convenience ---
+class BaryonBlocks:
+    """Handle wrapper.  Quark fields are torch tensors on the GPU with shape
+    [T, V, 3, n] or [V, 3, n] (complex128 for "c128", complex64 for "c64");
+    outputs are complex128 [T, n_mom, n1, n2, n3]."""
+
+    def __init__(self, L: int, prec: str = "bf16x3", in_dtype: str = "c128", max_ndil: int = 64,
+                 workspace_cap: int = 0, stream=None):
+        import torch
+        self.L, self.prec, self.in_dtype = L, prec, in_dtype
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = bblock_create(L, PREC[prec], DTYPE[in_dtype], max_ndil, workspace_cap, self.stream.cuda_stream)
+
+    def compute(self, q1, q2, q3, mom, t_begin: int = 0, t_end: int | None = None, out=None):
+        import torch
+        q1, q2, q3 = (q if q.dim() == 4 else q.unsqueeze(0) for q in (q1, q2, q3))
+        t_end = q1.shape[0] if t_end is None else t_end
+        m = np.asarray(mom, dtype=np.int32).reshape(-1, 3)
+        shape = (t_end - t_begin, m.shape[0], q1.shape[-1], q2.shape[-1], q3.shape[-1])
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex128, device=q1.device)
+        bblock_compute(self.h, q1, q2, q3, q1.shape[-1], q2.shape[-1], q3.shape[-1], m, t_begin, t_end, out)
+        return out
+
+    def compute_batch(self, descs, mom):
+        bblock_compute_batch(self.h, descs, mom)
+
+    def tune(self, n1, n2, n3, n_mom):
+        bblock_tune(self.h, n1, n2, n3, n_mom)
+
+    def set_plan(self, n1, n2, n3, n_mom, plan):
+        bblock_set_plan(self.h, n1, n2, n3, n_mom, plan)
+
+    def get_plan(self, n1, n2, n3, n_mom):
+        return bblock_get_plan(self.h, n1, n2, n3, n_mom)
+
+    def set_graph(self, enable: bool):
+        bblock_set_graph(self.h, enable)
+
+    def sync(self):
+        bblock_sync(self.h)
+
+    def close(self):
+        if self.h is not None:
+            bblock_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

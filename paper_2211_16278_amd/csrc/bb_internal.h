@@ -1,0 +1,67 @@
+// Internal declarations shared by the host API (bb_api.cpp) and the HIP
+// kernels (bb_kernels.hip) of libbblock.so.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bb {
+
+enum Prec : int { FP64 = 0, FP32 = 1, BF16X3 = 2 };
+
+// Sites per generation chunk.  Each chunk contributes 3 * CHUNK_SITES values
+// of the contraction index kappa = (colour, site) to the GEMM.
+constexpr int CHUNK_SITES = 8;
+constexpr int CHUNK_KAPPA = 3 * CHUNK_SITES;
+constexpr int THREADS = 256;  // four wave64 per workgroup
+constexpr int MAX_MOM = 128;
+constexpr int MAX_L = 256;
+
+// One baryon block as the kernels see it (device resident table).
+struct BlockDesc {
+    const void *q1, *q2, *q3;  // [V][3][n_i] complex (c128 or c64)
+    double *out;               // [n_mom][n1][n2][n3] complex128
+    void *ws;                  // split-K partials [S][2][M][N] (float or double), null if S == 1
+    int n1, n2, n3;
+    int M, N;                  // M = n1*n2 rows (d1,d2); N = n3*n_mom columns (p,d3)
+    int S;                     // number of site splits
+    int sps;                   // sites per split (multiple of CHUNK_SITES)
+    int pad;
+};
+
+// Arguments of one grouped GEMM launch.
+struct GemmArgs {
+    const BlockDesc *blocks;
+    const int4 *tiles;   // (block, m-tile, n-tile, split), cost-sorted
+    int n_tiles;
+    int *counter;        // [2] persistent work counter and exit counter; null = one tile per workgroup
+    const int *mom;      // [n_mom][3]
+    int n_mom;
+    int L, V;
+    int in_c64;
+    const double *roots; // [L] complex128 exp(-2 pi i k / L)
+};
+
+struct ReduceArgs {
+    const BlockDesc *blocks;
+    const int *list;     // indices of blocks with S > 1
+    int n_list;
+};
+
+// Geometry of one kernel instantiation.
+struct KernelGeom {
+    int m_tile;       // complex rows (d1,d2) per workgroup
+    int frag_cols;    // columns per MFMA fragment
+    int lds_bytes;    // dynamic LDS for (nb, n_mom, L)
+};
+
+// Column fragments per wave available for each precision.
+int nb_options(int prec, const int **list);
+KernelGeom kernel_geom(int prec, int nb, int n_mom, int L);
+
+hipError_t launch_gemm(int prec, int nb, const GemmArgs &a, int grid, hipStream_t st);
+hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
+hipError_t prepare_kernels(int lds_bytes);  // dynamic-LDS limit of every contraction kernel
+
+}  // namespace bb

@@ -1,0 +1,297 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Error metric (per block): err_max = max|B - R| / max|R|, R the oracle.
+Individual entries of B are sums of random-sign terms and may be arbitrarily
+small (exactly zero for identical fields), so an entrywise relative error has
+no bound; the max-normalised error is the one the tolerances refer to.
+Tolerances: FP64 path 1e-10; FP32 and BF16x3 split paths 1e-5.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_16278_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
+PRECS = ("fp64", "fp32", "bf16x3")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not os.path.exists(binding.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return torch, torch.device("cuda:0")
+
+
+def err_max(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def gpu_block(torch_dev, prec, L, qs, mom, dtype="c128", plan=None, graph=True, max_ndil=64):
+    torch, dev = torch_dev
+    tq = [torch.from_numpy(np.ascontiguousarray(q)).to(dev) for q in qs]
+    with binding.BaryonBlocks(L, prec=prec, in_dtype=dtype, max_ndil=max_ndil) as bb:
+        bb.set_graph(graph)
+        if plan is not None:
+            bb.set_plan(qs[0].shape[-1], qs[1].shape[-1], qs[2].shape[-1], len(mom), plan)
+        out = bb.compute(*tq, mom)
+        bb.sync()
+    return out[0].cpu().numpy()
+
+
+def fields(L, ns, workload=100, dtype=np.complex128, t=0):
+    return [synth.gaussian_field(L, n, workload=workload, role=i, t=t, dtype=dtype) for i, n in enumerate(ns)]
+
+
+# ------------------------------------------------------------ full blocks
+@pytest.mark.parametrize("prec", PRECS)
+def test_tiny_workload_full_block(torch_dev, prec):
+    """12^3 sites, N_dil = 32, zero momentum: every entry against the oracle."""
+    L, n = 12, 32
+    qs = synth.gaussian_fields(L, (n, n, n), workload=1)
+    mom = synth.momenta("zero")
+    say("case tiny-12", prec)
+    ref = oracle.bblock(L, *qs, mom)
+    got = gpu_block(torch_dev, prec, L, qs, mom)
+    e = err_max(got, ref)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+SHAPES = [(3, (5, 3, 7), "axis"), (5, (33, 17, 40), "cube"), (2, (1, 1, 1), "axis"), (4, (64, 2, 9), "zero"),
+          (7, (9, 31, 13), "shell4")]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L,ns,mset", SHAPES)
+def test_ragged_shapes_full_block(torch_dev, prec, L, ns, mset):
+    """Shapes that leave ragged row, column and site tiles, and several tiles."""
+    qs = fields(L, ns, workload=101)
+    mom = synth.momenta(mset)
+    say("case ragged", prec, L, ns, mset)
+    ref = oracle.bblock(L, *qs, mom)
+    got = gpu_block(torch_dev, prec, L, qs, mom)
+    e = err_max(got, ref)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_complex64_inputs(torch_dev, prec):
+    L, ns = 6, (20, 24, 28)
+    qs = fields(L, ns, workload=102, dtype=np.complex64)
+    mom = synth.momenta("axis")
+    say("case c64", prec)
+    ref = oracle.bblock(L, *qs, mom)  # the oracle upcasts the same complex64 values exactly
+    got = gpu_block(torch_dev, prec, L, qs, mom, dtype="c64")
+    e = err_max(got, ref)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+def test_identical_fields_antisymmetric_fp64(torch_dev):
+    L, n = 4, 6
+    q = synth.gaussian_field(L, n, workload=103)
+    mom = synth.momenta("axis")
+    say("case identical fields")
+    got = gpu_block(torch_dev, "fp64", L, [q, q, q], mom)
+    scale = np.abs(got).max()
+    assert np.abs(got + np.transpose(got, (0, 2, 1, 3))).max() < 1e-12 * scale
+    assert np.abs(got + np.transpose(got, (0, 1, 3, 2))).max() < 1e-12 * scale
+    assert err_max(got, oracle.bblock(L, q, q, q, mom)) < 1e-10
+
+
+# --------------------------------------------------------- plan variants
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_plan_candidate_passes(torch_dev, prec):
+    """Each tile shape / split / persistence the autotuner may pick is correct."""
+    L, ns = 5, (19, 21, 23)
+    qs = fields(L, ns, workload=104)
+    mom = synth.momenta("axis")
+    ref = oracle.bblock(L, *qs, mom)
+    opts = (1, 2, 4, 7, 14) if prec == "fp64" else (1, 2, 4, 7)
+    for nb in opts:
+        for splits in (1, 3, 16):
+            for persistent in (0, 1):
+                plan = dict(nb=nb, splits=splits, persistent=persistent, grid=7 if persistent else 0)
+                say("case plan", prec, plan)
+                e = err_max(gpu_block(torch_dev, prec, L, qs, mom, plan=plan), ref)
+                assert e < TOL[prec], (plan, e)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_determinism_graph_persistent(torch_dev, prec):
+    """Graph replay, eager launch, persistent and one-tile-per-workgroup
+    schedules give bitwise identical blocks (ordered FP64 split reduction)."""
+    L, ns = 6, (24, 24, 24)
+    qs = fields(L, ns, workload=105)
+    mom = synth.momenta("axis")
+    say("case determinism", prec)
+    a = gpu_block(torch_dev, prec, L, qs, mom, graph=False)
+    b = gpu_block(torch_dev, prec, L, qs, mom, graph=True)
+    c = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(nb=7 if prec != "fp64" else 14, splits=0, persistent=1))
+    d = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(nb=7 if prec != "fp64" else 14, splits=0, persistent=0))
+    assert np.array_equal(a, b)
+    assert np.array_equal(c, d)
+    assert err_max(a, oracle.bblock(L, *qs, mom)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_graph_replays_match_eager(torch_dev, prec):
+    """One handle: replay the captured grouped launch several times, with eager
+    work and synchronisation in between, each replay equal to the eager result."""
+    torch, dev = torch_dev
+    L, ns = 5, (16, 12, 20)
+    qs = [fields(L, ns, workload=106, t=t) for t in range(3)]
+    mom = synth.momenta("cube")
+    with binding.BaryonBlocks(L, prec=prec, in_dtype="c128", max_ndil=32) as bb:
+        tq = [[torch.from_numpy(q).to(dev) for q in trip] for trip in qs]
+        outs = [torch.zeros((len(mom), *ns), dtype=torch.complex128, device=dev) for _ in qs]
+        descs = [(a, b_, c, o) for (a, b_, c), o in zip(tq, outs)]
+        bb.set_graph(False)
+        bb.compute_batch(descs, mom)
+        bb.sync()
+        eager = [o.cpu().numpy().copy() for o in outs]
+        bb.set_graph(True)
+        for rep in range(4):
+            say("case graph replay", prec, rep)
+            for o in outs:
+                o.fill_(float("nan"))
+            bb.compute_batch(descs, mom)
+            bb.sync()
+            _ = (torch.ones(1000, device=dev) * rep).sum().item()  # eager work between replays
+            for o, e in zip(outs, eager):
+                assert np.array_equal(o.cpu().numpy(), e)
+    for trip, e in zip(qs, eager):
+        assert err_max(e, oracle.bblock(L, *trip, mom)) < TOL[prec]
+
+
+# ----------------------------------------------------------- timeslices
+@pytest.mark.parametrize("prec", PRECS)
+def test_timeslice_range(torch_dev, prec):
+    torch, dev = torch_dev
+    L, ns, T = 4, (8, 6, 10), 4
+    per_t = [fields(L, ns, workload=107, t=t) for t in range(T)]
+    Q = [np.stack([per_t[t][i] for t in range(T)]) for i in range(3)]
+    mom = synth.momenta("axis")
+    say("case timeslices", prec)
+    with binding.BaryonBlocks(L, prec=prec, in_dtype="c128", max_ndil=16) as bb:
+        out = bb.compute(*[torch.from_numpy(q).to(dev) for q in Q], mom, t_begin=1, t_end=4)
+        bb.sync()
+    got = out.cpu().numpy()
+    assert got.shape == (3, len(mom), *ns)
+    for i, t in enumerate(range(1, 4)):
+        assert err_max(got[i], oracle.bblock(L, *per_t[t], mom)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_uneven_batch(torch_dev, prec):
+    """Blocks with N_dil in {16, 32, 64} (and mixed within a block) in one grouped launch."""
+    torch, dev = torch_dev
+    L = 4
+    shapes = [(16, 16, 16), (64, 64, 64), (32, 32, 32), (16, 64, 32), (32, 16, 64)]
+    mom = synth.momenta("axis")
+    trips = [fields(L, s, workload=108, t=i, dtype=np.complex64) for i, s in enumerate(shapes)]
+    say("case uneven batch", prec)
+    with binding.BaryonBlocks(L, prec=prec, in_dtype="c64", max_ndil=64) as bb:
+        tq = [[torch.from_numpy(q).to(dev) for q in trip] for trip in trips]
+        outs = [torch.empty((len(mom), *s), dtype=torch.complex128, device=dev) for s in shapes]
+        bb.compute_batch([(*t, o) for t, o in zip(tq, outs)], mom)
+        bb.sync()
+    for trip, o in zip(trips, outs):
+        assert err_max(o.cpu().numpy(), oracle.bblock(L, *trip, mom)) < TOL[prec]
+
+
+def test_tune_then_compute(torch_dev):
+    L, ns = 6, (24, 24, 24)
+    qs = fields(L, ns, workload=109)
+    mom = synth.momenta("axis")
+    torch, dev = torch_dev
+    say("case tune")
+    with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
+        bb.tune(*ns, len(mom))
+        plan = bb.get_plan(*ns, len(mom))
+        assert plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
+        out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
+        bb.sync()
+    assert err_max(out[0].cpu().numpy(), oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
+
+
+# ---------------------------------------------------- full-size sampled
+def _sampled(torch_dev, prec, L, n, mset, dtype, rows, workload):
+    qs = synth.gaussian_fields(L, (n, n, n), workload=workload,
+                               dtype=np.complex64 if dtype == "c64" else np.complex128)
+    mom = synth.momenta(mset)
+    got = gpu_block(torch_dev, prec, L, qs, mom, dtype=dtype)
+    ref = oracle.bblock_rows(L, *qs, mom, rows)
+    sub = np.stack([got[:, d1, d2, :] for d1, d2 in rows], axis=1)
+    return err_max(sub, ref)
+
+
+ROWS32 = np.array([[0, 0], [0, 31], [31, 0], [31, 31], [7, 19], [16, 16], [3, 28], [25, 9]], dtype=np.int32)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_headline_32_sampled(torch_dev, prec):
+    """32^3 sites, N_dil = 32, 7 momenta, c128: the benchmarked workload and plan."""
+    say("case headline-32 sampled", prec)
+    e = _sampled(torch_dev, prec, 32, 32, "axis", "c128", ROWS32, workload=2)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ("fp64", "bf16x3"))
+def test_large_64_sampled(torch_dev, prec):
+    """64^3 sites, N_dil = 64, 33 momenta, c128 (one timeslice), sampled rows."""
+    rows = np.array([[0, 0], [63, 63], [12, 50], [40, 7]], dtype=np.int32)
+    say("case large-64 sampled", prec)
+    e = _sampled(torch_dev, prec, 64, 64, "shell4", "c128", rows, workload=5)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+# --------------------------------------------------------- error paths
+def test_error_paths_enqueue_nothing(torch_dev):
+    torch, dev = torch_dev
+    lib = binding.load()
+    L, n = 3, 4
+    q = torch.zeros((L ** 3, 3, n), dtype=torch.complex128, device=dev)
+    out = torch.full((1, n, n, n), 7.0, dtype=torch.complex128, device=dev)
+    m = (ctypes.c_int32 * 3)(0, 0, 0)
+    h = binding.bblock_create(L, binding.FP64, binding.C128, 8)
+    try:
+        p, o = q.data_ptr(), out.data_ptr()
+        cases = {
+            "null q": (None, p, p, n, n, n, m, 1, 0, 1, o),
+            "null out": (p, p, p, n, n, n, m, 1, 0, 1, None),
+            "n > max_ndil": (p, p, p, 9, n, n, m, 1, 0, 1, o),
+            "n = 0": (p, p, p, 0, n, n, m, 1, 0, 1, o),
+            "empty t range": (p, p, p, n, n, n, m, 1, 1, 1, o),
+            "negative t": (p, p, p, n, n, n, m, 1, -1, 1, o),
+            "n_mom = 0": (p, p, p, n, n, n, m, 0, 0, 1, o),
+            "null momenta": (p, p, p, n, n, n, None, 1, 0, 1, o),
+            "misaligned": (p + 8, p, p, n, n, n, m, 1, 0, 1, o),
+        }
+        for name, args in cases.items():
+            say("case error path", name)
+            assert lib.bblock_compute(h, *args) == 1, name
+            assert binding.bblock_last_error(h)
+        binding.bblock_sync(h)
+        assert torch.all(out == 7.0).item()
+    finally:
+        binding.bblock_destroy(h)
