@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Baryon-block benchmark on one MI355X.
+
+A step is one pass of the whole hot path over one block of synthetic input:
+the fused contraction kernel (diquark, phase-weighted third quark, MFMA
+complex GEMM) plus the FP64 split-K reduction that writes B.  The default
+workload is 32^3 sites, N_dil = 32 for all three quark fields, 7 momenta
+(0 and the six unit vectors), complex128 inputs, one timeslice; inputs are
+resident in HBM before timing starts.  All three arithmetic paths are timed;
+the headline value is the BF16x3 split-precision path in blocks/s.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--paths fp64,fp32,bf16x3]
+                       [--no-cpu-baseline] [--calib-copy-mib M]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "baryon-block TFLOP/s + blocks/s, 32^3 N_dil=32: FP64 vs split-prec MFMA"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6}  # dense MFMA peaks of the operand type
+MFMA_PASSES = {"fp64": 1, "fp32": 1, "bf16x3": 3}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
+KERNEL_PREC = {"fp64": "FP64", "fp32": "FP32", "bf16x3": "BF16X3"}
+
+
+def flops(V, n1, n2, n3, n_mom):
+    """F_gemm: what the MFMA formulation executes (8 real flops per complex
+    multiply-add over K = 3V, M = n1 n2, N = n3 n_mom).  F_alg: the paper's
+    operation order (diquark, singlet, momentum projection)."""
+    f_gemm = 24.0 * n_mom * V * n1 * n2 * n3
+    f_alg = 42.0 * V * n1 * n2 + (22.0 + 8.0 * n_mom) * V * n1 * n2 * n3
+    return f_gemm, f_alg
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("paper_2211_16278_amd/csrc/bb_kernels.hip", "paper_2211_16278_amd/csrc/bb_internal.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(path_name: str, workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when there is none or the kernel source changed since."""
+    fn = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (path_name, workload))
+    if not os.path.exists(fn):
+        return None
+    with open(fn) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(L, qs, mom, M, target_s=15.0):
+    """The oracle, untuned, on a bounded sample of (d1, d2) rows of one block."""
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    n2 = qs[1].shape[2]
+    pilot = max(1, min(M, threads))
+    rows = np.array([[r // n2, r % n2] for r in range(pilot)], dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.bblock_rows(L, *qs, mom, rows)
+    dt = time.perf_counter() - t0
+    per_row = dt / pilot
+    n_rows = int(min(M, max(pilot, round(target_s / per_row))))
+    rows = np.array([[r // n2, r % n2] for r in range(n_rows)], dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.bblock_rows(L, *qs, mom, rows)
+    dt = time.perf_counter() - t0
+    return {"value": (n_rows / M) / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d (d1,d2) rows of one block (all d3, all %d momenta), %.1f s; value scaled to "
+                      "whole blocks" % (n_rows, M, len(mom), dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--paths", default="fp64,fp32,bf16x3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (blocks shard across GPUs with no "
+              "communication; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2211_16278_amd import binding, synth
+
+    if not os.path.exists(binding.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    wl = synth.WORKLOADS["headline-32"]
+    L, n = wl["L"], wl["ndil"]
+    V = L ** 3
+    mom = synth.momenta(wl["momenta"])
+    n_mom = len(mom)
+    qs = synth.gaussian_fields(L, (n, n, n), workload=2)
+    tq = [torch.from_numpy(q).to(dev) for q in qs]
+    out = torch.empty((1, n_mom, n, n, n), dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    f_gemm, f_alg = flops(V, n, n, n, n_mom)
+    stream = torch.cuda.current_stream()
+
+    rows = np.array([[0, 0], [31, 31], [7, 19], [16, 3]], dtype=np.int32)
+    ref_rows = None
+    if not args.no_parity:
+        import oracle
+        ref_rows = oracle.bblock_rows(L, *qs, mom, rows)
+
+    paths = {}
+    for pname in [p for p in args.paths.split(",") if p]:
+        bb = binding.BaryonBlocks(L, prec=pname, in_dtype="c128", max_ndil=n, stream=stream)
+        plan = bb.get_plan(n, n, n, n_mom)
+        for _ in range(args.warmup):
+            bb.compute(*tq, mom, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            bb.compute(*tq, mom, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        # Per-kernel durations: HIP events around each launch on the library's stream.
+        bb.profile(True)
+        bb.profile_read()
+        for _ in range(args.steps):
+            bb.compute(*tq, mom, out=out)
+        gemm_ms, red_ms, launches = bb.profile_read()
+        bb.profile(False)
+        err = None
+        if ref_rows is not None:
+            got = out[0].cpu().numpy()
+            sub = np.stack([got[:, d1, d2, :] for d1, d2 in rows], axis=1)
+            err = float(np.abs(sub - ref_rows).max() / np.abs(ref_rows).max())
+        bb.close()
+        step_ms = max(ms, wall * 1e3) / args.steps
+        g_avg = gemm_ms / max(1, launches)
+        ach = MFMA_PASSES[pname] * f_gemm / (g_avg * 1e-3) / 1e12
+        paths[pname] = {
+            "blocks_per_s": 1e3 / step_ms,
+            "ms_per_step": step_ms,
+            "tflops_gemm_count": f_gemm / (step_ms * 1e-3) / 1e12,
+            "tflops_paper_count": f_alg / (step_ms * 1e-3) / 1e12,
+            "contraction_kernel_ms": g_avg,
+            "reduce_kernel_ms": red_ms / max(1, launches),
+            "mfma_tflops": ach,
+            "mfma_peak_tflops": PEAK_TFLOPS[pname],
+            "mfma_frac": ach / PEAK_TFLOPS[pname],
+            "err_max_sampled": err,
+            "tol": TOL[pname],
+            "plan": plan,
+        }
+        print("# %-6s %.3f ms/block  %.1f blocks/s  contraction %.3f ms  reduce %.3f ms  MFMA %.1f TF (%.1f%%)  "
+              "err %s" % (pname, step_ms, 1e3 / step_ms, g_avg, red_ms / max(1, launches), ach,
+                          100 * ach / PEAK_TFLOPS[pname], "%.2e" % err if err is not None else "-"),
+              file=sys.stderr, flush=True)
+
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# calibration copy: %d bytes read, %d bytes written" % (nbytes, nbytes), file=sys.stderr)
+
+    head = "bf16x3" if "bf16x3" in paths else next(iter(paths))
+    hp = paths[head]
+    traffic = read_traffic(head, "headline-32")
+    rec = {
+        "metric": METRIC,
+        "value": hp["blocks_per_s"],
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hp["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic (seeded iid complex normal quark fields)",
+        "config": {"workload": "headline-32: 32^3 sites, N_dil=32 (n1=n2=n3), 7 momenta {0, +-e_x, +-e_y, +-e_z}, "
+                               "complex128 inputs, one timeslice per step",
+                   "L": L, "n_dil": n, "n_mom": n_mom, "in_dtype": "c128", "blocks_per_step": 1},
+        "tflops": {"gemm_count": hp["tflops_gemm_count"], "paper_count": hp["tflops_paper_count"]},
+        "roofline": {"bound": "mfma", "kernel": "bb::bb_gemm<%s, %d>" % (KERNEL_PREC[head], hp["plan"]["nb"]), "achieved": hp["mfma_tflops"],
+                     "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s", "frac": hp["mfma_frac"],
+                     "traffic": traffic,
+                     "flops_per_launch": MFMA_PASSES[head] * f_gemm,
+                     "note": "achieved = MFMA flops of one block (%d x 24 n_mom V n^3) / mean event-timed duration "
+                             "of the contraction kernel" % MFMA_PASSES[head]},
+        "paths": paths,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(L, qs, mom, n * n)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

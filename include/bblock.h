@@ -136,6 +136,18 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
 bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom,
                               bblock_plan *plan);
 
+/* Kernel timing.  While enabled (enable = 1), launches run eagerly (never
+ * from a captured graph) and every contraction-kernel and reduction-kernel
+ * launch is bracketed by HIP events recorded on the handle's stream. */
+bblock_status bblock_profile(bblock_t h, int32_t enable);
+
+/* Synchronises on the last recorded event, then returns the summed
+ * event-timed milliseconds of the contraction kernels (gemm_ms) and of the
+ * split-K reduction kernels (reduce_ms) recorded since the previous read, and
+ * the number of contraction launches among them.  Any output pointer may be
+ * NULL. */
+bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms, int32_t *gemm_launches);
+
 /* Block until the handle's stream has drained; reports device-side errors. */
 bblock_status bblock_sync(bblock_t h);
 

@@ -25,8 +25,8 @@ STATUS = {0: "BBLOCK_OK", 1: "BBLOCK_EINVAL", 2: "BBLOCK_ENOMEM", 3: "BBLOCK_EHI
 
 # Every symbol include/bblock.h declares.
 EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_batch", "bblock_set_graph", "bblock_tune",
-           "bblock_set_plan", "bblock_get_plan", "bblock_sync", "bblock_destroy", "bblock_last_error",
-           "bblock_version")
+           "bblock_set_plan", "bblock_get_plan", "bblock_profile", "bblock_profile_read", "bblock_sync",
+           "bblock_destroy", "bblock_last_error", "bblock_version")
 
 
 class BBlockError(RuntimeError):
@@ -69,6 +69,9 @@ def load(path: str = LIB_PATH):
         "bblock_tune": ([h, i32, i32, i32, i32], ctypes.c_int),
         "bblock_set_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
         "bblock_get_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
+        "bblock_profile": ([h, i32], ctypes.c_int),
+        "bblock_profile_read": ([h, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "bblock_sync": ([h], ctypes.c_int),
         "bblock_destroy": ([h], ctypes.c_int),
         "bblock_last_error": ([h], ctypes.c_char_p),
@@ -145,6 +148,17 @@ def bblock_get_plan(h, n1, n2, n3, n_mom) -> dict:
     return dict(nb=p.nb, splits=p.splits, persistent=p.persistent, grid=p.grid)
 
 
+def bblock_profile(h, enable: bool):
+    _check(h, load().bblock_profile(h, 1 if enable else 0))
+
+
+def bblock_profile_read(h):
+    """(gemm_ms, reduce_ms, gemm_launches) summed since the previous read."""
+    g, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _check(h, load().bblock_profile_read(h, ctypes.byref(g), ctypes.byref(r), ctypes.byref(n)))
+    return g.value, r.value, n.value
+
+
 def bblock_sync(h):
     _check(h, load().bblock_sync(h))
 
@@ -199,6 +213,12 @@ class BaryonBlocks:
 
     def set_graph(self, enable: bool):
         bblock_set_graph(self.h, enable)
+
+    def profile(self, enable: bool):
+        bblock_profile(self.h, enable)
+
+    def profile_read(self):
+        return bblock_profile_read(self.h)
 
     def sync(self):
         bblock_sync(self.h)

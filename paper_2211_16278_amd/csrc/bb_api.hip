@@ -61,6 +61,9 @@ struct bblock_s {
     size_t ws_size = 0;
 
     bool graph_enabled = true;
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::array<hipEvent_t, 2>> ev_gemm, ev_reduce;
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
     std::map<ShapeKey, Plan> forced, tuned;
     std::string err;
@@ -214,6 +217,18 @@ struct SubBatch {
     int max_mn;
 };
 
+hipEvent_t take_event(bblock_t h)
+{
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
 // Launch the kernels of all sub-batches on stream st; tables already uploaded.
 bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_blocks, size_t off_tiles,
                       size_t off_list, size_t off_mom, int n_mom, hipStream_t st)
@@ -231,15 +246,34 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_
         ga.in_c64 = h->in_dtype == BBLOCK_C64;
         ga.roots = h->d_roots;
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
+        std::array<hipEvent_t, 2> ev{nullptr, nullptr};
+        if (h->profiling) {
+            ev = {take_event(h), take_event(h)};
+            if (!ev[0] || !ev[1]) return fail(h, BBLOCK_EHIP, "profiling event creation failed");
+            HIP_OR_FAIL(h, hipEventRecord(ev[0], st));
+        }
         hipError_t e = launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
+        if (h->profiling) {
+            HIP_OR_FAIL(h, hipEventRecord(ev[1], st));
+            h->ev_gemm.push_back(ev);
+        }
         if (sb.n_list > 0) {
             ReduceArgs ra;
             ra.blocks = ga.blocks;
             ra.list = reinterpret_cast<const int *>(h->d_table + off_list) + sb.list_off;
             ra.n_list = sb.n_list;
+            if (h->profiling) {
+                ev = {take_event(h), take_event(h)};
+                if (!ev[0] || !ev[1]) return fail(h, BBLOCK_EHIP, "profiling event creation failed");
+                HIP_OR_FAIL(h, hipEventRecord(ev[0], st));
+            }
             e = launch_reduce(h->prec, ra, sb.max_mn, st);
             if (e != hipSuccess) return hip_fail(h, e, "launch of the split-K reduction");
+            if (h->profiling) {
+                HIP_OR_FAIL(h, hipEventRecord(ev[1], st));
+                h->ev_reduce.push_back(ev);
+            }
         }
     }
     return BBLOCK_OK;
@@ -381,7 +415,8 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_table, hs, bytes, hipMemcpyHostToDevice, h->stream));
     HIP_OR_FAIL(h, hipEventRecord(h->staging_free, h->stream));
 
-    if (!h->graph_enabled) return enqueue(h, subs, off_blocks, off_tiles, off_list, off_mom, n_mom, h->stream);
+    if (!h->graph_enabled || h->profiling)
+        return enqueue(h, subs, off_blocks, off_tiles, off_list, off_mom, n_mom, h->stream);
 
     // Graph signature: everything baked into kernel arguments.
     std::vector<long long> sig;
@@ -708,6 +743,38 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
     return BBLOCK_OK;
 }
 
+bblock_status bblock_profile(bblock_t h, int32_t enable)
+{
+    if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
+    h->profiling = enable != 0;
+    return BBLOCK_OK;
+}
+
+bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms, int32_t *gemm_launches)
+{
+    if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
+    double sums[2] = {0.0, 0.0};
+    const int n_gemm = (int)h->ev_gemm.size();
+    bblock_status st = BBLOCK_OK;
+    std::vector<std::array<hipEvent_t, 2>> *lists[2] = {&h->ev_gemm, &h->ev_reduce};
+    for (int k = 0; k < 2; ++k) {
+        for (auto &ev : *lists[k]) {
+            float ms = 0.0f;
+            hipError_t e = hipEventSynchronize(ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess && st == BBLOCK_OK) st = hip_fail(h, e, "reading profiling events");
+            sums[k] += ms;
+            h->ev_pool.push_back(ev[0]);
+            h->ev_pool.push_back(ev[1]);
+        }
+        lists[k]->clear();
+    }
+    if (gemm_ms) *gemm_ms = sums[0];
+    if (reduce_ms) *reduce_ms = sums[1];
+    if (gemm_launches) *gemm_launches = n_gemm;
+    return st;
+}
+
 bblock_status bblock_sync(bblock_t h)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
@@ -727,6 +794,9 @@ bblock_status bblock_destroy(bblock_t h)
     if (h->d_roots) (void)hipFree(h->d_roots);
     if (h->d_counter) (void)hipFree(h->d_counter);
     if (h->staging_free) (void)hipEventDestroy(h->staging_free);
+    for (auto &ev : h->ev_gemm) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
+    for (auto &ev : h->ev_reduce) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return BBLOCK_OK;
