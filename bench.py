@@ -28,7 +28,15 @@ METRIC = "baryon-block TFLOP/s + blocks/s, 32^3 N_dil=32: FP64 vs split-prec MFM
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6}  # dense MFMA peaks of the operand type
 MFMA_PASSES = {"fp64": 1, "fp32": 1, "bf16x3": 3}
 TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
-KERNEL_PREC = {"fp64": "FP64", "fp32": "FP32", "bf16x3": "BF16X3"}
+PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+def kernel_name(path, plan, n2, n3):
+    """Name of the contraction kernel a plan launches (as rocprofv3 lists it)."""
+    if plan["kernel"] == 1:
+        b2, b3 = (32 if n2 >= 32 else 16), (32 if n3 >= 32 else 16)
+        return "bb::fast::bb_fast<%d, %d, %d, %d, false>" % (PREC_ID[path], plan["nb"], b2, b3)
+    return "bb::bb_gemm<%d, %d>" % (PREC_ID[path], plan["nb"])
 
 
 def flops(V, n1, n2, n3, n_mom):
@@ -208,7 +216,7 @@ def main() -> int:
                                "complex128 inputs, one timeslice per step",
                    "L": L, "n_dil": n, "n_mom": n_mom, "in_dtype": "c128", "blocks_per_step": 1},
         "tflops": {"gemm_count": hp["tflops_gemm_count"], "paper_count": hp["tflops_paper_count"]},
-        "roofline": {"bound": "mfma", "kernel": "bb::bb_gemm<%s, %d>" % (KERNEL_PREC[head], hp["plan"]["nb"]), "achieved": hp["mfma_tflops"],
+        "roofline": {"bound": "mfma", "kernel": kernel_name(head, hp["plan"], n, n), "achieved": hp["mfma_tflops"],
                      "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s", "frac": hp["mfma_frac"],
                      "traffic": traffic,
                      "flops_per_launch": MFMA_PASSES[head] * f_gemm,

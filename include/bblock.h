@@ -85,6 +85,9 @@ typedef struct {
     int32_t splits;      /* split-K count over sites (>= 1); 0 = planner chooses */
     int32_t persistent;  /* 1: persistent workgroups pull tiles from an atomic counter */
     int32_t grid;        /* persistent grid size; 0 = planner chooses */
+    int32_t kernel;      /* 0: generic tiles (any shape, every precision);
+                            1: pipelined rectangular tiles (FP32 and BF16X3,
+                               n2 >= 16 and n3 >= 16; nb 4 or 7) */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device.

@@ -43,7 +43,7 @@ class bblock_desc(ctypes.Structure):
 
 class bblock_plan(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int32), ("splits", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("grid", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 _lib = None
@@ -136,16 +136,17 @@ def bblock_tune(h, n1, n2, n3, n_mom):
 
 
 def bblock_set_plan(h, n1, n2, n3, n_mom, plan):
-    """plan: dict(nb=, splits=, persistent=, grid=) or None to forget a forced plan."""
+    """plan: dict(kernel=, nb=, splits=, persistent=, grid=) or None to forget a forced plan."""
     p = None if plan is None else ctypes.byref(bblock_plan(plan.get("nb", 0), plan.get("splits", 0),
-                                                           plan.get("persistent", 0), plan.get("grid", 0)))
+                                                           plan.get("persistent", 0), plan.get("grid", 0),
+                                                           plan.get("kernel", 0)))
     _check(h, load().bblock_set_plan(h, n1, n2, n3, n_mom, p))
 
 
 def bblock_get_plan(h, n1, n2, n3, n_mom) -> dict:
     p = bblock_plan()
     _check(h, load().bblock_get_plan(h, n1, n2, n3, n_mom, ctypes.byref(p)))
-    return dict(nb=p.nb, splits=p.splits, persistent=p.persistent, grid=p.grid)
+    return dict(kernel=p.kernel, nb=p.nb, splits=p.splits, persistent=p.persistent, grid=p.grid)
 
 
 def bblock_profile(h, enable: bool):

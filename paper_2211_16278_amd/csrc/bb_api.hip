@@ -1,12 +1,12 @@
 // Host side of libbblock.so: the C ABI declared in include/bblock.h.
 //
-// Responsibilities: argument validation, the phase-root table (paper, Sec. 3:
+// Responsibilities: argument validation, the phase tables (paper, Sec. 3:
 // the phase of the momentum projection is precomputed and reused across
-// kernel invocations with the same momentum set), the planner (tile shape,
-// split-K count, workspace), the grouped tile schedule, hipGraph capture and
-// replay of grouped launches, and the autotuner (the paper tunes its block
-// sizes experimentally per machine, Sec. 4; here the tile shape and split
-// count are timed on the device).
+// kernel invocations with the same momentum set), the planner (kernel, tile
+// shape, split-K count, workspace), the grouped tile schedule, hipGraph
+// capture and replay of grouped launches, and the autotuner (the paper tunes
+// its block sizes experimentally per machine, Sec. 4; here the kernel, tile
+// shape, split count and scheduling mode are timed on the device).
 
 #include <algorithm>
 #include <array>
@@ -30,14 +30,25 @@ thread_local std::string g_create_error;
 
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
+constexpr int K_GENERIC = 0, K_PIPELINED = 1;
 
 struct Plan {
-    int nb = 0, splits = 0, persistent = 0, grid = 0;
+    int kernel = K_GENERIC, nb = 0, splits = 0, persistent = 0, grid = 0;
 };
 
 using ShapeKey = std::array<int, 4>;  // n1, n2, n3, n_mom
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Tile geometry of one block shape under one (kernel, nb).
+struct Geometry {
+    int kernel = K_GENERIC, nb = 0;
+    int m_tile = 0, n_tile = 0;  // complex rows / columns per tile
+    int b1 = 0, b2 = 0, b3 = 0, bp = 0, n_mt2 = 1, n_nt3 = 1;  // pipelined rectangles
+    int n_mt = 0, n_nt = 0;
+    int lds = -1;
+};
 
 }  // namespace
 
@@ -59,6 +70,9 @@ struct bblock_s {
     hipEvent_t staging_free = nullptr;
     void *d_ws = nullptr;
     size_t ws_size = 0;
+    unsigned char *d_kidx = nullptr;  // [n_mom][V] phase index of the cached momentum set
+    size_t kidx_cap = 0;
+    std::vector<int> kidx_mom;        // momentum set (reduced mod L) the table holds
 
     bool graph_enabled = true;
     bool profiling = false;
@@ -105,31 +119,70 @@ void clear_graphs(bblock_t h)
     h->graphs.clear();
 }
 
-// Default plan of one block shape: the N tile covers the columns (p, d3) in
-// as few tiles as possible, the split count fills the device for a single
-// block and keeps FP32 accumulation chains bounded.
+int pipelined_block(int n) { return n >= 32 ? 32 : (n >= 16 ? 16 : 0); }
+
+// Geometry of (kernel, nb) for one block shape; lds < 0 when unsupported.
+Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_mom)
+{
+    Geometry g;
+    g.kernel = kernel;
+    g.nb = nb;
+    if (kernel == K_PIPELINED) {
+        g.b2 = pipelined_block(n2);
+        g.b3 = pipelined_block(n3);
+        if (h->prec == FP64 || g.b2 == 0 || g.b3 == 0 || (nb != 4 && nb != 7)) return g;
+        g.b1 = 128 / g.b2;
+        g.m_tile = 128;
+        g.n_tile = 32 * nb;
+        g.bp = std::min(n_mom, g.n_tile / g.b3);
+        g.n_mt2 = cdiv(n2, g.b2);
+        g.n_nt3 = cdiv(n3, g.b3);
+        g.n_mt = cdiv(n1, g.b1) * g.n_mt2;
+        g.n_nt = cdiv(n_mom, g.bp) * g.n_nt3;
+        g.lds = fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
+    } else {
+        const KernelGeom k = kernel_geom(h->prec, nb, n_mom, h->L);
+        if (k.lds_bytes <= 0) return g;
+        g.m_tile = k.m_tile;
+        g.n_tile = nb * k.frag_cols;
+        g.n_mt = cdiv(n1 * n2, g.m_tile);
+        g.n_nt = cdiv(n3 * n_mom, g.n_tile);
+        g.lds = k.lds_bytes;
+    }
+    if (g.lds > h->lds_max) g.lds = -1;
+    return g;
+}
+
+// Default plan of one block shape: the pipelined kernel where it applies
+// (fewest padded columns, then the wider tile), else the generic kernel with
+// the N tile covering the columns in as few tiles as possible; the split
+// count fills the device for a single block.
 Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
 {
-    const int *opts;
-    const int n_opts = nb_options(h->prec, &opts);
-    const KernelGeom g0 = kernel_geom(h->prec, opts[0], n_mom, h->L);
-    const int N = n3 * n_mom, M = n1 * n2;
-    const int max_nb = opts[n_opts - 1];
-    const int n_nt = (N + max_nb * g0.frag_cols - 1) / (max_nb * g0.frag_cols);
-    const int want_nb = (N + n_nt * g0.frag_cols - 1) / (n_nt * g0.frag_cols);
     Plan p;
-    p.nb = max_nb;
-    for (int i = 0; i < n_opts; ++i)
-        if (opts[i] >= want_nb) {
-            p.nb = opts[i];
-            break;
+    Geometry best;
+    for (int nb : {7, 4}) {
+        const Geometry g = geometry(h, K_PIPELINED, nb, n1, n2, n3, n_mom);
+        if (g.lds < 0) continue;
+        if (best.lds < 0 || (long)g.n_nt * g.n_tile < (long)best.n_nt * best.n_tile) best = g;
+    }
+    if (best.lds < 0) {
+        const int *opts;
+        const int n_opts = nb_options(h->prec, &opts);
+        const int frag = kernel_geom(h->prec, opts[0], n_mom, h->L).frag_cols;
+        const int N = n3 * n_mom, max_nb = opts[n_opts - 1];
+        const int n_nt = cdiv(N, max_nb * frag);
+        const int want_nb = cdiv(N, n_nt * frag);
+        for (int i = n_opts - 1; i >= 0; --i) {
+            const Geometry g = geometry(h, K_GENERIC, opts[i], n1, n2, n3, n_mom);
+            if (g.lds < 0) continue;
+            if (best.lds < 0 || opts[i] >= want_nb) best = g;
         }
-    const KernelGeom g = kernel_geom(h->prec, p.nb, n_mom, h->L);
-    const long tiles = (long)((M + g.m_tile - 1) / g.m_tile) * ((N + p.nb * g.frag_cols - 1) / (p.nb * g.frag_cols));
-    long s = (h->num_cu + tiles - 1) / tiles;
-    p.splits = (int)std::max<long>(1, s);
-    p.persistent = 0;
-    p.grid = 0;
+    }
+    p.kernel = best.kernel;
+    p.nb = best.nb;
+    const long tiles = std::max(1L, (long)best.n_mt * best.n_nt);
+    p.splits = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
     return p;
 }
 
@@ -152,7 +205,7 @@ int min_splits(bblock_t h)
 struct BlockPlan {
     BlockDesc d;
     Plan plan;
-    int n_mt, n_nt;
+    Geometry g;
     size_t ws_bytes;
 };
 
@@ -161,7 +214,7 @@ struct BlockPlan {
 void set_splits(bblock_t h, BlockPlan &bp, int S)
 {
     S = std::max(1, std::min(S, (h->V + CHUNK_SITES - 1) / CHUNK_SITES));
-    int sps = (int)align_up((size_t)((h->V + S - 1) / S), CHUNK_SITES);
+    const int sps = (int)align_up((size_t)((h->V + S - 1) / S), CHUNK_SITES);
     bp.d.sps = sps;
     bp.d.S = (h->V + sps - 1) / sps;
     bp.ws_bytes = bp.d.S > 1 ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
@@ -188,7 +241,7 @@ bblock_status ensure_table(bblock_t h, size_t bytes)
     h->d_table = nullptr;
     h->h_staging = nullptr;
     h->table_cap = 0;
-    const size_t cap = align_up(std::max(bytes, bytes + bytes / 2), 1 << 16);
+    const size_t cap = align_up(bytes + bytes / 2, 1 << 16);
     if (hipMalloc(&h->d_table, cap) != hipSuccess) return fail(h, BBLOCK_ENOMEM, "table allocation of %zu bytes", cap);
     if (hipHostMalloc(&h->h_staging, cap, hipHostMallocDefault) != hipSuccess)
         return fail(h, BBLOCK_ENOMEM, "pinned staging allocation of %zu bytes", cap);
@@ -200,6 +253,7 @@ bblock_status ensure_ws(bblock_t h, size_t bytes)
 {
     if (bytes <= h->ws_size) return BBLOCK_OK;
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    clear_graphs(h);
     if (h->d_ws) (void)hipFree(h->d_ws);
     h->d_ws = nullptr;
     h->ws_size = 0;
@@ -208,11 +262,35 @@ bblock_status ensure_ws(bblock_t h, size_t bytes)
     return BBLOCK_OK;
 }
 
+// Phase-index table kidx[p][x] = (n_p . x) mod L of one momentum set, built on
+// the device when the set changes (reused across calls, paper Sec. 3).
+// d_mom: the reduced momenta already uploaded to the device.
+bblock_status ensure_kidx(bblock_t h, const std::vector<int> &mom_red, const int *d_mom)
+{
+    if (mom_red == h->kidx_mom && h->d_kidx) return BBLOCK_OK;
+    const int n_mom = (int)mom_red.size() / 3;
+    const size_t bytes = (size_t)n_mom * h->V;
+    if (bytes > h->kidx_cap) {
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        clear_graphs(h);
+        if (h->d_kidx) (void)hipFree(h->d_kidx);
+        h->d_kidx = nullptr;
+        h->kidx_cap = 0;
+        if (hipMalloc(&h->d_kidx, bytes) != hipSuccess)
+            return fail(h, BBLOCK_ENOMEM, "phase table allocation of %zu bytes", bytes);
+        h->kidx_cap = bytes;
+    }
+    const hipError_t e = launch_phase_index(d_mom, n_mom, h->L, h->d_kidx, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "launch of the phase-index kernel");
+    h->kidx_mom = mom_red;
+    return BBLOCK_OK;
+}
+
 struct SubBatch {
     int first, count;       // blocks [first, first+count)
     int tile_off, n_tiles;  // into the tile table
     int list_off, n_list;   // into the reduce list
-    int nb;                 // kernel instantiation
+    int kernel, nb, b2, b3;
     int persistent, grid;
     int max_mn;
 };
@@ -245,6 +323,7 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_
         ga.V = h->V;
         ga.in_c64 = h->in_dtype == BBLOCK_C64;
         ga.roots = h->d_roots;
+        ga.kidx = h->d_kidx;
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
         if (h->profiling) {
@@ -252,7 +331,9 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_
             if (!ev[0] || !ev[1]) return fail(h, BBLOCK_EHIP, "profiling event creation failed");
             HIP_OR_FAIL(h, hipEventRecord(ev[0], st));
         }
-        hipError_t e = launch_gemm(h->prec, sb.nb, ga, grid, st);
+        hipError_t e = sb.kernel == K_PIPELINED
+                           ? launch_fast(h->prec, sb.nb, sb.b2, sb.b3, ga.in_c64, ga, grid, st)
+                           : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
         if (h->profiling) {
             HIP_OR_FAIL(h, hipEventRecord(ev[1], st));
@@ -283,12 +364,14 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
     if (!desc || n_desc < 1) return fail(h, BBLOCK_EINVAL, "empty batch");
+    if (n_desc > 65535) return fail(h, BBLOCK_EINVAL, "at most 65535 blocks per batch");
     if (!mom || n_mom < 1 || n_mom > MAX_MOM) return fail(h, BBLOCK_EINVAL, "n_mom must be in [1,%d]", MAX_MOM);
     for (int i = 0; i < n_desc; ++i) {
         bblock_status st = validate_desc(h, desc[i], i);
         if (st != BBLOCK_OK) return st;
     }
-    // Plans and workspace per block.
+
+    // Plans, geometry and split counts per block.
     const int s_min = min_splits(h);
     std::vector<BlockPlan> bps(n_desc);
     long total_tiles_s1 = 0;
@@ -296,9 +379,10 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         const bblock_desc &d = desc[i];
         BlockPlan &bp = bps[i];
         bp.plan = plan_for(h, d.n1, d.n2, d.n3, n_mom);
-        const KernelGeom g = kernel_geom(h->prec, bp.plan.nb, n_mom, h->L);
-        if (g.lds_bytes < 0 || g.lds_bytes > h->lds_max)
-            return fail(h, BBLOCK_EUNSUPPORTED, "no kernel for nb=%d with n_mom=%d, L=%d", bp.plan.nb, n_mom, h->L);
+        bp.g = geometry(h, bp.plan.kernel, bp.plan.nb, d.n1, d.n2, d.n3, n_mom);
+        if (bp.g.lds < 0)
+            return fail(h, BBLOCK_EUNSUPPORTED, "no kernel for plan (kernel %d, nb %d) at shape (%d,%d,%d), n_mom %d",
+                        bp.plan.kernel, bp.plan.nb, d.n1, d.n2, d.n3, n_mom);
         std::memset(&bp.d, 0, sizeof bp.d);
         bp.d.q1 = d.q1;
         bp.d.q2 = d.q2;
@@ -309,23 +393,24 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         bp.d.n3 = d.n3;
         bp.d.M = d.n1 * d.n2;
         bp.d.N = d.n3 * n_mom;
-        bp.n_mt = (bp.d.M + g.m_tile - 1) / g.m_tile;
-        bp.n_nt = (bp.d.N + bp.plan.nb * g.frag_cols - 1) / (bp.plan.nb * g.frag_cols);
-        total_tiles_s1 += (long)bp.n_mt * bp.n_nt;
+        bp.d.n_mt2 = bp.g.n_mt2;
+        bp.d.n_nt3 = bp.g.n_nt3;
+        bp.d.bp = bp.g.bp;
+        total_tiles_s1 += (long)bp.g.n_mt * bp.g.n_nt;
     }
-    // Split count: a forced/tuned plan fixes it for single blocks; in batches
-    // it follows from the device size, never below the accuracy bound.
+    // Split count: a forced plan fixes it; a single block uses its plan's
+    // count; batches fill the device; never below the accuracy bound.
     for (int i = 0; i < n_desc; ++i) {
         BlockPlan &bp = bps[i];
-        int S;
         const ShapeKey k{bp.d.n1, bp.d.n2, bp.d.n3, n_mom};
         const bool fixed = h->forced.count(k) && bp.plan.splits > 0;
+        int S;
         if (fixed)
             S = bp.plan.splits;
         else if (n_desc == 1 && bp.plan.splits > 0)
             S = std::max(bp.plan.splits, s_min);
         else
-            S = std::max<long>(s_min, (2L * h->num_cu + total_tiles_s1 - 1) / total_tiles_s1);
+            S = (int)std::max<long>(s_min, (2L * h->num_cu + total_tiles_s1 - 1) / total_tiles_s1);
         set_splits(h, bp, S);
         if (!fixed && bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
         if (bp.ws_bytes > h->ws_cap)
@@ -340,15 +425,23 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     std::vector<int> list;
     std::vector<size_t> ws_off(n_desc, 0);
     size_t ws_need = 0;
+    bool any_pipelined = false;
+    auto same_kernel = [&](const BlockPlan &x, const SubBatch &sb) {
+        return x.plan.kernel == sb.kernel && x.plan.nb == sb.nb && x.g.b2 == sb.b2 && x.g.b3 == sb.b3 &&
+               x.plan.persistent == sb.persistent;
+    };
     for (int i = 0; i < n_desc;) {
         SubBatch sb{};
         sb.first = i;
+        sb.kernel = bps[i].plan.kernel;
         sb.nb = bps[i].plan.nb;
+        sb.b2 = bps[i].g.b2;
+        sb.b3 = bps[i].g.b3;
         sb.persistent = bps[i].plan.persistent;
         sb.grid = bps[i].plan.grid > 0 ? bps[i].plan.grid : h->num_cu;
+        any_pipelined |= sb.kernel == K_PIPELINED;
         size_t used = 0;
-        while (i < n_desc && bps[i].plan.nb == sb.nb && bps[i].plan.persistent == sb.persistent &&
-               used + bps[i].ws_bytes <= h->ws_cap) {
+        while (i < n_desc && same_kernel(bps[i], sb) && used + bps[i].ws_bytes <= h->ws_cap) {
             ws_off[i] = used;
             used += align_up(bps[i].ws_bytes, 256);
             ++i;
@@ -365,16 +458,11 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         sb.list_off = (int)list.size();
         for (int b = sb.first; b < i; ++b) {
             const BlockPlan &bp = bps[b];
-            const KernelGeom g = kernel_geom(h->prec, bp.plan.nb, n_mom, h->L);
-            const int nt_w = bp.plan.nb * g.frag_cols;
             for (int s = 0; s < bp.d.S; ++s) {
                 const long sites = std::min(bp.d.sps, h->V - s * bp.d.sps);
-                for (int nt = 0; nt < bp.n_nt; ++nt)
-                    for (int mt = 0; mt < bp.n_mt; ++mt) {
-                        const long rows = std::min(g.m_tile, bp.d.M - mt * g.m_tile);
-                        const long cols = std::min(nt_w, bp.d.N - nt * nt_w);
-                        items.push_back({rows * cols * sites, make_int4(b, mt, nt, s)});
-                    }
+                const long cost = (long)bp.g.m_tile * bp.g.n_tile * sites;
+                for (int nt = 0; nt < bp.g.n_nt; ++nt)
+                    for (int mt = 0; mt < bp.g.n_mt; ++mt) items.push_back({cost, make_int4(b, mt, nt, s)});
             }
             if (bp.d.S > 1) {
                 list.push_back(b);
@@ -396,6 +484,8 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         bps[i].d.ws = bps[i].ws_bytes ? static_cast<unsigned char *>(h->d_ws) + ws_off[i] : nullptr;
 
     // Device tables: blocks | tiles | reduce list | momenta (reduced mod L).
+    std::vector<int> mom_red(3 * n_mom);
+    for (int i = 0; i < 3 * n_mom; ++i) mom_red[i] = ((mom[i] % h->L) + h->L) % h->L;
     const size_t off_blocks = 0;
     const size_t off_tiles = align_up(off_blocks + sizeof(BlockDesc) * n_desc, 256);
     const size_t off_list = align_up(off_tiles + sizeof(int4) * tiles.size(), 256);
@@ -410,10 +500,13 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     for (int i = 0; i < n_desc; ++i) std::memcpy(hs + off_blocks + sizeof(BlockDesc) * i, &bps[i].d, sizeof(BlockDesc));
     if (!tiles.empty()) std::memcpy(hs + off_tiles, tiles.data(), sizeof(int4) * tiles.size());
     if (!list.empty()) std::memcpy(hs + off_list, list.data(), sizeof(int) * list.size());
-    int *hm = reinterpret_cast<int *>(hs + off_mom);
-    for (int i = 0; i < 3 * n_mom; ++i) hm[i] = ((mom[i] % h->L) + h->L) % h->L;
+    std::memcpy(hs + off_mom, mom_red.data(), sizeof(int) * 3 * n_mom);
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_table, hs, bytes, hipMemcpyHostToDevice, h->stream));
     HIP_OR_FAIL(h, hipEventRecord(h->staging_free, h->stream));
+    if (any_pipelined) {
+        bblock_status st = ensure_kidx(h, mom_red, reinterpret_cast<const int *>(h->d_table + off_mom));
+        if (st != BBLOCK_OK) return st;
+    }
 
     if (!h->graph_enabled || h->profiling)
         return enqueue(h, subs, off_blocks, off_tiles, off_list, off_mom, n_mom, h->stream);
@@ -422,10 +515,10 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     std::vector<long long> sig;
     sig.push_back(n_mom);
     sig.push_back((long long)(uintptr_t)h->d_table);
-    for (const SubBatch &sb : subs) {
-        sig.insert(sig.end(), {sb.first, sb.count, sb.tile_off, sb.n_tiles, sb.list_off, sb.n_list, sb.nb,
-                               sb.persistent, sb.grid, sb.max_mn});
-    }
+    sig.push_back((long long)(uintptr_t)h->d_kidx);
+    for (const SubBatch &sb : subs)
+        sig.insert(sig.end(), {sb.first, sb.count, sb.tile_off, sb.n_tiles, sb.list_off, sb.n_list, sb.kernel, sb.nb,
+                               sb.b2, sb.b3, sb.persistent, sb.grid, sb.max_mn});
     sig.push_back(n_desc);
     sig.push_back((long long)tiles.size());
     auto it = h->graphs.find(sig);
@@ -466,12 +559,20 @@ __global__ void fill_uniform(F *p, size_t n, unsigned seed)
     }
 }
 
+bblock_status shape_ok(bblock_t h, int n1, int n2, int n3, int n_mom)
+{
+    if (n1 < 1 || n2 < 1 || n3 < 1 || n1 > h->max_ndil || n2 > h->max_ndil || n3 > h->max_ndil || n_mom < 1 ||
+        n_mom > MAX_MOM)
+        return fail(h, BBLOCK_EINVAL, "bad shape (%d,%d,%d) n_mom %d", n1, n2, n3, n_mom);
+    return BBLOCK_OK;
+}
+
 }  // namespace
 
 // ================================================================== ABI ===
 extern "C" {
 
-const char *bblock_version(void) { return "bblock 0.1 (gfx950)"; }
+const char *bblock_version(void) { return "bblock 0.2 (gfx950)"; }
 
 bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_dtype, int32_t max_ndil,
                             size_t workspace_cap, void *hip_stream)
@@ -501,16 +602,17 @@ bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_d
     h->ws_cap = workspace_cap ? workspace_cap : (size_t)8 << 30;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    h->lds_max = (int)prop.sharedMemPerBlock;
 
     auto bail = [&](bblock_status st, const char *what) {
-        g_create_error = what;
         bblock_destroy(h);
+        g_create_error = what;
         return st;
     };
     // Best effort: ROCm launches accept dynamic LDS up to the device limit
     // without this attribute; where the call is supported it documents intent.
-    if (prepare_kernels((int)prop.sharedMemPerBlock) != hipSuccess) (void)hipGetLastError();
-    h->lds_max = (int)prop.sharedMemPerBlock;
+    if (prepare_kernels(h->lds_max) != hipSuccess) (void)hipGetLastError();
+    if (prepare_fast_kernels(h->lds_max) != hipSuccess) (void)hipGetLastError();
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(BBLOCK_EHIP, "stream creation failed");
     if (hipEventCreateWithFlags(&h->staging_free, hipEventDisableTiming) != hipSuccess)
@@ -531,12 +633,13 @@ bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_d
     // Tuned plans persisted by earlier runs.
     if (const char *path = std::getenv("BBLOCK_TUNE_CACHE")) {
         if (FILE *f = std::fopen(path, "r")) {
-            int pr, l, n1, n2, n3, nm, nb, sp, pe, gr;
+            int pr, l, n1, n2, n3, nm, ke, nb, sp, pe, gr;
             char line[256];
             while (std::fgets(line, sizeof line, f))
-                if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &pr, &l, &n1, &n2, &n3, &nm, &nb, &sp, &pe, &gr) == 10 &&
-                    pr == prec && l == L && kernel_geom(prec, nb, nm, L).lds_bytes > 0)
-                    h->tuned[{n1, n2, n3, nm}] = Plan{nb, sp, pe, gr};
+                if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d", &pr, &l, &n1, &n2, &n3, &nm, &ke, &nb, &sp,
+                                &pe, &gr) == 11 &&
+                    pr == prec && l == L && geometry(h, ke, nb, n1, n2, n3, nm).lds > 0)
+                    h->tuned[{n1, n2, n3, nm}] = Plan{ke, nb, sp, pe, gr};
             std::fclose(f);
         }
     }
@@ -585,19 +688,24 @@ bblock_status bblock_set_graph(bblock_t h, int32_t enable)
 bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom, const bblock_plan *plan)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
-    if (n1 < 1 || n2 < 1 || n3 < 1 || n_mom < 1 || n_mom > MAX_MOM) return fail(h, BBLOCK_EINVAL, "bad shape");
+    if (bblock_status st = shape_ok(h, n1, n2, n3, n_mom)) return st;
     const ShapeKey k{n1, n2, n3, n_mom};
     if (!plan) {
         h->forced.erase(k);
         return BBLOCK_OK;
     }
-    const KernelGeom g = kernel_geom(h->prec, plan->nb, n_mom, h->L);
-    if (g.lds_bytes <= 0 || g.lds_bytes > h->lds_max)
-        return fail(h, BBLOCK_EINVAL, "nb=%d is not available for this precision/momentum count", plan->nb);
+    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED) return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
-    Plan p{plan->nb, plan->splits, plan->persistent, plan->grid};
-    if (p.splits == 0) p.splits = default_plan(h, n1, n2, n3, n_mom).splits;
+    if (geometry(h, plan->kernel, plan->nb, n1, n2, n3, n_mom).lds <= 0)
+        return fail(h, BBLOCK_EINVAL, "kernel %d with nb=%d is not available for this precision and shape", plan->kernel,
+                    plan->nb);
+    Plan p{plan->kernel, plan->nb, plan->splits, plan->persistent, plan->grid};
+    if (p.splits == 0) {
+        const Geometry g = geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom);
+        const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
+        p.splits = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
+    }
     h->forced[k] = p;
     return BBLOCK_OK;
 }
@@ -605,39 +713,39 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
 bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom, bblock_plan *plan)
 {
     if (!h || !plan) return fail(h, BBLOCK_EINVAL, "null argument");
-    if (n1 < 1 || n2 < 1 || n3 < 1 || n_mom < 1 || n_mom > MAX_MOM) return fail(h, BBLOCK_EINVAL, "bad shape");
+    if (bblock_status st = shape_ok(h, n1, n2, n3, n_mom)) return st;
     const Plan p = plan_for(h, n1, n2, n3, n_mom);
     plan->nb = p.nb;
     plan->splits = std::max(p.splits, min_splits(h));
     plan->persistent = p.persistent;
     plan->grid = p.grid;
+    plan->kernel = p.kernel;
     return BBLOCK_OK;
 }
 
 bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
-    if (n1 < 1 || n2 < 1 || n3 < 1 || n1 > h->max_ndil || n2 > h->max_ndil || n3 > h->max_ndil || n_mom < 1 ||
-        n_mom > MAX_MOM)
-        return fail(h, BBLOCK_EINVAL, "bad shape");
+    if (bblock_status st = shape_ok(h, n1, n2, n3, n_mom)) return st;
     const ShapeKey key{n1, n2, n3, n_mom};
     const size_t eb = in_bytes(h->in_dtype);
     const size_t qn[3] = {(size_t)h->V * 3 * n1, (size_t)h->V * 3 * n2, (size_t)h->V * 3 * n3};
     const size_t out_elems = (size_t)n_mom * n1 * n2 * n3;
     void *q[3] = {nullptr, nullptr, nullptr};
-    double *out = nullptr, *ref = nullptr;
+    double *out = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bblock_status st = BBLOCK_OK;
     std::vector<int32_t> mom(3 * n_mom);
-    for (int i = 0; i < n_mom; ++i) {
+    for (int i = 0; i < n_mom; ++i) {  // a spread of momenta; timing does not depend on them
         mom[3 * i] = i % 3 == 0 ? i / 3 : 0;
         mom[3 * i + 1] = i % 3 == 1 ? i / 3 : 0;
         mom[3 * i + 2] = i % 3 == 2 ? i / 3 : 0;
     }
-    const bool saved_graph = h->graph_enabled;
+    const bool saved_graph = h->graph_enabled, saved_prof = h->profiling;
     const bool had_forced = h->forced.count(key) != 0;
     const Plan saved_forced = had_forced ? h->forced[key] : Plan{};
     Plan best{};
+    bool have_best = false;
     float best_ms = 1e30f;
     std::vector<double> hout(2 * out_elems), href(2 * out_elems);
 
@@ -645,24 +753,24 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         for (void *p : q)
             if (p) (void)hipFree(p);
         if (out) (void)hipFree(out);
-        if (ref) (void)hipFree(ref);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         h->graph_enabled = saved_graph;
+        h->profiling = saved_prof;
         if (had_forced)
             h->forced[key] = saved_forced;
         else
             h->forced.erase(key);
     };
     for (int i = 0; i < 3 && st == BBLOCK_OK; ++i) {
-        if (hipMalloc(&q[i], qn[i] * eb) != hipSuccess) st = fail(h, BBLOCK_ENOMEM, "tune inputs");
+        if (hipMalloc(&q[i], qn[i] * eb) != hipSuccess)
+            st = fail(h, BBLOCK_ENOMEM, "tune inputs");
         else if (h->in_dtype == BBLOCK_C128)
             hipLaunchKernelGGL(fill_uniform<double>, dim3(512), dim3(256), 0, h->stream, (double *)q[i], qn[i] * 2, 17u * (i + 1));
         else
             hipLaunchKernelGGL(fill_uniform<float>, dim3(512), dim3(256), 0, h->stream, (float *)q[i], qn[i] * 2, 17u * (i + 1));
     }
-    if (st == BBLOCK_OK && (hipMalloc(&out, out_elems * 16) != hipSuccess || hipMalloc(&ref, out_elems * 16) != hipSuccess))
-        st = fail(h, BBLOCK_ENOMEM, "tune outputs");
+    if (st == BBLOCK_OK && hipMalloc(&out, out_elems * 16) != hipSuccess) st = fail(h, BBLOCK_ENOMEM, "tune outputs");
     if (st == BBLOCK_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         st = fail(h, BBLOCK_EHIP, "tune events");
     if (st != BBLOCK_OK) {
@@ -670,73 +778,75 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         return st;
     }
     h->graph_enabled = false;
+    h->profiling = false;
 
-    const int *opts;
-    const int n_opts = nb_options(h->prec, &opts);
-    const Plan def = default_plan(h, n1, n2, n3, n_mom);
-    const KernelGeom g0 = kernel_geom(h->prec, opts[0], n_mom, h->L);
-    const int N = n3 * n_mom;
+    // Candidates: kernel x column fragments x split count x scheduling.
+    std::vector<Plan> cands;
+    {
+        const int *opts;
+        const int n_opts = nb_options(h->prec, &opts);
+        std::vector<std::pair<int, int>> kn;
+        for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
+        for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
+        const int N = n3 * n_mom;
+        for (auto [kernel, nb] : kn) {
+            const Geometry g = geometry(h, kernel, nb, n1, n2, n3, n_mom);
+            if (g.lds <= 0) continue;
+            if ((long)g.n_nt * g.n_tile > 2L * std::max(N, 32)) continue;  // mostly padding
+            const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
+            const int s_base = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
+            for (int sf : {1, 2, 4})
+                for (int pers = 0; pers < 2; ++pers)
+                    cands.push_back(Plan{kernel, nb, std::max(s_base * sf / 2, 1), pers, pers ? h->num_cu : 0});
+        }
+    }
     const double tol = h->prec == FP64 ? 1e-11 : 1e-4;
     bool have_ref = false;
-    for (int oi = 0; oi < n_opts && st == BBLOCK_OK; ++oi) {
-        const int nb = opts[oi];
-        const KernelGeom g = kernel_geom(h->prec, nb, n_mom, h->L);
-        if (g.lds_bytes <= 0 || g.lds_bytes > h->lds_max) continue;
-        if (nb * g.frag_cols > 2 * std::max(N, g0.frag_cols) && nb != def.nb) continue;  // mostly padding
-        const int n_tiles = ((n1 * n2 + g.m_tile - 1) / g.m_tile) * ((N + nb * g.frag_cols - 1) / (nb * g.frag_cols));
-        const int s_base = std::max(1, (h->num_cu + n_tiles - 1) / n_tiles);
-        for (int sf : {1, 2, 4}) {
-            for (int pers = 0; pers < 2; ++pers) {
-                Plan cand{nb, std::max(s_base * sf / 2, 1), pers, pers ? h->num_cu : 0};
-                h->forced[key] = cand;
-                const bblock_desc d{q[0], q[1], q[2], n1, n2, n3, 0, out};
-                st = run_batch(h, &d, 1, mom.data(), n_mom);
-                if (st != BBLOCK_OK) break;
-                if (hipStreamSynchronize(h->stream) != hipSuccess) {
-                    st = fail(h, BBLOCK_EHIP, "tune candidate failed");
-                    break;
-                }
-                // Consistency against the first candidate's result.
-                if (!have_ref) {
-                    (void)hipMemcpy(ref, out, out_elems * 16, hipMemcpyDeviceToDevice);
-                    (void)hipMemcpy(href.data(), ref, out_elems * 16, hipMemcpyDeviceToHost);
-                    have_ref = true;
-                } else {
-                    (void)hipMemcpy(hout.data(), out, out_elems * 16, hipMemcpyDeviceToHost);
-                    double dmax = 0, rmax = 0;
-                    for (size_t i = 0; i < hout.size(); ++i) {
-                        dmax = std::max(dmax, std::fabs(hout[i] - href[i]));
-                        rmax = std::max(rmax, std::fabs(href[i]));
-                    }
-                    if (!(dmax <= tol * std::max(rmax, 1e-300))) continue;  // rejected candidate
-                }
-                float best_of = 1e30f;
-                for (int rep = 0; rep < 3; ++rep) {
-                    (void)hipEventRecord(e0, h->stream);
-                    st = run_batch(h, &d, 1, mom.data(), n_mom);
-                    (void)hipEventRecord(e1, h->stream);
-                    if (st != BBLOCK_OK || hipEventSynchronize(e1) != hipSuccess) break;
-                    float ms = 0;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    best_of = std::min(best_of, ms);
-                }
-                if (st != BBLOCK_OK) break;
-                if (best_of < best_ms) {
-                    best_ms = best_of;
-                    best = cand;
-                }
+    for (const Plan &cand : cands) {
+        h->forced[key] = cand;
+        const bblock_desc d{q[0], q[1], q[2], n1, n2, n3, 0, out};
+        st = run_batch(h, &d, 1, mom.data(), n_mom);
+        if (st != BBLOCK_OK) break;
+        if (hipStreamSynchronize(h->stream) != hipSuccess) {
+            st = fail(h, BBLOCK_EHIP, "tune candidate failed");
+            break;
+        }
+        // Consistency against the first candidate's result.
+        (void)hipMemcpy(have_ref ? hout.data() : href.data(), out, out_elems * 16, hipMemcpyDeviceToHost);
+        if (have_ref) {
+            double dmax = 0, rmax = 0;
+            for (size_t i = 0; i < hout.size(); ++i) {
+                dmax = std::max(dmax, std::fabs(hout[i] - href[i]));
+                rmax = std::max(rmax, std::fabs(href[i]));
             }
-            if (st != BBLOCK_OK) break;
+            if (!(dmax <= tol * std::max(rmax, 1e-300))) continue;  // rejected candidate
+        }
+        have_ref = true;
+        float best_of = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, h->stream);
+            st = run_batch(h, &d, 1, mom.data(), n_mom);
+            (void)hipEventRecord(e1, h->stream);
+            if (st != BBLOCK_OK || hipEventSynchronize(e1) != hipSuccess) break;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best_of = std::min(best_of, ms);
+        }
+        if (st != BBLOCK_OK) break;
+        if (best_of < best_ms) {
+            best_ms = best_of;
+            best = cand;
+            have_best = true;
         }
     }
     cleanup();
     if (st != BBLOCK_OK) return st;
-    if (best.nb == 0) return fail(h, BBLOCK_EHIP, "no tuning candidate passed");
+    if (!have_best) return fail(h, BBLOCK_EHIP, "no tuning candidate passed");
     h->tuned[key] = best;
     if (const char *path = std::getenv("BBLOCK_TUNE_CACHE")) {
         if (FILE *f = std::fopen(path, "a")) {
-            std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d\n", h->prec, h->L, n1, n2, n3, n_mom, best.nb, best.splits,
-                         best.persistent, best.grid);
+            std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", h->prec, h->L, n1, n2, n3, n_mom, best.kernel, best.nb,
+                         best.splits, best.persistent, best.grid);
             std::fclose(f);
         }
     }
@@ -786,10 +896,11 @@ bblock_status bblock_sync(bblock_t h)
 bblock_status bblock_destroy(bblock_t h)
 {
     if (!h) return BBLOCK_OK;
-    if (h->stream || h->d_table) (void)hipStreamSynchronize(h->stream);
+    if (h->d_table || h->d_roots) (void)hipStreamSynchronize(h->stream);
     clear_graphs(h);
     if (h->d_ws) (void)hipFree(h->d_ws);
     if (h->d_table) (void)hipFree(h->d_table);
+    if (h->d_kidx) (void)hipFree(h->d_kidx);
     if (h->h_staging) (void)hipHostFree(h->h_staging);
     if (h->d_roots) (void)hipFree(h->d_roots);
     if (h->d_counter) (void)hipFree(h->d_counter);

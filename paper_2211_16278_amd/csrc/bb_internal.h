@@ -27,6 +27,11 @@ struct BlockDesc {
     int M, N;                  // M = n1*n2 rows (d1,d2); N = n3*n_mom columns (p,d3)
     int S;                     // number of site splits
     int sps;                   // sites per split (multiple of CHUNK_SITES)
+    // Rectangular tiles of the pipelined kernel: m-tile = (d1 block) x (d2
+    // block), n-tile = (momentum block of bp momenta) x (d3 block).
+    int n_mt2;                 // d2 blocks
+    int n_nt3;                 // d3 blocks
+    int bp;                    // momenta per n-tile
     int pad;
 };
 
@@ -41,6 +46,7 @@ struct GemmArgs {
     int L, V;
     int in_c64;
     const double *roots; // [L] complex128 exp(-2 pi i k / L)
+    const unsigned char *kidx;  // [n_mom][V] phase index (n_p . x) mod L (pipelined kernel)
 };
 
 struct ReduceArgs {
@@ -61,6 +67,14 @@ int nb_options(int prec, const int **list);
 KernelGeom kernel_geom(int prec, int nb, int n_mom, int L);
 
 hipError_t launch_gemm(int prec, int nb, const GemmArgs &a, int grid, hipStream_t st);
+
+// Pipelined kernel (FP32 and BF16X3; d2 and d3 blocks of 16 or 32).
+// Returns the dynamic LDS bytes, or -1 when no instantiation exists.
+int fast_lds_bytes(int prec, int nb, int b2, int b3, int L);
+hipError_t launch_fast(int prec, int nb, int b2, int b3, int in_c64, const GemmArgs &a, int grid, hipStream_t st);
+hipError_t prepare_fast_kernels(int lds_bytes);
+// kidx[p][x] = (n_p . x) mod L for all sites of one timeslice (momenta already in [0, L)).
+hipError_t launch_phase_index(const int *mom, int n_mom, int L, unsigned char *kidx, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
 hipError_t prepare_kernels(int lds_bytes);  // dynamic-LDS limit of every contraction kernel
 

@@ -117,21 +117,32 @@ def test_identical_fields_antisymmetric_fp64(torch_dev):
 
 
 # --------------------------------------------------------- plan variants
+def _plans(prec):
+    """Every (kernel, nb, splits, persistent) the planner or autotuner may pick."""
+    out = []
+    kernels = [(0, nb) for nb in ((1, 2, 4, 7, 14) if prec == "fp64" else (1, 2, 4, 7))]
+    if prec != "fp64":
+        kernels += [(1, 4), (1, 7)]
+    for kernel, nb in kernels:
+        for splits in (1, 3, 16):
+            for persistent in (0, 1):
+                out.append(dict(kernel=kernel, nb=nb, splits=splits, persistent=persistent,
+                                grid=7 if persistent else 0))
+    return out
+
+
 @pytest.mark.parametrize("prec", PRECS)
-def test_every_plan_candidate_passes(torch_dev, prec):
-    """Each tile shape / split / persistence the autotuner may pick is correct."""
-    L, ns = 5, (19, 21, 23)
+@pytest.mark.parametrize("L,ns", [(5, (19, 21, 23)), (4, (40, 33, 35))])
+def test_every_plan_candidate_passes(torch_dev, prec, L, ns):
+    """Each kernel / tile shape / split / persistence the autotuner may pick is
+    correct, on shapes with ragged edges for both tile families."""
     qs = fields(L, ns, workload=104)
     mom = synth.momenta("axis")
     ref = oracle.bblock(L, *qs, mom)
-    opts = (1, 2, 4, 7, 14) if prec == "fp64" else (1, 2, 4, 7)
-    for nb in opts:
-        for splits in (1, 3, 16):
-            for persistent in (0, 1):
-                plan = dict(nb=nb, splits=splits, persistent=persistent, grid=7 if persistent else 0)
-                say("case plan", prec, plan)
-                e = err_max(gpu_block(torch_dev, prec, L, qs, mom, plan=plan), ref)
-                assert e < TOL[prec], (plan, e)
+    for plan in _plans(prec):
+        say("case plan", prec, L, ns, plan)
+        e = err_max(gpu_block(torch_dev, prec, L, qs, mom, plan=plan), ref)
+        assert e < TOL[prec], (plan, e)
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -144,8 +155,10 @@ def test_determinism_graph_persistent(torch_dev, prec):
     say("case determinism", prec)
     a = gpu_block(torch_dev, prec, L, qs, mom, graph=False)
     b = gpu_block(torch_dev, prec, L, qs, mom, graph=True)
-    c = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(nb=7 if prec != "fp64" else 14, splits=0, persistent=1))
-    d = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(nb=7 if prec != "fp64" else 14, splits=0, persistent=0))
+    kernel = 0 if prec == "fp64" else 1
+    nb = 14 if prec == "fp64" else 7
+    c = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(kernel=kernel, nb=nb, splits=0, persistent=1))
+    d = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(kernel=kernel, nb=nb, splits=0, persistent=0))
     assert np.array_equal(a, b)
     assert np.array_equal(c, d)
     assert err_max(a, oracle.bblock(L, *qs, mom)) < TOL[prec]
@@ -226,7 +239,7 @@ def test_tune_then_compute(torch_dev):
     with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
         bb.tune(*ns, len(mom))
         plan = bb.get_plan(*ns, len(mom))
-        assert plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
+        assert plan["kernel"] in (0, 1) and plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
         out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
         bb.sync()
     assert err_max(out[0].cpu().numpy(), oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
