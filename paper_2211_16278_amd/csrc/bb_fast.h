@@ -20,6 +20,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "bb_internal.h"
 
@@ -216,15 +217,74 @@ __device__ __forceinline__ void multiply(const uint32_t *buf, int c, f16_t (&acc
     }
 }
 
+// Global-memory (address space 1) pointers: loads through them are
+// global_load, which count only on vmcnt, so LDS waits never wait on HBM.
+template <class T>
+using gptr = const T __attribute__((address_space(1))) *;
+
+// Compile-time loop: f(integral_constant<int, I>) for I in [B, E).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Slot K of SLOTS runs the sub-steps [ceil(K*NSUB/SLOTS), ceil((K+1)*NSUB/SLOTS))
+// of a piece of work split into NSUB sub-steps.
+template <int K, int SLOTS, int NSUB, class F>
+__device__ __forceinline__ void slot_steps(F &&f)
+{
+    static_for<(K * NSUB + SLOTS - 1) / SLOTS, ((K + 1) * NSUB + SLOTS - 1) / SLOTS>(f);
+}
+
+__device__ __forceinline__ bf8_t embed(uint4 v, uint32_t sel, uint32_t flip)
+{
+    return __builtin_bit_cast(bf8_t, make_uint4(__builtin_amdgcn_perm(v.x, v.x, sel) ^ flip,
+                                                __builtin_amdgcn_perm(v.y, v.y, sel) ^ flip,
+                                                __builtin_amdgcn_perm(v.z, v.z, sel) ^ flip,
+                                                __builtin_amdgcn_perm(v.w, v.w, sel) ^ flip));
+}
+
+// Scheduling pattern of one section: each MFMA followed by NV VALU and ND LDS
+// instructions, so the VALU work of the generation issues while the matrix
+// core is busy (one wave per SIMD: overlap has to come from within the wave).
+template <int NM, int NV, int ND>
+__device__ __forceinline__ void interleave()
+{
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        if constexpr (NV > 0) __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // VALU
+        if constexpr (ND > 0) __builtin_amdgcn_sched_group_barrier(0x080, ND, 0);  // LDS
+    }
+}
+
+// Instruction estimates per section and wave, for the interleave patterns.
+template <int P, int NB, int B2, int B3>
+struct Sched {
+    using Lt = Layout<NB, B2, B3>;
+    static constexpr int SPLIT = P == BF16X3 ? 7 : 0;  // VALU per complex hi/lo split
+    static constexpr int XFORM = P == BF16X3 ? 32 : 16; // row-embedding VALU per colour
+    static constexpr int MF = P == BF16X3 ? 6 * NB : 16 * NB;  // MFMAs per colour
+    static constexpr int V_D = 12 * (10 + SPLIT) + XFORM;
+    static constexpr int V_W = Lt::JW * 12 * (4 + SPLIT) + XFORM;
+    static constexpr int V_S = 4 * Lt::JL + 12 + XFORM;
+    static constexpr int cd(int a, int b) { return (a + b - 1) / b; }
+    static constexpr int NV_D = cd(V_D, MF), NV_W = cd(V_W, MF), NV_S = cd(V_S, MF);
+};
+
+// Complex input element as a native vector (loads through address-space-1
+// pointers need a trivially copyable type).
 template <bool C64>
-struct InT;
-template <>
-struct InT<false> {
-    using T = double2;
+struct InT {
+    using T = double __attribute__((ext_vector_type(2)));
 };
 template <>
 struct InT<true> {
-    using T = float2;
+    using T = float __attribute__((ext_vector_type(2)));
 };
 
 template <int P, int NB, int B2, int B3, bool C64>
@@ -286,20 +346,23 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
         const bool ph_live = tid < Lt::EPH;
         const bool ph_ok = ph_live && ph_ip < bd.bp && (p0 + ph_ip) < a.n_mom;
         const int ph_dst = ph_live ? Lt::E1 + Lt::E2 + Lt::E3 + tid : Lt::SG + lane;
-        const unsigned char *kp = a.kidx + (size_t)(ph_ok ? p0 + ph_ip : 0) * V;
-        const IT *q1p = reinterpret_cast<const IT *>(bd.q1);
-        const IT *q2p = reinterpret_cast<const IT *>(bd.q2);
-        const IT *q3p = reinterpret_cast<const IT *>(bd.q3);
+        const gptr<unsigned char> kp = (gptr<unsigned char>)(a.kidx + (size_t)(ph_ok ? p0 + ph_ip : 0) * V);
+        const gptr<IT> q1p = (gptr<IT>)bd.q1;
+        const gptr<IT> q2p = (gptr<IT>)bd.q2;
+        const gptr<IT> q3p = (gptr<IT>)bd.q3;
 
         IT rv[Lt::JL];
         unsigned okbits = 0;
         int kval = 0;
-        auto load_slot = [&](int q, const IT *basep, int n_k, int x0) {
+        // Out-of-range elements load element 0 (always valid) and are
+        // zeroed at the staging store; masks instead of branches keep the
+        // whole loop body one scheduling region.
+        auto load_slot = [&](int q, gptr<IT> basep, int n_k, int x0) {
             const int xa = x0 + (int)((plan[q] >> 26) & 7u);
-            const bool ok = ((plan[q] >> 29) & 1u) && xa < xe;
-            const int idx = ok ? xa * 3 * n_k + (int)(plan[q] & 0x3fffu) : 0;
+            const unsigned ok = ((plan[q] >> 29) & 1u) & (unsigned)(xa < xe);
+            const int idx = (xa * 3 * n_k + (int)(plan[q] & 0x3fffu)) & -(int)ok;
             rv[q] = basep[idx];
-            okbits |= ok ? (1u << q) : 0u;
+            okbits |= ok << q;
         };
         auto issue_loads = [&](int ci) {
             const int x0 = xs + ci * CHUNK_SITES;
@@ -311,17 +374,19 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
 #pragma unroll
             for (int j = 0; j < Lt::J3; ++j) load_slot(Lt::J1 + Lt::J2 + j, q3p, bd.n3, x0);
             const int xa = x0 + ph_x;
-            const bool ok = ph_ok && xa < V;
-            kval = kp[ok ? xa : 0];
-            okbits |= ok ? (1u << 31) : 0u;
+            const unsigned ok = (unsigned)ph_ok & (unsigned)(xa < V);
+            kval = kp[xa & -(int)ok];
+            okbits |= ok << 31;
         };
         auto store_staging = [&]() {
 #pragma unroll
             for (int q = 0; q < Lt::JL; ++q) {
-                const bool ok = (okbits >> q) & 1u;
-                stg[(plan[q] >> 14) & 0xfffu] = ok ? make_float2((float)rv[q].x, (float)rv[q].y) : make_float2(0.f, 0.f);
+                const float m = (float)((okbits >> q) & 1u);
+                stg[(plan[q] >> 14) & 0xfffu] = make_float2(m * (float)rv[q].x, m * (float)rv[q].y);
             }
-            stg[ph_dst] = (okbits >> 31) ? roots[kval] : make_float2(0.f, 0.f);
+            const float m = (float)(okbits >> 31);
+            const float2 r = roots[kval];
+            stg[ph_dst] = make_float2(m * r.x, m * r.y);
         };
 
         f16_t acc[2][NB];
@@ -346,25 +411,228 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
         issue_loads(2);
         __syncthreads();
 
-        // Steady state: each colour's MFMAs of chunk i are paired with one
+        if constexpr (P == BF16X3) {
+            // Steady state, one wave per SIMD: each of the 126 MFMAs of a chunk
+            // is followed (in program order, fenced by scheduling barriers) by
+            // a slice of VALU/LDS work, so the matrix core and the VALU run
+            // concurrently.  Section c multiplies colour c of chunk i; its
+            // slices build the diquark tile (c = 0) and the W tile (c = 1) of
+            // chunk i+1, or stage chunk i+2 and load chunk i+3 (c = 2), and
+            // prefetch the A fragments of the next section.
+            constexpr int SLOTS = 6 * NB;
+            const int g = lane >> 5, r = lane & 31;
+            const uint32_t sel = r >= 16 ? 0x01000302u : 0x03020100u;
+            const uint32_t flip = r >= 16 ? 0u : 0x80000000u;
+            const int aoff = rowaddr(wave * 32 + (r & 15)) + 4 * g;
+            const int boff = rowaddr(r) + 4 * g;
+            const int i2 = lane % B2, xgd = (lane / B2) & 1, i1 = wave * (Lt::B1 / 4) + lane / (2 * B2);
+            const int doff = rowaddr(i1 * B2 + i2) + 4 * xgd;
+            const int i3 = lane % B3, xgw = (lane / B3) & 1, ipl = lane / (2 * B3);
+            const float2 *S1 = stg, *S2 = stg + Lt::E1, *S3 = S2 + Lt::E2, *PH = S3 + Lt::E3;
+
+            bf8_t ah[2], al[2], ahn[2], aln[2];
+            uint4 rah[2], ral[2];
+            auto load_a = [&](const uint32_t *buf, int c) {
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    rah[f] = *reinterpret_cast<const uint4 *>(buf + aoff + 8 * c + f * rowaddr(16));
+                    ral[f] = *reinterpret_cast<const uint4 *>(buf + Lt::DPL + aoff + 8 * c + f * rowaddr(16));
+                }
+            };
+            // A prefetch for the next section: raw loads at mid-section, the
+            // row embedding in the last four slots.
+            auto a_prefetch = [&](auto kk, const uint32_t *buf, int c) {
+                constexpr int k = kk;
+                if constexpr (k == SLOTS / 2) load_a(buf, c);
+                if constexpr (k == SLOTS - 4) ahn[0] = embed(rah[0], sel, flip);
+                if constexpr (k == SLOTS - 3) aln[0] = embed(ral[0], sel, flip);
+                if constexpr (k == SLOTS - 2) ahn[1] = embed(rah[1], sel, flip);
+                if constexpr (k == SLOTS - 1) aln[1] = embed(ral[1], sel, flip);
+            };
+            // One colour of MFMAs: 6 per column fragment (lo*hi, hi*lo, hi*hi
+            // for both row fragments); B fragments prefetched one ahead.
+            auto run_section = [&](const uint32_t *buf, auto cc, auto &&pre, auto &&work) {
+                constexpr int c = cc;
+                const uint32_t *W0 = buf + 2 * Lt::DPL, *W1 = W0 + Lt::WPL;
+                uint4 bh[2], bl[2];
+                bh[0] = *reinterpret_cast<const uint4 *>(W0 + boff + 8 * c);
+                bl[0] = *reinterpret_cast<const uint4 *>(W1 + boff + 8 * c);
+                pre();
+                static_for<0, NB>([&](auto nn) {
+                    constexpr int n = nn;
+                    if constexpr (n + 1 < NB) {
+                        bh[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W0 + boff + 8 * c + (n + 1) * rowaddr(32));
+                        bl[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W1 + boff + 8 * c + (n + 1) * rowaddr(32));
+                    }
+                    static_for<0, 6>([&](auto kk) {
+                        constexpr int k = kk, f = k & 1, prod = k >> 1;
+                        const bf8_t A = prod == 0 ? al[f] : ah[f];
+                        const bf8_t Bv = __builtin_bit_cast(bf8_t, prod == 1 ? bl[n & 1] : bh[n & 1]);
+                        acc[f][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bv, acc[f][n], 0, 0, 0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        work(std::integral_constant<int, n * 6 + k>{});
+                        __builtin_amdgcn_sched_barrier(0);
+                    });
+                });
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    ah[f] = ahn[f];
+                    al[f] = aln[f];
+                }
+            };
+
+            load_a(dwbuf, 0);
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                ah[f] = embed(rah[f], sel, flip);
+                al[f] = embed(ral[f], sel, flip);
+            }
+            for (int i = 0; i < n_chunks; ++i) {
+                const uint32_t *cur = dwbuf + (i & 1) * Lt::DW;
+                uint32_t *nxt = dwbuf + ((i + 1) & 1) * Lt::DW;
+
+                // Colour 0 + diquark tile of chunk i+1: 12 values (3 colours
+                // x 4 sites), 4 sub-steps each.
+                {
+                    float2 u[3][4], v[3][4], t1[12], t2[12];
+                    uint32_t dh[3][4], dl[3][4];
+                    auto pre = [&]() {
+#pragma unroll
+                        for (int x = 0; x < 4; ++x)
+#pragma unroll
+                            for (int q = 0; q < 3; ++q) {
+                                u[q][x] = S1[(q * 8 + 4 * xgd + x) * Lt::B1 + i1];
+                                v[q][x] = S2[(q * 8 + 4 * xgd + x) * B2 + i2];
+                            }
+                    };
+                    auto step = [&](auto ss) {
+                        constexpr int st = ss, t = st / 4, part = st % 4, x = t / 3, c = t % 3;
+                        constexpr int a_ = (c + 1) % 3, b_ = (c + 2) % 3;  // eps_{a b c} = +1
+                        if constexpr (part == 0) {
+                            t1[t] = cmulf(u[a_][x], v[b_][x]);
+                        } else if constexpr (part == 1) {
+                            t2[t] = cmulf(u[b_][x], v[a_][x]);
+                        } else if constexpr (part == 2) {
+                            const float2 d = make_float2(t1[t].x - t2[t].x, t1[t].y - t2[t].y);
+                            const uint32_t hi = pack_bf16(d.x, d.y);
+                            dh[c][x] = hi;
+                            t1[t] = make_float2(d.x - __uint_as_float(hi << 16), d.y - __uint_as_float(hi & 0xffff0000u));
+                        } else {
+                            dl[c][x] = pack_bf16(t1[t].x, t1[t].y);
+                            if constexpr (x == 3) {
+                                *reinterpret_cast<uint4 *>(nxt + doff + 8 * c) = make_uint4(dh[c][0], dh[c][1], dh[c][2], dh[c][3]);
+                                *reinterpret_cast<uint4 *>(nxt + Lt::DPL + doff + 8 * c) =
+                                    make_uint4(dl[c][0], dl[c][1], dl[c][2], dl[c][3]);
+                            }
+                        }
+                    };
+                    run_section(cur, std::integral_constant<int, 0>{}, pre, [&](auto kk) {
+                        slot_steps<decltype(kk)::value, SLOTS, 48>(step);
+                        a_prefetch(kk, cur, 1);
+                    });
+                }
+                // Colour 1 + W tile of chunk i+1: JW rounds x 3 colours x 4
+                // sites, 2 sub-steps each.
+                {
+                    float2 s3[3][4], ph[Lt::JW][4], wt[12 * Lt::JW];
+                    uint32_t wh[Lt::JW][3][4], wl[Lt::JW][3][4];
+                    int ip[Lt::JW];
+#pragma unroll
+                    for (int j = 0; j < Lt::JW; ++j) {
+                        const bool live = (wave + 4 * j) < NB;
+                        ip[j] = wave * Lt::IPW + ipl + (live ? 4 * Lt::IPW * j : 0);
+                    }
+                    auto pre = [&]() {
+#pragma unroll
+                        for (int x = 0; x < 4; ++x) {
+#pragma unroll
+                            for (int q = 0; q < 3; ++q) s3[q][x] = S3[(q * 8 + 4 * xgw + x) * B3 + i3];
+#pragma unroll
+                            for (int j = 0; j < Lt::JW; ++j) ph[j][x] = PH[ip[j] * 8 + 4 * xgw + x];
+                        }
+                    };
+                    auto step = [&](auto ss) {
+                        constexpr int st = ss, t = st / 2, part = st % 2, x = t % 4, c = (t / 4) % 3, j = t / 12;
+                        if constexpr (part == 0) {
+                            wt[t] = cmulf(s3[c][x], ph[j][x]);
+                        } else {
+                            const uint32_t hi = pack_bf16(wt[t].x, wt[t].y);
+                            wh[j][c][x] = hi;
+                            wl[j][c][x] = pack_bf16(wt[t].x - __uint_as_float(hi << 16), wt[t].y - __uint_as_float(hi & 0xffff0000u));
+                            if constexpr (x == 3) {
+                                const int off = rowaddr(ip[j] * B3 + i3) + 4 * xgw + 8 * c;
+                                *reinterpret_cast<uint4 *>(nxt + 2 * Lt::DPL + off) =
+                                    make_uint4(wh[j][c][0], wh[j][c][1], wh[j][c][2], wh[j][c][3]);
+                                *reinterpret_cast<uint4 *>(nxt + 2 * Lt::DPL + Lt::WPL + off) =
+                                    make_uint4(wl[j][c][0], wl[j][c][1], wl[j][c][2], wl[j][c][3]);
+                            }
+                        }
+                    };
+                    run_section(cur, std::integral_constant<int, 1>{}, pre, [&](auto kk) {
+                        slot_steps<decltype(kk)::value, SLOTS, 24 * Lt::JW>(step);
+                        a_prefetch(kk, cur, 2);
+                    });
+                }
+                __syncthreads();
+                // Colour 2 + staging of chunk i+2 and loads of chunk i+3.
+                {
+                    const int x0 = xs + (i + 3) * CHUNK_SITES;
+                    auto step = [&](auto ss) {
+                        constexpr int st = ss;
+                        if constexpr (st < Lt::JL) {
+                            const float m = (float)((okbits >> st) & 1u);
+                            stg[(plan[st] >> 14) & 0xfffu] = make_float2(m * (float)rv[st].x, m * (float)rv[st].y);
+                        } else if constexpr (st == Lt::JL) {
+                            const float m = (float)(okbits >> 31);
+                            const float2 rr = roots[kval];
+                            stg[ph_dst] = make_float2(m * rr.x, m * rr.y);
+                            okbits = 0;
+                        } else if constexpr (st < 2 * Lt::JL + 1) {
+                            constexpr int q = st - Lt::JL - 1;
+                            if constexpr (q < Lt::J1)
+                                load_slot(q, q1p, bd.n1, x0);
+                            else if constexpr (q < Lt::J1 + Lt::J2)
+                                load_slot(q, q2p, bd.n2, x0);
+                            else
+                                load_slot(q, q3p, bd.n3, x0);
+                        } else {
+                            const int xa = x0 + ph_x;
+                            const unsigned ok = (unsigned)ph_ok & (unsigned)(xa < V);
+                            kval = kp[xa & -(int)ok];
+                            okbits |= ok << 31;
+                        }
+                    };
+                    run_section(cur, std::integral_constant<int, 2>{}, [] {}, [&](auto kk) {
+                        slot_steps<decltype(kk)::value, SLOTS, 2 * Lt::JL + 2>(step);
+                        a_prefetch(kk, nxt, 0);
+                    });
+                }
+                __syncthreads();
+            }
+        } else {
+        // Steady state: each colour's MFMAs of chunk i are interleaved with one
         // piece of the generation of chunk i+1 (or the staging of chunk i+2);
-        // the scheduling barriers bound the live registers of each pair.
+        // the scheduling barriers bound the live registers of each piece.
+        using Sc = Sched<P, NB, B2, B3>;
         for (int i = 0; i < n_chunks; ++i) {
             const uint32_t *cur = dwbuf + (i & 1) * Lt::DW;
             uint32_t *nxt = dwbuf + ((i + 1) & 1) * Lt::DW;
             gen_d<P, NB, B2, B3>(nxt, stg, lane, wave);
             multiply<P, NB, B2, B3>(cur, 0, acc, lane, wave);
-            __builtin_amdgcn_sched_barrier(0);
-            gen_w<P, NB, B2, B3>(nxt, stg, 0, lane, wave);
-            multiply<P, NB, B2, B3>(cur, 1, acc, lane, wave);
+            interleave<Sc::MF, Sc::NV_D, 1>();
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int j = 1; j < Lt::JW; ++j) gen_w<P, NB, B2, B3>(nxt, stg, j, lane, wave);
+            for (int j = 0; j < Lt::JW; ++j) gen_w<P, NB, B2, B3>(nxt, stg, j, lane, wave);
+            multiply<P, NB, B2, B3>(cur, 1, acc, lane, wave);
+            interleave<Sc::MF, Sc::NV_W, 1>();
+            __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
             store_staging();
             issue_loads(i + 3);
             multiply<P, NB, B2, B3>(cur, 2, acc, lane, wave);
+            interleave<Sc::MF, Sc::NV_S, 1>();
             __syncthreads();
+        }
         }
 
         // Epilogue: real row -> (complex row, Re/Im), column -> (p, d3).
