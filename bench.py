@@ -69,6 +69,119 @@ def read_traffic(path_name: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def device_fields(torch, dev, shape_list, dtype, seed):
+    """Seeded iid complex-normal fields generated on the device (the batched
+    workloads hold tens of GB of inputs; content does not affect timing)."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(16278 * 1000 + seed)
+    real = torch.float32 if dtype == "c64" else torch.float64
+    out = []
+    for shp in shape_list:
+        t = torch.empty((*shp, 2), dtype=real, device=dev)
+        t.normal_(0.0, 0.5 ** 0.5, generator=g)
+        out.append(torch.view_as_complex(t))
+    return out
+
+
+def batch_workload(torch, dev, name):
+    """Descriptors (q1, q2, q3, out) of a grouped workload, all resident on the device."""
+    from paper_2211_16278_amd import synth
+    wl = synth.WORKLOADS[name]
+    L, T = wl["L"], wl["T"]
+    V = L ** 3
+    mom = synth.momenta(wl["momenta"])
+    descs, fields, f_gemm, f_alg = [], [], 0.0, 0.0
+    if name == "batched-48":
+        # 3 quark lines x 4 spin components per timeslice; spin triples (s, s, s).
+        n = wl["ndil"]
+        for t in range(T):
+            lines = [device_fields(torch, dev, [(V, 3, n)] * 4, wl["dtype"], 100 * t + ln) for ln in range(3)]
+            fields.append(lines)
+            for s_ in range(4):
+                out = torch.empty((len(mom), n, n, n), dtype=torch.complex128, device=dev)
+                descs.append((lines[0][s_], lines[1][s_], lines[2][s_], out))
+    elif name == "uneven-32":
+        # 8 noise triples per timeslice with N_dil (16, 32, 64)[k mod 3], 3 lines x 4
+        # spins each; the first 20 spin triples of {0..3}^3 per noise triple.
+        import itertools
+        triples = list(itertools.product(range(4), repeat=3))[:20]
+        for t in range(T):
+            for k in range(8):
+                n = (16, 32, 64)[k % 3]
+                lines = [device_fields(torch, dev, [(V, 3, n)] * 4, wl["dtype"], 10000 * t + 100 * k + ln)
+                         for ln in range(3)]
+                fields.append(lines)
+                for (a, b, c) in triples:
+                    out = torch.empty((len(mom), n, n, n), dtype=torch.complex128, device=dev)
+                    descs.append((lines[0][a], lines[1][b], lines[2][c], out))
+    elif name in ("large-64", "tiny-12", "headline-32"):
+        n = wl["ndil"]
+        for t in range(T):
+            q = device_fields(torch, dev, [(V, 3, n)] * 3, wl["dtype"], t)
+            fields.append(q)
+            out = torch.empty((len(mom), n, n, n), dtype=torch.complex128, device=dev)
+            descs.append((q[0], q[1], q[2], out))
+    else:
+        raise SystemExit("unknown workload %s" % name)
+    for q1, q2, q3, _ in descs:
+        fg, fa = flops(V, q1.shape[-1], q2.shape[-1], q3.shape[-1], len(mom))
+        f_gemm += fg
+        f_alg += fa
+    return L, mom, descs, fields, f_gemm, f_alg, wl
+
+
+def run_batch_workload(args, name):
+    """Time a grouped workload: a step is one grouped launch over all its blocks."""
+    import torch
+    from paper_2211_16278_amd import binding
+    dev = torch.device("cuda:0")
+    L, mom, descs, fields, f_gemm, f_alg, wl = batch_workload(torch, dev, name)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    max_n = max(max(d[0].shape[-1], d[1].shape[-1], d[2].shape[-1]) for d in descs)
+    res = {}
+    for pname in [p for p in args.paths.split(",") if p]:
+        bb = binding.BaryonBlocks(L, prec=pname, in_dtype=wl["dtype"], max_ndil=max_n, stream=stream,
+                                  workspace_cap=args.workspace_gib << 30)
+        for _ in range(args.warmup):
+            bb.compute_batch(descs, mom)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            bb.compute_batch(descs, mom)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        step_ms = max(e0.elapsed_time(e1), wall * 1e3) / args.steps
+        bb.profile(True)
+        bb.profile_read()
+        bb.compute_batch(descs, mom)
+        gemm_ms, red_ms, launches = bb.profile_read()
+        bb.profile(False)
+        bb.close()
+        res[pname] = {"blocks_per_s": len(descs) * 1e3 / step_ms, "ms_per_step": step_ms,
+                      "tflops_gemm_count": f_gemm / (step_ms * 1e-3) / 1e12,
+                      "tflops_paper_count": f_alg / (step_ms * 1e-3) / 1e12,
+                      "contraction_kernel_ms_per_step": gemm_ms, "reduce_kernel_ms_per_step": red_ms,
+                      "contraction_launches_per_step": launches,
+                      "mfma_frac": MFMA_PASSES[pname] * f_gemm / (gemm_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname]}
+        print("# %s %-6s %d blocks  %.2f ms/step  %.1f blocks/s  MFMA %.1f%%" % (
+            name, pname, len(descs), step_ms, len(descs) * 1e3 / step_ms, 100 * res[pname]["mfma_frac"]),
+            file=sys.stderr, flush=True)
+    head = "bf16x3" if "bf16x3" in res else next(iter(res))
+    rec = {"metric": METRIC, "value": res[head]["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[head]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
+           "data": "synthetic (seeded iid complex normal quark fields, generated on the device)",
+           "config": {"workload": name, "L": L, "T": wl["T"], "n_dil": wl["ndil"], "n_mom": len(mom),
+                      "blocks_per_step": len(descs), "in_dtype": wl["dtype"]},
+           "paths": res}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def cpu_baseline(L, qs, mom, M, target_s=15.0):
     """The oracle, untuned, on a bounded sample of (d1, d2) rows of one block."""
     import numpy as np
@@ -99,6 +212,10 @@ def main() -> int:
     ap.add_argument("--paths", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--workload", default="headline-32",
+                    help="headline-32 (the benchmark line), or a grouped workload: batched-48, uneven-32, "
+                         "large-64, tiny-12")
+    ap.add_argument("--workspace-gib", type=int, default=16)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -106,6 +223,9 @@ def main() -> int:
         print("bench.py measures one GPU: this build has no multi-GPU path (blocks shard across GPUs with no "
               "communication; see the design notes). Run with --gpus 1.", file=sys.stderr)
         return 2
+
+    if args.workload != "headline-32":
+        return run_batch_workload(args, args.workload)
 
     import numpy as np
     import torch

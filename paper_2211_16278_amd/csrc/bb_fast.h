@@ -450,19 +450,28 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                 if constexpr (k == SLOTS - 1) aln[1] = embed(ral[1], sel, flip);
             };
             // One colour of MFMAs: 6 per column fragment (lo*hi, hi*lo, hi*hi
-            // for both row fragments); B fragments prefetched one ahead.
-            auto run_section = [&](const uint32_t *buf, auto cc, auto &&pre, auto &&work) {
+            // for both row fragments).  B fragments are prefetched one ahead;
+            // the first one of the next section (colour nc of buffer nbuf) is
+            // loaded during this section's last column fragment.
+            uint4 b0h, b0l;
+            auto load_b0 = [&](const uint32_t *buf, int c) {
+                b0h = *reinterpret_cast<const uint4 *>(buf + 2 * Lt::DPL + boff + 8 * c);
+                b0l = *reinterpret_cast<const uint4 *>(buf + 2 * Lt::DPL + Lt::WPL + boff + 8 * c);
+            };
+            auto run_section = [&](const uint32_t *buf, auto cc, auto &&pre, auto &&work, const uint32_t *nbuf, int nc) {
                 constexpr int c = cc;
                 const uint32_t *W0 = buf + 2 * Lt::DPL, *W1 = W0 + Lt::WPL;
                 uint4 bh[2], bl[2];
-                bh[0] = *reinterpret_cast<const uint4 *>(W0 + boff + 8 * c);
-                bl[0] = *reinterpret_cast<const uint4 *>(W1 + boff + 8 * c);
+                bh[0] = b0h;
+                bl[0] = b0l;
                 pre();
                 static_for<0, NB>([&](auto nn) {
                     constexpr int n = nn;
                     if constexpr (n + 1 < NB) {
                         bh[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W0 + boff + 8 * c + (n + 1) * rowaddr(32));
                         bl[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W1 + boff + 8 * c + (n + 1) * rowaddr(32));
+                    } else {
+                        load_b0(nbuf, nc);
                     }
                     static_for<0, 6>([&](auto kk) {
                         constexpr int k = kk, f = k & 1, prod = k >> 1;
@@ -480,8 +489,12 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                     al[f] = aln[f];
                 }
             };
+            // Generation slices start two MFMAs into a section, once the
+            // staging reads issued at its start have landed.
+            constexpr int GEN0 = 2;
 
             load_a(dwbuf, 0);
+            load_b0(dwbuf, 0);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 ah[f] = embed(rah[f], sel, flip);
@@ -527,9 +540,10 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                         }
                     };
                     run_section(cur, std::integral_constant<int, 0>{}, pre, [&](auto kk) {
-                        slot_steps<decltype(kk)::value, SLOTS, 48>(step);
+                        constexpr int k = kk;
+                        if constexpr (k >= GEN0) slot_steps<k - GEN0, SLOTS - GEN0, 48>(step);
                         a_prefetch(kk, cur, 1);
-                    });
+                    }, cur, 1);
                 }
                 // Colour 1 + W tile of chunk i+1: JW rounds x 3 colours x 4
                 // sites, 2 sub-steps each.
@@ -569,9 +583,10 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                         }
                     };
                     run_section(cur, std::integral_constant<int, 1>{}, pre, [&](auto kk) {
-                        slot_steps<decltype(kk)::value, SLOTS, 24 * Lt::JW>(step);
+                        constexpr int k = kk;
+                        if constexpr (k >= GEN0) slot_steps<k - GEN0, SLOTS - GEN0, 24 * Lt::JW>(step);
                         a_prefetch(kk, cur, 2);
-                    });
+                    }, cur, 2);
                 }
                 __syncthreads();
                 // Colour 2 + staging of chunk i+2 and loads of chunk i+3.
@@ -605,7 +620,7 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                     run_section(cur, std::integral_constant<int, 2>{}, [] {}, [&](auto kk) {
                         slot_steps<decltype(kk)::value, SLOTS, 2 * Lt::JL + 2>(step);
                         a_prefetch(kk, nxt, 0);
-                    });
+                    }, nxt, 0);
                 }
                 __syncthreads();
             }

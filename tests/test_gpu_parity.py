@@ -308,3 +308,54 @@ def test_error_paths_enqueue_nothing(torch_dev):
         assert torch.all(out == 7.0).item()
     finally:
         binding.bblock_destroy(h)
+
+
+# ------------------------------------------- grouped workloads at full block size
+def _sampled_batch_check(torch_dev, prec, L, dtype, blocks, mom, rows_per_block=2, seed=7):
+    """blocks: list of (q1, q2, q3) numpy fields; one grouped launch, sampled rows vs oracle."""
+    torch, dev = torch_dev
+    g = np.random.default_rng(seed)
+    tq = [[torch.from_numpy(q).to(dev) for q in trip] for trip in blocks]
+    outs = [torch.empty((len(mom), *(q.shape[-1] for q in trip)), dtype=torch.complex128, device=dev)
+            for trip in blocks]
+    max_n = max(max(q.shape[-1] for q in trip) for trip in blocks)
+    with binding.BaryonBlocks(L, prec=prec, in_dtype=dtype, max_ndil=max_n) as bb:
+        bb.compute_batch([(*t, o) for t, o in zip(tq, outs)], mom)
+        bb.sync()
+    worst = 0.0
+    for trip, o in zip(blocks, outs):
+        n1, n2 = trip[0].shape[-1], trip[1].shape[-1]
+        rows = np.stack([g.integers(0, n1, rows_per_block), g.integers(0, n2, rows_per_block)], axis=1)
+        got = o.cpu().numpy()
+        sub = np.stack([got[:, d1, d2, :] for d1, d2 in rows], axis=1)
+        worst = max(worst, err_max(sub, oracle.bblock_rows(L, *trip, mom, rows.astype(np.int32))))
+    return worst
+
+
+@pytest.mark.parametrize("prec", ("bf16x3", "fp32"))
+def test_batched_48_sampled(torch_dev, prec):
+    """48^3 sites, N_dil = 32, 27 momenta, complex64: 4 spin triples of one
+    timeslice in one grouped launch (the batched workload's block shape)."""
+    L, n = 48, 32
+    lines = [[synth.gaussian_field(L, n, workload=3, role=ln, spin=s, dtype=np.complex64) for s in range(2)]
+             for ln in range(3)]
+    blocks = [(lines[0][a], lines[1][b], lines[2][c]) for (a, b, c) in ((0, 0, 0), (1, 1, 1), (0, 1, 0))]
+    say("case batched-48 sampled", prec)
+    e = _sampled_batch_check(torch_dev, prec, L, "c64", blocks, synth.momenta("cube"))
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ("bf16x3", "fp64"))
+def test_uneven_32_sampled(torch_dev, prec):
+    """32^3 sites, 7 momenta, complex64: noise triples with N_dil 16, 32 and 64
+    mixed in one grouped launch (the uneven workload's block shapes)."""
+    L = 32
+    blocks = []
+    for k, n in enumerate((16, 32, 64)):
+        trip = [synth.gaussian_field(L, n, workload=4, t=k, role=ln, dtype=np.complex64) for ln in range(3)]
+        blocks.append(tuple(trip))
+    say("case uneven-32 sampled", prec)
+    e = _sampled_batch_check(torch_dev, prec, L, "c64", blocks, synth.momenta("axis"))
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
