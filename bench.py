@@ -33,6 +33,9 @@ PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 def kernel_name(path, plan, n2, n3):
     """Name of the contraction kernel a plan launches (as rocprofv3 lists it)."""
+    if plan["kernel"] == 2:
+        b2 = 32 if n2 >= 32 else 16
+        return "bb::w3::contract<%d, %d, false>" % (plan["nb"], b2)
     if plan["kernel"] == 1:
         b2, b3 = (32 if n2 >= 32 else 16), (32 if n3 >= 32 else 16)
         return "bb::fast::bb_fast<%d, %d, %d, %d, false>" % (PREC_ID[path], plan["nb"], b2, b3)
@@ -50,9 +53,11 @@ def flops(V, n1, n2, n3, n_mom):
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("paper_2211_16278_amd/csrc/bb_kernels.hip", "paper_2211_16278_amd/csrc/bb_internal.h"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2211_16278_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -158,13 +163,14 @@ def run_batch_workload(args, name):
         bb.profile(True)
         bb.profile_read()
         bb.compute_batch(descs, mom)
-        gemm_ms, red_ms, launches = bb.profile_read()
+        gemm_ms, red_ms, prep_ms, launches = bb.profile_read()
         bb.profile(False)
         bb.close()
         res[pname] = {"blocks_per_s": len(descs) * 1e3 / step_ms, "ms_per_step": step_ms,
                       "tflops_gemm_count": f_gemm / (step_ms * 1e-3) / 1e12,
                       "tflops_paper_count": f_alg / (step_ms * 1e-3) / 1e12,
                       "contraction_kernel_ms_per_step": gemm_ms, "reduce_kernel_ms_per_step": red_ms,
+                      "w_image_kernel_ms_per_step": prep_ms,
                       "contraction_launches_per_step": launches,
                       "mfma_frac": MFMA_PASSES[pname] * f_gemm / (gemm_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname]}
         print("# %s %-6s %d blocks  %.2f ms/step  %.1f blocks/s  MFMA %.1f%%" % (
@@ -207,11 +213,12 @@ def cpu_baseline(L, qs, mom, M, target_s=15.0):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--paths", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a captured hipGraph")
     ap.add_argument("--workload", default="headline-32",
                     help="headline-32 (the benchmark line), or a grouped workload: batched-48, uneven-32, "
                          "large-64, tiny-12")
@@ -259,6 +266,8 @@ def main() -> int:
     paths = {}
     for pname in [p for p in args.paths.split(",") if p]:
         bb = binding.BaryonBlocks(L, prec=pname, in_dtype="c128", max_ndil=n, stream=stream)
+        if args.no_graph:
+            bb.set_graph(False)
         plan = bb.get_plan(n, n, n, n_mom)
         for _ in range(args.warmup):
             bb.compute(*tq, mom, out=out)
@@ -277,7 +286,7 @@ def main() -> int:
         bb.profile_read()
         for _ in range(args.steps):
             bb.compute(*tq, mom, out=out)
-        gemm_ms, red_ms, launches = bb.profile_read()
+        gemm_ms, red_ms, prep_ms, launches = bb.profile_read()
         bb.profile(False)
         err = None
         if ref_rows is not None:
@@ -291,10 +300,13 @@ def main() -> int:
         paths[pname] = {
             "blocks_per_s": 1e3 / step_ms,
             "ms_per_step": step_ms,
+            "event_ms_per_step": ms / args.steps,
+            "wall_ms_per_step": wall * 1e3 / args.steps,
             "tflops_gemm_count": f_gemm / (step_ms * 1e-3) / 1e12,
             "tflops_paper_count": f_alg / (step_ms * 1e-3) / 1e12,
             "contraction_kernel_ms": g_avg,
             "reduce_kernel_ms": red_ms / max(1, launches),
+            "w_image_kernel_ms": prep_ms / max(1, launches),
             "mfma_tflops": ach,
             "mfma_peak_tflops": PEAK_TFLOPS[pname],
             "mfma_frac": ach / PEAK_TFLOPS[pname],
@@ -302,8 +314,9 @@ def main() -> int:
             "tol": TOL[pname],
             "plan": plan,
         }
-        print("# %-6s %.3f ms/block  %.1f blocks/s  contraction %.3f ms  reduce %.3f ms  MFMA %.1f TF (%.1f%%)  "
-              "err %s" % (pname, step_ms, 1e3 / step_ms, g_avg, red_ms / max(1, launches), ach,
+        print("# %-6s %.3f ms/block  %.1f blocks/s  contraction %.3f ms  reduce %.3f ms  w-image %.3f ms  "
+              "MFMA %.1f TF (%.1f%%)  err %s" % (pname, step_ms, 1e3 / step_ms, g_avg, red_ms / max(1, launches),
+                                                 prep_ms / max(1, launches), ach,
                           100 * ach / PEAK_TFLOPS[pname], "%.2e" % err if err is not None else "-"),
               file=sys.stderr, flush=True)
 
@@ -314,7 +327,10 @@ def main() -> int:
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print("# calibration copy: %d bytes read, %d bytes written" % (nbytes, nbytes), file=sys.stderr)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print("# calibration: device copy and elementwise neg, each %d bytes read, %d bytes written"
+              % (nbytes, nbytes), file=sys.stderr)
 
     head = "bf16x3" if "bf16x3" in paths else next(iter(paths))
     hp = paths[head]

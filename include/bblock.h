@@ -87,7 +87,14 @@ typedef struct {
     int32_t grid;        /* persistent grid size; 0 = planner chooses */
     int32_t kernel;      /* 0: generic tiles (any shape, every precision);
                             1: pipelined rectangular tiles (FP32 and BF16X3,
-                               n2 >= 16 and n3 >= 16; nb 4 or 7) */
+                               n2 >= 16 and n3 >= 16; nb 4 or 7);
+                            2: as 1 with the phase-weighted q3 precomputed
+                               into workspace images by a separate launch
+                               (BF16X3 only; the default there).  Needs
+                               workspace for one image per (column tile,
+                               chunk of 8 sites): 45056 bytes (nb 7) or 28672
+                               bytes (nb 4); the planner falls back to 1 when
+                               the cap does not allow it. */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device.
@@ -140,16 +147,17 @@ bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
                               bblock_plan *plan);
 
 /* Kernel timing.  While enabled (enable = 1), launches run eagerly (never
- * from a captured graph) and every contraction-kernel and reduction-kernel
- * launch is bracketed by HIP events recorded on the handle's stream. */
+ * from a captured graph) and every contraction-kernel, reduction-kernel and
+ * W-image launch is bracketed by HIP events recorded on the handle's stream. */
 bblock_status bblock_profile(bblock_t h, int32_t enable);
 
 /* Synchronises on the last recorded event, then returns the summed
- * event-timed milliseconds of the contraction kernels (gemm_ms) and of the
- * split-K reduction kernels (reduce_ms) recorded since the previous read, and
- * the number of contraction launches among them.  Any output pointer may be
- * NULL. */
-bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms, int32_t *gemm_launches);
+ * event-timed milliseconds of the contraction kernels (gemm_ms), of the
+ * split-K reduction kernels (reduce_ms) and of the W-image kernels of plan
+ * kernel 2 (prep_ms) recorded since the previous read, and the number of
+ * contraction launches among them.  Any output pointer may be NULL. */
+bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms, double *prep_ms,
+                                  int32_t *gemm_launches);
 
 /* Block until the handle's stream has drained; reports device-side errors. */
 bblock_status bblock_sync(bblock_t h);

@@ -71,7 +71,7 @@ def load(path: str = LIB_PATH):
         "bblock_get_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
         "bblock_profile": ([h, i32], ctypes.c_int),
         "bblock_profile_read": ([h, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
-                                 ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "bblock_sync": ([h], ctypes.c_int),
         "bblock_destroy": ([h], ctypes.c_int),
         "bblock_last_error": ([h], ctypes.c_char_p),
@@ -154,10 +154,10 @@ def bblock_profile(h, enable: bool):
 
 
 def bblock_profile_read(h):
-    """(gemm_ms, reduce_ms, gemm_launches) summed since the previous read."""
-    g, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
-    _check(h, load().bblock_profile_read(h, ctypes.byref(g), ctypes.byref(r), ctypes.byref(n)))
-    return g.value, r.value, n.value
+    """(gemm_ms, reduce_ms, prep_ms, gemm_launches) summed since the previous read."""
+    g, r, p, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _check(h, load().bblock_profile_read(h, ctypes.byref(g), ctypes.byref(r), ctypes.byref(p), ctypes.byref(n)))
+    return g.value, r.value, p.value, n.value
 
 
 def bblock_sync(h):

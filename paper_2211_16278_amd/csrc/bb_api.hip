@@ -30,7 +30,7 @@ thread_local std::string g_create_error;
 
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
-constexpr int K_GENERIC = 0, K_PIPELINED = 1;
+constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2;
 
 struct Plan {
     int kernel = K_GENERIC, nb = 0, splits = 0, persistent = 0, grid = 0;
@@ -57,6 +57,8 @@ struct SubBatch {
     int kernel, nb, b2, b3;
     int persistent, grid;
     int max_mn;
+    int went_off, n_went;   // W-image entries (precomputed-W kernel)
+    int cps_max;            // chunks per split, largest of the sub-batch
 };
 
 }  // namespace
@@ -69,6 +71,7 @@ struct bblock_s {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     int num_cu = 256;
+    int n_xcd = 8, cu_per_xcd = 32;  // gfx950: 32 CUs per XCD
     int lds_max = 160 * 1024;
 
     double *d_roots = nullptr;  // [L] complex128
@@ -91,9 +94,9 @@ struct bblock_s {
     // graph replay) is issued.
     std::vector<unsigned char> last_key;
     std::vector<SubBatch> last_subs;
-    size_t last_offs[4] = {0, 0, 0, 0};  // blocks, tiles, reduce list, momenta
+    size_t last_offs[5] = {0, 0, 0, 0, 0};  // blocks, tiles, reduce list, momenta, W-image entries
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::array<hipEvent_t, 2>> ev_gemm, ev_reduce;
+    std::vector<std::array<hipEvent_t, 2>> ev_gemm, ev_reduce, ev_prep;
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
     std::map<ShapeKey, Plan> forced, tuned;
     std::string err;
@@ -144,10 +147,11 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
     Geometry g;
     g.kernel = kernel;
     g.nb = nb;
-    if (kernel == K_PIPELINED) {
+    if (kernel == K_PIPELINED || kernel == K_W3) {
         g.b2 = pipelined_block(n2);
         g.b3 = pipelined_block(n3);
         if (h->prec == FP64 || g.b2 == 0 || g.b3 == 0 || (nb != 4 && nb != 7)) return g;
+        if (kernel == K_W3 && h->prec != BF16X3) return g;
         g.b1 = 128 / g.b2;
         g.m_tile = 128;
         g.n_tile = 32 * nb;
@@ -156,7 +160,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_nt3 = cdiv(n3, g.b3);
         g.n_mt = cdiv(n1, g.b1) * g.n_mt2;
         g.n_nt = cdiv(n_mom, g.bp) * g.n_nt3;
-        g.lds = fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
+        g.lds = kernel == K_W3 ? w3_lds_bytes(nb, g.b2) : fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
     } else {
         const KernelGeom k = kernel_geom(h->prec, nb, n_mom, h->L);
         if (k.lds_bytes <= 0) return g;
@@ -178,8 +182,9 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
 {
     Plan p;
     Geometry best;
+    const int tiled = h->prec == BF16X3 ? K_W3 : K_PIPELINED;
     for (int nb : {7, 4}) {
-        const Geometry g = geometry(h, K_PIPELINED, nb, n1, n2, n3, n_mom);
+        const Geometry g = geometry(h, tiled, nb, n1, n2, n3, n_mom);
         if (g.lds < 0) continue;
         if (best.lds < 0 || (long)g.n_nt * g.n_tile < (long)best.n_nt * best.n_tile) best = g;
     }
@@ -223,7 +228,8 @@ struct BlockPlan {
     BlockDesc d;
     Plan plan;
     Geometry g;
-    size_t ws_bytes;
+    size_t part_bytes;  // split-K partials
+    size_t ws_bytes;    // partials, then (precomputed-W kernel) the W images
 };
 
 // Sites per split for S splits: a multiple of CHUNK_SITES; the split count
@@ -234,7 +240,20 @@ void set_splits(bblock_t h, BlockPlan &bp, int S)
     const int sps = (int)align_up((size_t)((h->V + S - 1) / S), CHUNK_SITES);
     bp.d.sps = sps;
     bp.d.S = (h->V + sps - 1) / sps;
-    bp.ws_bytes = bp.d.S > 1 ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
+    bp.d.cps = sps / CHUNK_SITES;
+    bp.part_bytes = bp.d.S > 1 ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
+    bp.ws_bytes = bp.part_bytes;
+    if (bp.plan.kernel == K_W3)
+        bp.ws_bytes = align_up(bp.part_bytes, 4096) +
+                      (size_t)bp.g.n_nt * bp.d.S * bp.d.cps * w3_image_bytes(bp.plan.nb);
+}
+
+// The precomputed-W kernel addresses one split of q1/q2 with 32-bit byte
+// offsets (plus three chunks of read-ahead).
+bool w3_offsets_fit(bblock_t h, const BlockPlan &bp)
+{
+    const size_t per_site = (size_t)3 * std::max(bp.d.n1, bp.d.n2) * in_bytes(h->in_dtype);
+    return (size_t)(bp.d.sps + 4 * CHUNK_SITES) * per_site < ((size_t)1 << 31);
 }
 
 bblock_status validate_desc(bblock_t h, const bblock_desc &d, int i)
@@ -318,7 +337,7 @@ hipEvent_t take_event(bblock_t h)
 
 // Launch the kernels of all sub-batches on stream st; tables already uploaded.
 bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_blocks, size_t off_tiles,
-                      size_t off_list, size_t off_mom, int n_mom, hipStream_t st)
+                      size_t off_list, size_t off_mom, size_t off_went, int n_mom, hipStream_t st)
 {
     for (const SubBatch &sb : subs) {
         GemmArgs ga;
@@ -335,14 +354,36 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_
         ga.kidx = h->d_kidx;
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
+        if (sb.kernel == K_W3) {
+            WImageArgs wa;
+            wa.blocks = ga.blocks;
+            wa.entries = reinterpret_cast<const int4 *>(h->d_table + off_went) + sb.went_off;
+            wa.n_entries = sb.n_went;
+            wa.mom = ga.mom;
+            wa.n_mom = n_mom;
+            wa.L = h->L;
+            wa.V = h->V;
+            wa.roots = h->d_roots;
+            if (h->profiling) {
+                ev = {take_event(h), take_event(h)};
+                if (!ev[0] || !ev[1]) return fail(h, BBLOCK_EHIP, "profiling event creation failed");
+                HIP_OR_FAIL(h, hipEventRecord(ev[0], st));
+            }
+            hipError_t e = launch_w3_image(sb.nb, ga.in_c64, wa, sb.cps_max, st);
+            if (e != hipSuccess) return hip_fail(h, e, "launch of the W-image kernel");
+            if (h->profiling) {
+                HIP_OR_FAIL(h, hipEventRecord(ev[1], st));
+                h->ev_prep.push_back(ev);
+            }
+        }
         if (h->profiling) {
             ev = {take_event(h), take_event(h)};
             if (!ev[0] || !ev[1]) return fail(h, BBLOCK_EHIP, "profiling event creation failed");
             HIP_OR_FAIL(h, hipEventRecord(ev[0], st));
         }
-        hipError_t e = sb.kernel == K_PIPELINED
-                           ? launch_fast(h->prec, sb.nb, sb.b2, sb.b3, ga.in_c64, ga, grid, st)
-                           : launch_gemm(h->prec, sb.nb, ga, grid, st);
+        hipError_t e = sb.kernel == K_PIPELINED ? launch_fast(h->prec, sb.nb, sb.b2, sb.b3, ga.in_c64, ga, grid, st)
+                       : sb.kernel == K_W3      ? launch_w3(sb.nb, sb.b2, ga.in_c64, ga, grid, st)
+                                                : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
         if (h->profiling) {
             HIP_OR_FAIL(h, hipEventRecord(ev[1], st));
@@ -371,22 +412,24 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_
 
 // Launch a planned batch whose tables are on the device: eagerly, or by
 // replaying (capturing on first use) the graph of this batch structure.
-bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, const size_t offs[4], int n_mom)
+bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, const size_t offs[5], int n_mom)
 {
-    if (!h->graph_enabled || h->profiling) return enqueue(h, subs, offs[0], offs[1], offs[2], offs[3], n_mom, h->stream);
+    if (!h->graph_enabled || h->profiling)
+        return enqueue(h, subs, offs[0], offs[1], offs[2], offs[3], offs[4], n_mom, h->stream);
     // Graph signature: everything baked into kernel arguments.
     std::vector<long long> sig;
     sig.push_back(n_mom);
     sig.push_back((long long)(uintptr_t)h->d_table);
     sig.push_back((long long)(uintptr_t)h->d_kidx);
-    for (int k = 0; k < 4; ++k) sig.push_back((long long)offs[k]);
+    sig.push_back((long long)(uintptr_t)h->d_ws);
+    for (int k = 0; k < 5; ++k) sig.push_back((long long)offs[k]);
     for (const SubBatch &sb : subs)
         sig.insert(sig.end(), {sb.first, sb.count, sb.tile_off, sb.n_tiles, sb.list_off, sb.n_list, sb.kernel, sb.nb,
-                               sb.b2, sb.b3, sb.persistent, sb.grid, sb.max_mn});
+                               sb.b2, sb.b3, sb.persistent, sb.grid, sb.max_mn, sb.went_off, sb.n_went, sb.cps_max});
     auto it = h->graphs.find(sig);
     if (it == h->graphs.end()) {
         HIP_OR_FAIL(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        bblock_status st = enqueue(h, subs, offs[0], offs[1], offs[2], offs[3], n_mom, h->cap_stream);
+        bblock_status st = enqueue(h, subs, offs[0], offs[1], offs[2], offs[3], offs[4], n_mom, h->cap_stream);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
         if (st != BBLOCK_OK) {
@@ -456,6 +499,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         bp.d.n_mt2 = bp.g.n_mt2;
         bp.d.n_nt3 = bp.g.n_nt3;
         bp.d.bp = bp.g.bp;
+        bp.d.b3 = bp.g.b3;
         total_tiles_s1 += (long)bp.g.n_mt * bp.g.n_nt;
     }
     // Split count: a forced plan fixes it; a single block uses its plan's
@@ -473,6 +517,18 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             S = (int)std::max<long>(s_min, (2L * h->num_cu + total_tiles_s1 - 1) / total_tiles_s1);
         set_splits(h, bp, S);
         if (!fixed && bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
+        if (bp.plan.kernel == K_W3 && (bp.ws_bytes > h->ws_cap || !w3_offsets_fit(h, bp))) {
+            // The W images do not fit the workspace (or the split is too long
+            // for 32-bit offsets): the pipelined kernel builds W in LDS instead.
+            if (h->forced.count(k))
+                return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the precomputed-W plan needs %zu workspace bytes "
+                            "(cap %zu) and splits of at most 2 GiB of q1/q2", i, bp.ws_bytes, h->ws_cap);
+            bp.plan.kernel = K_PIPELINED;
+            bp.g = geometry(h, K_PIPELINED, bp.plan.nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
+            if (bp.g.lds < 0) return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
+            set_splits(h, bp, S);
+            if (bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
+        }
         if (bp.ws_bytes > h->ws_cap)
             return fail(h, BBLOCK_ENOMEM, "block %d needs %zu workspace bytes, cap is %zu", i, bp.ws_bytes, h->ws_cap);
     }
@@ -481,7 +537,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     // workspace within the cap.  Sub-batches run one after the other on the
     // stream, so each one reuses the workspace from offset 0.
     std::vector<SubBatch> subs;
-    std::vector<int4> tiles;
+    std::vector<int4> tiles, went;
     std::vector<int> list;
     std::vector<size_t> ws_off(n_desc, 0);
     size_t ws_need = 0;
@@ -501,7 +557,13 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         sb.grid = bps[i].plan.grid > 0 ? bps[i].plan.grid : h->num_cu;
         any_pipelined |= sb.kernel == K_PIPELINED;
         size_t used = 0;
+        long n_went = 0;
         while (i < n_desc && same_kernel(bps[i], sb) && used + bps[i].ws_bytes <= h->ws_cap) {
+            if (sb.kernel == K_W3) {  // image entries form the y dimension of one launch
+                const long e = (long)bps[i].g.n_nt * bps[i].d.S;
+                if (i > sb.first && n_went + e > 65535) break;
+                n_went += e;
+            }
             ws_off[i] = used;
             used += align_up(bps[i].ws_bytes, 256);
             ++i;
@@ -530,18 +592,53 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             }
         }
         sb.n_list = (int)list.size() - sb.list_off;
+        sb.went_off = (int)went.size();
+        if (sb.kernel == K_W3) {
+            for (int b = sb.first; b < i; ++b) {
+                const BlockPlan &bp = bps[b];
+                sb.cps_max = std::max(sb.cps_max, bp.d.cps);
+                for (int nt = 0; nt < bp.g.n_nt; ++nt)
+                    for (int s = 0; s < bp.d.S; ++s) went.push_back(make_int4(b, nt, s, 0));
+            }
+            if (went.size() - sb.went_off > 65535)
+                return fail(h, BBLOCK_EUNSUPPORTED, "block %d has more than 65535 (n-tile, split) pairs", sb.first);
+        }
+        sb.n_went = (int)went.size() - sb.went_off;
         std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
         sb.tile_off = (int)tiles.size();
         sb.n_tiles = (int)items.size();
-        for (const Item &it : items) tiles.push_back(it.t);
+        // XCD-aware order.  The dispatcher hands workgroup g to XCD g mod
+        // n_xcd, and each XCD has its own L2.  The tiles of one (block,
+        // split) read the same q2/q3 site range, so they are dealt to one
+        // XCD: in each round of n_xcd * k table entries, XCD x receives k
+        // consecutive entries of the cost-sorted list (k = tiles per split).
+        // A persistent launch takes tiles from a counter instead, where the
+        // order only sets the cost ordering.
+        {
+            const int n_xcd = sb.persistent ? 1 : h->n_xcd;
+            const BlockPlan &b0 = bps[sb.first];
+            const int k = (int)std::min<long>(std::max<long>(1, (long)b0.g.n_mt * b0.g.n_nt), h->cu_per_xcd);
+            const int n = (int)items.size();
+            for (int base = 0; base < n; base += n_xcd * k) {
+                const int m = std::min(n_xcd * k, n - base);
+                const int q = m / n_xcd, r = m % n_xcd;
+                for (int j = 0; j < m; ++j) {
+                    const int x = j % n_xcd, local = j / n_xcd;
+                    tiles.push_back(items[base + x * q + std::min(x, r) + local].t);
+                }
+            }
+        }
         subs.push_back(sb);
     }
     {
         bblock_status st = ensure_ws(h, ws_need);
         if (st != BBLOCK_OK) return st;
     }
-    for (int i = 0; i < n_desc; ++i)
-        bps[i].d.ws = bps[i].ws_bytes ? static_cast<unsigned char *>(h->d_ws) + ws_off[i] : nullptr;
+    for (int i = 0; i < n_desc; ++i) {
+        unsigned char *base = static_cast<unsigned char *>(h->d_ws) + ws_off[i];
+        bps[i].d.ws = bps[i].part_bytes ? base : nullptr;
+        bps[i].d.wimg = bps[i].plan.kernel == K_W3 ? base + align_up(bps[i].part_bytes, 4096) : nullptr;
+    }
 
     // Device tables: blocks | tiles | reduce list | momenta (reduced mod L).
     std::vector<int> mom_red(3 * n_mom);
@@ -550,7 +647,8 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     const size_t off_tiles = align_up(off_blocks + sizeof(BlockDesc) * n_desc, 256);
     const size_t off_list = align_up(off_tiles + sizeof(int4) * tiles.size(), 256);
     const size_t off_mom = align_up(off_list + sizeof(int) * std::max<size_t>(1, list.size()), 256);
-    const size_t bytes = align_up(off_mom + sizeof(int) * 3 * n_mom, 256);
+    const size_t off_went = align_up(off_mom + sizeof(int) * 3 * n_mom, 256);
+    const size_t bytes = align_up(off_went + sizeof(int4) * std::max<size_t>(1, went.size()), 256);
     {
         bblock_status st = ensure_table(h, bytes);
         if (st != BBLOCK_OK) return st;
@@ -561,6 +659,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     if (!tiles.empty()) std::memcpy(hs + off_tiles, tiles.data(), sizeof(int4) * tiles.size());
     if (!list.empty()) std::memcpy(hs + off_list, list.data(), sizeof(int) * list.size());
     std::memcpy(hs + off_mom, mom_red.data(), sizeof(int) * 3 * n_mom);
+    if (!went.empty()) std::memcpy(hs + off_went, went.data(), sizeof(int4) * went.size());
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_table, hs, bytes, hipMemcpyHostToDevice, h->stream));
     HIP_OR_FAIL(h, hipEventRecord(h->staging_free, h->stream));
     if (any_pipelined) {
@@ -574,6 +673,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     h->last_offs[1] = off_tiles;
     h->last_offs[2] = off_list;
     h->last_offs[3] = off_mom;
+    h->last_offs[4] = off_went;
     return launch_planned(h, subs, h->last_offs, n_mom);
 }
 
@@ -636,6 +736,7 @@ bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_d
     h->ws_cap = workspace_cap ? workspace_cap : (size_t)8 << 30;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    h->n_xcd = std::max(1, h->num_cu / h->cu_per_xcd);
     h->lds_max = (int)prop.sharedMemPerBlock;
 
     auto bail = [&](bblock_status st, const char *what) {
@@ -729,7 +830,8 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         h->forced.erase(k);
         return BBLOCK_OK;
     }
-    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED) return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
+    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && plan->kernel != K_W3)
+        return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
     if (geometry(h, plan->kernel, plan->nb, n1, n2, n3, n_mom).lds <= 0)
@@ -822,6 +924,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         const int *opts;
         const int n_opts = nb_options(h->prec, &opts);
         std::vector<std::pair<int, int>> kn;
+        for (int nb : {7, 4}) kn.push_back({K_W3, nb});
         for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
         const int N = n3 * n_mom;
@@ -842,6 +945,10 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         h->forced[key] = cand;
         const bblock_desc d{q[0], q[1], q[2], n1, n2, n3, 0, out};
         st = run_batch(h, &d, 1, mom.data(), n_mom);
+        if (st == BBLOCK_EUNSUPPORTED || st == BBLOCK_ENOMEM) {  // candidate does not fit this shape
+            st = BBLOCK_OK;
+            continue;
+        }
         if (st != BBLOCK_OK) break;
         if (hipStreamSynchronize(h->stream) != hipSuccess) {
             st = fail(h, BBLOCK_EHIP, "tune candidate failed");
@@ -897,14 +1004,15 @@ bblock_status bblock_profile(bblock_t h, int32_t enable)
     return BBLOCK_OK;
 }
 
-bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms, int32_t *gemm_launches)
+bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms, double *prep_ms,
+                                  int32_t *gemm_launches)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
-    double sums[2] = {0.0, 0.0};
+    double sums[3] = {0.0, 0.0, 0.0};
     const int n_gemm = (int)h->ev_gemm.size();
     bblock_status st = BBLOCK_OK;
-    std::vector<std::array<hipEvent_t, 2>> *lists[2] = {&h->ev_gemm, &h->ev_reduce};
-    for (int k = 0; k < 2; ++k) {
+    std::vector<std::array<hipEvent_t, 2>> *lists[3] = {&h->ev_gemm, &h->ev_reduce, &h->ev_prep};
+    for (int k = 0; k < 3; ++k) {
         for (auto &ev : *lists[k]) {
             float ms = 0.0f;
             hipError_t e = hipEventSynchronize(ev[1]);
@@ -918,6 +1026,7 @@ bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms
     }
     if (gemm_ms) *gemm_ms = sums[0];
     if (reduce_ms) *reduce_ms = sums[1];
+    if (prep_ms) *prep_ms = sums[2];
     if (gemm_launches) *gemm_launches = n_gemm;
     return st;
 }
@@ -944,6 +1053,7 @@ bblock_status bblock_destroy(bblock_t h)
     if (h->staging_free) (void)hipEventDestroy(h->staging_free);
     for (auto &ev : h->ev_gemm) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
     for (auto &ev : h->ev_reduce) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
+    for (auto &ev : h->ev_prep) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;

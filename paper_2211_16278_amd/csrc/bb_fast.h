@@ -64,9 +64,12 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
     return __builtin_bit_cast(uint32_t, v);
 }
 
+// Complex product with a fixed rounding sequence (one rounded product, then
+// one fused multiply-add per part), so that every kernel that forms the same
+// product gets the same bits whatever the compiler's contraction choices.
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b)
 {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
 // Four complex values of one tile row (4 consecutive kappa) into the two planes.

@@ -32,6 +32,11 @@ struct BlockDesc {
     int n_mt2;                 // d2 blocks
     int n_nt3;                 // d3 blocks
     int bp;                    // momenta per n-tile
+    int b3;                    // d3 per n-tile
+    // W images of the precomputed-W kernel: [n-tile][split][chunk] images of
+    // one n-tile over one chunk; null for the other kernels.
+    void *wimg;
+    int cps;                   // chunks per split (image stride)
     int pad;
 };
 
@@ -47,6 +52,17 @@ struct GemmArgs {
     int in_c64;
     const double *roots; // [L] complex128 exp(-2 pi i k / L)
     const unsigned char *kidx;  // [n_mom][V] phase index (n_p . x) mod L (pipelined kernel)
+};
+
+// Arguments of the W-image launch of the precomputed-W kernel.
+struct WImageArgs {
+    const BlockDesc *blocks;
+    const int4 *entries;  // (block, n-tile, split, 0)
+    int n_entries;
+    const int *mom;       // [n_mom][3], reduced mod L
+    int n_mom;
+    int L, V;
+    const double *roots;  // [L] complex128 exp(-2 pi i k / L)
 };
 
 struct ReduceArgs {
@@ -75,6 +91,12 @@ hipError_t launch_fast(int prec, int nb, int b2, int b3, int in_c64, const GemmA
 hipError_t prepare_fast_kernels(int lds_bytes);
 // kidx[p][x] = (n_p . x) mod L for all sites of one timeslice (momenta already in [0, L)).
 hipError_t launch_phase_index(const int *mom, int n_mom, int L, unsigned char *kidx, hipStream_t st);
+// Precomputed-W kernel (BF16X3; d2 blocks of 16 or 32, nb 4 or 7): static
+// LDS bytes (-1 when no instantiation), bytes per W image, launches.
+int w3_lds_bytes(int nb, int b2);
+size_t w3_image_bytes(int nb);
+hipError_t launch_w3_image(int nb, int c64, const WImageArgs &a, int cps_max, hipStream_t st);
+hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
 hipError_t prepare_kernels(int lds_bytes);  // dynamic-LDS limit of every contraction kernel
 

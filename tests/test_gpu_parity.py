@@ -42,10 +42,10 @@ def err_max(got, ref):
     return float(np.abs(got - ref).max() / np.abs(ref).max())
 
 
-def gpu_block(torch_dev, prec, L, qs, mom, dtype="c128", plan=None, graph=True, max_ndil=64):
+def gpu_block(torch_dev, prec, L, qs, mom, dtype="c128", plan=None, graph=True, max_ndil=64, workspace_cap=0):
     torch, dev = torch_dev
     tq = [torch.from_numpy(np.ascontiguousarray(q)).to(dev) for q in qs]
-    with binding.BaryonBlocks(L, prec=prec, in_dtype=dtype, max_ndil=max_ndil) as bb:
+    with binding.BaryonBlocks(L, prec=prec, in_dtype=dtype, max_ndil=max_ndil, workspace_cap=workspace_cap) as bb:
         bb.set_graph(graph)
         if plan is not None:
             bb.set_plan(qs[0].shape[-1], qs[1].shape[-1], qs[2].shape[-1], len(mom), plan)
@@ -123,6 +123,8 @@ def _plans(prec):
     kernels = [(0, nb) for nb in ((1, 2, 4, 7, 14) if prec == "fp64" else (1, 2, 4, 7))]
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
+    if prec == "bf16x3":
+        kernels += [(2, 4), (2, 7)]
     for kernel, nb in kernels:
         for splits in (1, 3, 16):
             for persistent in (0, 1):
@@ -162,6 +164,39 @@ def test_determinism_graph_persistent(torch_dev, prec):
     assert np.array_equal(a, b)
     assert np.array_equal(c, d)
     assert err_max(a, oracle.bblock(L, *qs, mom)) < TOL[prec]
+
+
+@pytest.mark.parametrize("L,ns,dtype", [(6, (24, 24, 24), "c128"), (5, (19, 40, 23), "c128"), (4, (33, 16, 35), "c64")])
+def test_precomputed_w_matches_pipelined_bitwise(torch_dev, L, ns, dtype):
+    """BF16x3: the kernel with precomputed W images (plan kernel 2) forms the
+    same products in the same order as the kernel that builds W in LDS (plan
+    kernel 1), so the two blocks are bitwise equal; persistent and
+    one-tile-per-workgroup schedules of kernel 2 agree too."""
+    qs = fields(L, ns, workload=112, dtype=np.complex64 if dtype == "c64" else np.complex128)
+    mom = synth.momenta("cube")
+    for nb in (7, 4):
+        say("case w3 vs pipelined", L, ns, dtype, nb)
+        a = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=1, nb=nb, splits=3, persistent=0))
+        b = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=2, nb=nb, splits=3, persistent=0))
+        c = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype,
+                      plan=dict(kernel=2, nb=nb, splits=3, persistent=1, grid=5))
+        assert np.array_equal(a, b)
+        assert np.array_equal(b, c)
+    assert err_max(b, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
+
+
+def test_precomputed_w_small_workspace_falls_back(torch_dev):
+    """A workspace cap too small for the W images: the planner runs the block
+    with the in-LDS W kernel instead, with the same result."""
+    L, ns = 6, (24, 24, 24)
+    qs = fields(L, ns, workload=113)
+    mom = synth.momenta("axis")
+    say("case w3 fallback")
+    # 1 MiB holds neither the images nor split partials: one split, kernel 1.
+    small = gpu_block(torch_dev, "bf16x3", L, qs, mom, workspace_cap=1 << 20)
+    k1 = gpu_block(torch_dev, "bf16x3", L, qs, mom, plan=dict(kernel=1, nb=7, splits=1, persistent=0))
+    assert np.array_equal(small, k1)
+    assert err_max(small, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -239,7 +274,7 @@ def test_tune_then_compute(torch_dev):
     with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
         bb.tune(*ns, len(mom))
         plan = bb.get_plan(*ns, len(mom))
-        assert plan["kernel"] in (0, 1) and plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
+        assert plan["kernel"] in (0, 1, 2) and plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
         out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
         bb.sync()
     assert err_max(out[0].cpu().numpy(), oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
