@@ -33,10 +33,17 @@ typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
 
 constexpr int MT = 128;  // complex rows per workgroup
 
-// u32 offset of tile row r: 24 words (one chunk of kappa) per row plus 4 words
-// of padding after every 4 rows, so the 8 lanes of one ds_read_b128 /
-// ds_write_b128 pass (8 consecutive rows) touch disjoint banks.
-__host__ __device__ constexpr int rowaddr(int r) { return r * 24 + (r >> 2) * 4; }
+// u32 offsets of tile rows (24 words = one chunk of kappa per row, plus
+// padding).  The fragment accesses put row r = lane % 32 (and k-group
+// lane / 32, +4 words) on each lane; on gfx950 these 128-bit accesses are
+// free of LDS bank conflicts (SQ_LDS_BANK_CONFLICT = 0, measured per layout
+// with a probe kernel) for
+//   W tiles, read as B fragments: 24 r + 4 (r >> 4);
+//   D tiles, read as A fragments and written row per lane: 28 r;
+// while the earlier 24 r + 4 (r >> 2) costs about four conflict cycles per
+// read.  Both are additive over 32-row fragments: f(32 n + r) = f(32 n) + f(r).
+__host__ __device__ constexpr int wrow(int r) { return r * 24 + (r >> 4) * 4; }
+__host__ __device__ constexpr int drow(int r) { return r * 28; }
 
 template <int NB, int B2, int B3>
 struct Layout {
@@ -45,8 +52,8 @@ struct Layout {
     static constexpr int BPM = NT / B3;       // momentum slots per n-tile
     static constexpr int IPW = 32 / B3;       // momentum slots per wave per W round
     static constexpr int JW = (BPM + 4 * IPW - 1) / (4 * IPW);  // W rounds
-    static constexpr int DPL = rowaddr(MT);   // u32 per D plane
-    static constexpr int WPL = rowaddr(NT);   // u32 per W plane
+    static constexpr int DPL = drow(MT);   // u32 per D plane
+    static constexpr int WPL = wrow(NT);   // u32 per W plane
     static constexpr int DW = 2 * DPL + 2 * WPL;
     static constexpr int E1 = 24 * B1, E2 = 24 * B2, E3 = 24 * B3, EPH = 8 * BPM;
     static constexpr int SG = E1 + E2 + E3 + EPH;  // float2 per staging tile
@@ -103,7 +110,7 @@ __device__ __forceinline__ void gen_d(uint32_t *buf, const float2 *stg, int lane
     const float2 *S1 = stg, *S2 = stg + Lt::E1;
     uint32_t *D0 = buf, *D1 = buf + Lt::DPL;
     const int i2 = lane % B2, xg = (lane / B2) & 1, i1 = wave * (Lt::B1 / 4) + lane / (2 * B2);
-    const int off = rowaddr(i1 * B2 + i2) + 4 * xg;
+    const int off = drow(i1 * B2 + i2) + 4 * xg;
     float2 d[3][4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
@@ -136,7 +143,7 @@ __device__ __forceinline__ void gen_w(uint32_t *buf, const float2 *stg, int j, i
     const int i3 = lane % B3, xg = (lane / B3) & 1, ipl = lane / (2 * B3);
     const bool live = (wave + 4 * j) < NB;
     const int ip = wave * Lt::IPW + ipl + (live ? 4 * Lt::IPW * j : 0);
-    const int off = rowaddr(ip * B3 + i3) + 4 * xg;
+    const int off = wrow(ip * B3 + i3) + 4 * xg;
     float2 ph[4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) ph[x] = PH[ip * 8 + 4 * xg + x];
@@ -162,13 +169,13 @@ __device__ __forceinline__ void multiply(const uint32_t *buf, int c, f16_t (&acc
         // Row side real embedding: Re-row (Re, -Im), Im-row (Im, Re).
         const uint32_t sel = im_row ? 0x01000302u : 0x03020100u;
         const uint32_t flip = im_row ? 0u : 0x80000000u;
-        const int aoff = rowaddr(wave * 32 + (r & 15)) + 4 * g + 8 * c;
-        const int boff = rowaddr(r) + 4 * g + 8 * c;
+        const int aoff = drow(wave * 32 + (r & 15)) + 4 * g + 8 * c;
+        const int boff = wrow(r) + 4 * g + 8 * c;
         bf8_t ah[2], al[2];
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-            uint4 h = *reinterpret_cast<const uint4 *>(D0 + aoff + f * rowaddr(16));
-            uint4 l = *reinterpret_cast<const uint4 *>(D1 + aoff + f * rowaddr(16));
+            uint4 h = *reinterpret_cast<const uint4 *>(D0 + aoff + f * drow(16));
+            uint4 l = *reinterpret_cast<const uint4 *>(D1 + aoff + f * drow(16));
             h = make_uint4(__builtin_amdgcn_perm(h.x, h.x, sel) ^ flip, __builtin_amdgcn_perm(h.y, h.y, sel) ^ flip,
                            __builtin_amdgcn_perm(h.z, h.z, sel) ^ flip, __builtin_amdgcn_perm(h.w, h.w, sel) ^ flip);
             l = make_uint4(__builtin_amdgcn_perm(l.x, l.x, sel) ^ flip, __builtin_amdgcn_perm(l.y, l.y, sel) ^ flip,
@@ -178,8 +185,8 @@ __device__ __forceinline__ void multiply(const uint32_t *buf, int c, f16_t (&acc
         }
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
-            const bf8_t bh = __builtin_bit_cast(bf8_t, *reinterpret_cast<const uint4 *>(W0 + boff + n * rowaddr(32)));
-            const bf8_t bl = __builtin_bit_cast(bf8_t, *reinterpret_cast<const uint4 *>(W1 + boff + n * rowaddr(32)));
+            const bf8_t bh = __builtin_bit_cast(bf8_t, *reinterpret_cast<const uint4 *>(W0 + boff + n * wrow(32)));
+            const bf8_t bl = __builtin_bit_cast(bf8_t, *reinterpret_cast<const uint4 *>(W1 + boff + n * wrow(32)));
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 acc[f][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[f], bh, acc[f][n], 0, 0, 0);
@@ -193,14 +200,14 @@ __device__ __forceinline__ void multiply(const uint32_t *buf, int c, f16_t (&acc
         const uint32_t *Ap = (s ^ t) ? D1 : D0;
         const uint32_t flip = (s == 0 && t == 1) ? 0x80000000u : 0u;
         const uint32_t *Bp = t ? W1 : W0;
-        const int aoff = rowaddr(wave * 32 + (r & 15)) + 8 * c;
-        const int boff = rowaddr(r) + 8 * c;
+        const int aoff = drow(wave * 32 + (r & 15)) + 8 * c;
+        const int boff = wrow(r) + 8 * c;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             float av[2][4];
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(Ap + aoff + f * rowaddr(16) + 4 * h);
+                const uint4 v = *reinterpret_cast<const uint4 *>(Ap + aoff + f * drow(16) + 4 * h);
                 av[f][0] = __uint_as_float(v.x ^ flip);
                 av[f][1] = __uint_as_float(v.y ^ flip);
                 av[f][2] = __uint_as_float(v.z ^ flip);
@@ -208,7 +215,7 @@ __device__ __forceinline__ void multiply(const uint32_t *buf, int c, f16_t (&acc
             }
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(Bp + boff + n * rowaddr(32) + 4 * h);
+                const uint4 v = *reinterpret_cast<const uint4 *>(Bp + boff + n * wrow(32) + 4 * h);
                 const float bv[4] = {__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w)};
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -426,10 +433,10 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
             const int g = lane >> 5, r = lane & 31;
             const uint32_t sel = r >= 16 ? 0x01000302u : 0x03020100u;
             const uint32_t flip = r >= 16 ? 0u : 0x80000000u;
-            const int aoff = rowaddr(wave * 32 + (r & 15)) + 4 * g;
-            const int boff = rowaddr(r) + 4 * g;
+            const int aoff = drow(wave * 32 + (r & 15)) + 4 * g;
+            const int boff = wrow(r) + 4 * g;
             const int i2 = lane % B2, xgd = (lane / B2) & 1, i1 = wave * (Lt::B1 / 4) + lane / (2 * B2);
-            const int doff = rowaddr(i1 * B2 + i2) + 4 * xgd;
+            const int doff = drow(i1 * B2 + i2) + 4 * xgd;
             const int i3 = lane % B3, xgw = (lane / B3) & 1, ipl = lane / (2 * B3);
             const float2 *S1 = stg, *S2 = stg + Lt::E1, *S3 = S2 + Lt::E2, *PH = S3 + Lt::E3;
 
@@ -438,8 +445,8 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
             auto load_a = [&](const uint32_t *buf, int c) {
 #pragma unroll
                 for (int f = 0; f < 2; ++f) {
-                    rah[f] = *reinterpret_cast<const uint4 *>(buf + aoff + 8 * c + f * rowaddr(16));
-                    ral[f] = *reinterpret_cast<const uint4 *>(buf + Lt::DPL + aoff + 8 * c + f * rowaddr(16));
+                    rah[f] = *reinterpret_cast<const uint4 *>(buf + aoff + 8 * c + f * drow(16));
+                    ral[f] = *reinterpret_cast<const uint4 *>(buf + Lt::DPL + aoff + 8 * c + f * drow(16));
                 }
             };
             // A prefetch for the next section: raw loads at mid-section, the
@@ -471,8 +478,8 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                 static_for<0, NB>([&](auto nn) {
                     constexpr int n = nn;
                     if constexpr (n + 1 < NB) {
-                        bh[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W0 + boff + 8 * c + (n + 1) * rowaddr(32));
-                        bl[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W1 + boff + 8 * c + (n + 1) * rowaddr(32));
+                        bh[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W0 + boff + 8 * c + (n + 1) * wrow(32));
+                        bl[(n + 1) & 1] = *reinterpret_cast<const uint4 *>(W1 + boff + 8 * c + (n + 1) * wrow(32));
                     } else {
                         load_b0(nbuf, nc);
                     }
@@ -577,7 +584,7 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                             wh[j][c][x] = hi;
                             wl[j][c][x] = pack_bf16(wt[t].x - __uint_as_float(hi << 16), wt[t].y - __uint_as_float(hi & 0xffff0000u));
                             if constexpr (x == 3) {
-                                const int off = rowaddr(ip[j] * B3 + i3) + 4 * xgw + 8 * c;
+                                const int off = wrow(ip[j] * B3 + i3) + 4 * xgw + 8 * c;
                                 *reinterpret_cast<uint4 *>(nxt + 2 * Lt::DPL + off) =
                                     make_uint4(wh[j][c][0], wh[j][c][1], wh[j][c][2], wh[j][c][3]);
                                 *reinterpret_cast<uint4 *>(nxt + 2 * Lt::DPL + Lt::WPL + off) =

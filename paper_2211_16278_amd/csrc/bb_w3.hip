@@ -29,16 +29,17 @@ using fast::cmulf;
 using fast::f16_t;
 using fast::MT;
 using fast::pack_bf16;
-using fast::rowaddr;
+using fast::drow;
+using fast::wrow;
 using fast::static_for;
 
 // One W image: the hi and lo planes of an n-tile of NT columns over one chunk
-// (24 kappa per column, rowaddr padding), padded to whole 4 KiB rounds of the
+// (24 kappa per column, wrow padding), padded to whole 4 KiB rounds of the
 // direct-to-LDS copy (4 waves x 64 lanes x 16 bytes).
 template <int NB>
 struct WImg {
     static constexpr int NT = 32 * NB;
-    static constexpr int WPL = rowaddr(NT);                 // u32 per plane
+    static constexpr int WPL = wrow(NT);                 // u32 per plane
     static constexpr int DW = (2 * WPL + 1023) / 1024 * 1024; // u32 per image
     static constexpr int ROUNDS = DW / 1024;                 // copy instructions per wave
 };
@@ -46,7 +47,7 @@ struct WImg {
 template <int NB, int B2>
 struct CLayout {
     static constexpr int B1 = MT / B2;
-    static constexpr int DPL = rowaddr(MT);  // u32 per D plane
+    static constexpr int DPL = drow(MT);  // u32 per D plane
     static constexpr int E1 = 24 * B1, E2 = 24 * B2;
     static constexpr int SG = E1 + E2;       // float2 per staging buffer
     static constexpr int SINK = 64;          // slots written by lanes without an element
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(THREADS) w_image(WImageArgs a)
             hi[j] = pack_bf16(wr, wi);
             lo[j] = split_lo(wr, wi, hi[j]);
         }
-        const int off = rowaddr(col) + 8 * c + 4 * xg;
+        const int off = wrow(col) + 8 * c + 4 * xg;
         *reinterpret_cast<uint4 *>(img + off) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
         *reinterpret_cast<uint4 *>(img + Wi::WPL + off) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
     }
@@ -256,9 +257,9 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
 
         // Diquark generation: lane -> (i1, i2, site group of 4).
         const int i2 = lane % B2, xgd = (lane / B2) & 1, i1 = wave * (B1 / 4) + lane / (2 * B2);
-        const int doff = rowaddr(i1 * B2 + i2) + 4 * xgd;
-        const int aoff = rowaddr(wave * 32 + r) + 4 * g;
-        const int boff = rowaddr(r) + 4 * g;
+        const int doff = drow(i1 * B2 + i2) + 4 * xgd;
+        const int aoff = drow(wave * 32 + r) + 4 * g;
+        const int boff = wrow(r) + 4 * g;
 
         f16_t acc[2][NB];
 #pragma unroll
@@ -278,8 +279,8 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
             ra[1] = *reinterpret_cast<const uint4 *>(dbuf + Lt::DPL + aoff + 8 * c);
         };
         auto load_b = [&](const uint32_t *wbuf, int c, int n, int slot) {
-            bh[slot] = *reinterpret_cast<const uint4 *>(wbuf + boff + 8 * c + n * rowaddr(32));
-            bl[slot] = *reinterpret_cast<const uint4 *>(wbuf + Wi::WPL + boff + 8 * c + n * rowaddr(32));
+            bh[slot] = *reinterpret_cast<const uint4 *>(wbuf + boff + 8 * c + n * wrow(32));
+            bl[slot] = *reinterpret_cast<const uint4 *>(wbuf + Wi::WPL + boff + 8 * c + n * wrow(32));
         };
         // An[0..3] = (hi Re rows, lo Re rows, hi Im rows, lo Im rows)
         auto embed_step = [&](int s) {
@@ -371,7 +372,12 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
         // overlap its MFMAs.
         constexpr int NSLOT = 6 * FR - 6;                      // slots before the barrier
         constexpr int NQ = Lt::JL, NW = Wi::ROUNDS;
-        constexpr int W_STAGE = 0, W_LOAD = NQ, W_COPY = 2 * NQ, W_DGEN = 2 * NQ + NW;
+        // Work items in order: staging stores (their registers were loaded a
+        // chunk ago), the W copies, the staging loads, the diquark steps.
+        // The staging stores precede the copies because any wait for the
+        // stores' registers while a copy is in flight would wait for the copy.
+        constexpr int W_STAGE = 0, W_COPY = NQ, W_LOAD = NQ + NW, W_DGEN = 2 * NQ + NW;
+        constexpr int NFIRST = NQ + NW;  // items issued one per slot from the start of the chunk
         constexpr int NWORK = W_DGEN + NDGEN;
         auto chunk = [&](auto par, int i) {
             constexpr int P = decltype(par)::value;
@@ -382,15 +388,14 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
             const float2 *Sd = stg[P ^ 1];
             float2 *Ss = stg[P];
             const int cnext = min(i + 1, n_chunks - 1);
-            // Work item w of the chunk, run in slot w * NSLOT / NWORK.
             auto work = [&](auto ww) {
                 constexpr int w = ww;
-                if constexpr (w < W_LOAD)
+                if constexpr (w < W_COPY)
                     qstore(w - W_STAGE, Ss);
-                else if constexpr (w < W_COPY)
-                    qload(w - W_LOAD, i + 3);
-                else if constexpr (w < W_DGEN)
+                else if constexpr (w < W_LOAD)
                     wcopy(Wn, w - W_COPY, cnext);
+                else if constexpr (w < W_DGEN)
+                    qload(w - W_LOAD, i + 3);
                 else
                     dgen(std::integral_constant<int, w - W_DGEN>{}, Sd, Dn);
             };
@@ -421,8 +426,15 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
                         __builtin_amdgcn_sched_barrier(0);
                         constexpr int s = fr * 6 + k;  // slot
                         if constexpr (fr < FR - 1) {
-                            // Generation work, spread evenly over the slots.
-                            static_for<(s * NWORK + NSLOT - 1) / NSLOT, ((s + 1) * NWORK + NSLOT - 1) / NSLOT>(work);
+                            // Stores and copies one per slot from the start
+                            // (the copies' latency is the longest), the rest
+                            // of the work spread evenly over the other slots.
+                            if constexpr (s < NFIRST) {
+                                work(std::integral_constant<int, s>{});
+                            } else {
+                                constexpr int s2 = s - NFIRST, NS2 = NSLOT - NFIRST, NW2 = NWORK - NFIRST;
+                                static_for<NFIRST + (s2 * NW2 + NS2 - 1) / NS2, NFIRST + ((s2 + 1) * NW2 + NS2 - 1) / NS2>(work);
+                            }
                             // A of the next colour: read at mid-colour, turned
                             // into the four operands in the colour's last slots.
                             constexpr int cs = s - c * 6 * NB;  // slot within the colour
