@@ -229,7 +229,9 @@ struct BlockPlan {
     Plan plan;
     Geometry g;
     size_t part_bytes;  // split-K partials
-    size_t ws_bytes;    // partials, then (precomputed-W kernel) the W images
+    size_t ws_bytes;    // partials, then (precomputed-W kernel) the W images of one round
+    int rounds = 1;     // precomputed-W kernel: rounds of spr splits each
+    int spr = 0;
 };
 
 // Sites per split for S splits: a multiple of CHUNK_SITES; the split count
@@ -241,11 +243,21 @@ void set_splits(bblock_t h, BlockPlan &bp, int S)
     bp.d.sps = sps;
     bp.d.S = (h->V + sps - 1) / sps;
     bp.d.cps = sps / CHUNK_SITES;
+    bp.d.n_nt = bp.g.n_nt;
     bp.part_bytes = bp.d.S > 1 ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
     bp.ws_bytes = bp.part_bytes;
-    if (bp.plan.kernel == K_W3)
-        bp.ws_bytes = align_up(bp.part_bytes, 4096) +
-                      (size_t)bp.g.n_nt * bp.d.S * bp.d.cps * w3_image_bytes(bp.plan.nb);
+    bp.rounds = 1;
+    bp.spr = bp.d.S;
+    if (bp.plan.kernel == K_W3) {
+        // W images of all splits if they fit beside the partials, else rounds
+        // of as many splits as fit (at least one; 0 = does not fit).
+        const size_t per_split = (size_t)bp.g.n_nt * bp.d.cps * w3_image_bytes(bp.plan.nb);
+        const size_t part = align_up(bp.part_bytes, 4096);
+        const size_t room = h->ws_cap > part ? h->ws_cap - part : 0;
+        bp.spr = (int)std::min<size_t>(bp.d.S, room / per_split);
+        bp.rounds = bp.spr > 0 ? (bp.d.S + bp.spr - 1) / bp.spr : 1;
+        bp.ws_bytes = part + (size_t)std::max(bp.spr, 1) * per_split;
+    }
 }
 
 // The precomputed-W kernel addresses one split of q1/q2 with 32-bit byte
@@ -518,8 +530,9 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         set_splits(h, bp, S);
         if (!fixed && bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
         if (bp.plan.kernel == K_W3 && (bp.ws_bytes > h->ws_cap || !w3_offsets_fit(h, bp))) {
-            // The W images do not fit the workspace (or the split is too long
-            // for 32-bit offsets): the pipelined kernel builds W in LDS instead.
+            // Not even one split's W images fit beside the partials (or the
+            // split is too long for 32-bit offsets): the pipelined kernel
+            // builds W in LDS instead.
             if (h->forced.count(k))
                 return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the precomputed-W plan needs %zu workspace bytes "
                             "(cap %zu) and splits of at most 2 GiB of q1/q2", i, bp.ws_bytes, h->ws_cap);
@@ -533,42 +546,69 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             return fail(h, BBLOCK_ENOMEM, "block %d needs %zu workspace bytes, cap is %zu", i, bp.ws_bytes, h->ws_cap);
     }
 
-    // Sub-batches: consecutive blocks with one kernel instantiation and
-    // workspace within the cap.  Sub-batches run one after the other on the
-    // stream, so each one reuses the workspace from offset 0.
+    // Work units: (block, round).  Every block is one unit, except a
+    // precomputed-W block whose images need rounds: each round is a unit of
+    // its own with its own descriptor (a copy of the block's with img_s0 set).
+    struct Unit {
+        int b, r, d;  // block, round, descriptor index
+    };
+    std::vector<Unit> units;
+    std::vector<BlockDesc> descs(n_desc);
+    for (int b = 0; b < n_desc; ++b) {
+        for (int r = 0; r < bps[b].rounds; ++r) {
+            int d = b;
+            if (r > 0) {
+                d = (int)descs.size();
+                descs.push_back(BlockDesc{});
+            }
+            units.push_back({b, r, d});
+        }
+    }
+    if (descs.size() > 65535) return fail(h, BBLOCK_EUNSUPPORTED, "more than 65535 block rounds in one batch");
+
+    // Sub-batches: consecutive units with one kernel instantiation and
+    // workspace within the cap (a unit of a block in rounds stays alone).
+    // Sub-batches run one after the other on the stream, so each one reuses
+    // the workspace from offset 0; a block in rounds keeps its partials at
+    // offset 0 through all its rounds and is reduced after the last.
     std::vector<SubBatch> subs;
     std::vector<int4> tiles, went;
     std::vector<int> list;
-    std::vector<size_t> ws_off(n_desc, 0);
+    std::vector<size_t> ws_off(descs.size(), 0);
     size_t ws_need = 0;
     bool any_pipelined = false;
     auto same_kernel = [&](const BlockPlan &x, const SubBatch &sb) {
         return x.plan.kernel == sb.kernel && x.plan.nb == sb.nb && x.g.b2 == sb.b2 && x.g.b3 == sb.b3 &&
                x.plan.persistent == sb.persistent;
     };
-    for (int i = 0; i < n_desc;) {
+    for (size_t u = 0; u < units.size();) {
+        const BlockPlan &b0 = bps[units[u].b];
         SubBatch sb{};
-        sb.first = i;
-        sb.kernel = bps[i].plan.kernel;
-        sb.nb = bps[i].plan.nb;
-        sb.b2 = bps[i].g.b2;
-        sb.b3 = bps[i].g.b3;
-        sb.persistent = bps[i].plan.persistent;
-        sb.grid = bps[i].plan.grid > 0 ? bps[i].plan.grid : h->num_cu;
+        sb.first = (int)u;
+        sb.kernel = b0.plan.kernel;
+        sb.nb = b0.plan.nb;
+        sb.b2 = b0.g.b2;
+        sb.b3 = b0.g.b3;
+        sb.persistent = b0.plan.persistent;
+        sb.grid = b0.plan.grid > 0 ? b0.plan.grid : h->num_cu;
         any_pipelined |= sb.kernel == K_PIPELINED;
         size_t used = 0;
         long n_went = 0;
-        while (i < n_desc && same_kernel(bps[i], sb) && used + bps[i].ws_bytes <= h->ws_cap) {
+        const size_t u0 = u;
+        while (u < units.size()) {
+            const BlockPlan &bp = bps[units[u].b];
+            if (u > u0 && (bp.rounds > 1 || b0.rounds > 1)) break;
+            if (!same_kernel(bp, sb) || used + bp.ws_bytes > h->ws_cap) break;
             if (sb.kernel == K_W3) {  // image entries form the y dimension of one launch
-                const long e = (long)bps[i].g.n_nt * bps[i].d.S;
-                if (i > sb.first && n_went + e > 65535) break;
+                const long e = (long)bp.g.n_nt * bp.spr;
+                if (u > u0 && n_went + e > 65535) break;
                 n_went += e;
             }
-            ws_off[i] = used;
-            used += align_up(bps[i].ws_bytes, 256);
-            ++i;
+            ws_off[units[u].d] = used;
+            used += align_up(bp.ws_bytes, 256);
+            ++u;
         }
-        sb.count = i - sb.first;
+        sb.count = (int)(u - u0);
         ws_need = std::max(ws_need, used);
         // Tiles, longest first (cost ~ rows x columns x sites); ties keep
         // (block, split, n-tile, m-tile) order so neighbours share inputs.
@@ -578,31 +618,30 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         };
         std::vector<Item> items;
         sb.list_off = (int)list.size();
-        for (int b = sb.first; b < i; ++b) {
-            const BlockPlan &bp = bps[b];
-            for (int s = 0; s < bp.d.S; ++s) {
+        sb.went_off = (int)went.size();
+        for (size_t v = u0; v < u; ++v) {
+            const Unit &un = units[v];
+            const BlockPlan &bp = bps[un.b];
+            const int s_lo = un.r * bp.spr, s_hi = std::min(bp.d.S, s_lo + bp.spr);
+            for (int s = s_lo; s < s_hi; ++s) {
                 const long sites = std::min(bp.d.sps, h->V - s * bp.d.sps);
                 const long cost = (long)bp.g.m_tile * bp.g.n_tile * sites;
                 for (int nt = 0; nt < bp.g.n_nt; ++nt)
-                    for (int mt = 0; mt < bp.g.n_mt; ++mt) items.push_back({cost, make_int4(b, mt, nt, s)});
+                    for (int mt = 0; mt < bp.g.n_mt; ++mt) items.push_back({cost, make_int4(un.d, mt, nt, s)});
             }
-            if (bp.d.S > 1) {
-                list.push_back(b);
+            if (sb.kernel == K_W3) {
+                sb.cps_max = std::max(sb.cps_max, bp.d.cps);
+                for (int s = s_lo; s < s_hi; ++s)
+                    for (int nt = 0; nt < bp.g.n_nt; ++nt) went.push_back(make_int4(un.d, nt, s, 0));
+            }
+            if (bp.d.S > 1 && un.r == bp.rounds - 1) {
+                list.push_back(un.d);
                 sb.max_mn = std::max(sb.max_mn, bp.d.M * bp.d.N);
             }
         }
         sb.n_list = (int)list.size() - sb.list_off;
-        sb.went_off = (int)went.size();
-        if (sb.kernel == K_W3) {
-            for (int b = sb.first; b < i; ++b) {
-                const BlockPlan &bp = bps[b];
-                sb.cps_max = std::max(sb.cps_max, bp.d.cps);
-                for (int nt = 0; nt < bp.g.n_nt; ++nt)
-                    for (int s = 0; s < bp.d.S; ++s) went.push_back(make_int4(b, nt, s, 0));
-            }
-            if (went.size() - sb.went_off > 65535)
-                return fail(h, BBLOCK_EUNSUPPORTED, "block %d has more than 65535 (n-tile, split) pairs", sb.first);
-        }
+        if (went.size() - sb.went_off > 65535)
+            return fail(h, BBLOCK_EUNSUPPORTED, "block %d has more than 65535 (n-tile, split) pairs", units[u0].b);
         sb.n_went = (int)went.size() - sb.went_off;
         std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
         sb.tile_off = (int)tiles.size();
@@ -616,7 +655,6 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         // order only sets the cost ordering.
         {
             const int n_xcd = sb.persistent ? 1 : h->n_xcd;
-            const BlockPlan &b0 = bps[sb.first];
             const int k = (int)std::min<long>(std::max<long>(1, (long)b0.g.n_mt * b0.g.n_nt), h->cu_per_xcd);
             const int n = (int)items.size();
             for (int base = 0; base < n; base += n_xcd * k) {
@@ -634,17 +672,21 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         bblock_status st = ensure_ws(h, ws_need);
         if (st != BBLOCK_OK) return st;
     }
-    for (int i = 0; i < n_desc; ++i) {
-        unsigned char *base = static_cast<unsigned char *>(h->d_ws) + ws_off[i];
-        bps[i].d.ws = bps[i].part_bytes ? base : nullptr;
-        bps[i].d.wimg = bps[i].plan.kernel == K_W3 ? base + align_up(bps[i].part_bytes, 4096) : nullptr;
+    for (const Unit &un : units) {
+        BlockPlan &bp = bps[un.b];
+        BlockDesc d = bp.d;
+        unsigned char *base = static_cast<unsigned char *>(h->d_ws) + ws_off[un.d];
+        d.ws = bp.part_bytes ? base : nullptr;
+        d.wimg = bp.plan.kernel == K_W3 ? base + align_up(bp.part_bytes, 4096) : nullptr;
+        d.img_s0 = un.r * bp.spr;
+        descs[un.d] = d;
     }
 
     // Device tables: blocks | tiles | reduce list | momenta (reduced mod L).
     std::vector<int> mom_red(3 * n_mom);
     for (int i = 0; i < 3 * n_mom; ++i) mom_red[i] = ((mom[i] % h->L) + h->L) % h->L;
     const size_t off_blocks = 0;
-    const size_t off_tiles = align_up(off_blocks + sizeof(BlockDesc) * n_desc, 256);
+    const size_t off_tiles = align_up(off_blocks + sizeof(BlockDesc) * descs.size(), 256);
     const size_t off_list = align_up(off_tiles + sizeof(int4) * tiles.size(), 256);
     const size_t off_mom = align_up(off_list + sizeof(int) * std::max<size_t>(1, list.size()), 256);
     const size_t off_went = align_up(off_mom + sizeof(int) * 3 * n_mom, 256);
@@ -655,7 +697,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     }
     HIP_OR_FAIL(h, hipEventSynchronize(h->staging_free));  // previous upload has left the staging buffer
     unsigned char *hs = h->h_staging;
-    for (int i = 0; i < n_desc; ++i) std::memcpy(hs + off_blocks + sizeof(BlockDesc) * i, &bps[i].d, sizeof(BlockDesc));
+    std::memcpy(hs + off_blocks, descs.data(), sizeof(BlockDesc) * descs.size());
     if (!tiles.empty()) std::memcpy(hs + off_tiles, tiles.data(), sizeof(int4) * tiles.size());
     if (!list.empty()) std::memcpy(hs + off_list, list.data(), sizeof(int) * list.size());
     std::memcpy(hs + off_mom, mom_red.data(), sizeof(int) * 3 * n_mom);

@@ -33,10 +33,14 @@ struct BlockDesc {
     int n_nt3;                 // d3 blocks
     int bp;                    // momenta per n-tile
     int b3;                    // d3 per n-tile
-    // W images of the precomputed-W kernel: [n-tile][split][chunk] images of
-    // one n-tile over one chunk; null for the other kernels.
+    // W images of the precomputed-W kernel: [split - img_s0][n-tile][chunk],
+    // one image per n-tile and chunk; null for the other kernels.  A block
+    // whose images exceed the workspace runs in rounds of consecutive splits
+    // (one descriptor per round, img_s0 = the round's first split).
     void *wimg;
-    int cps;                   // chunks per split (image stride)
+    int cps;                   // chunks per split
+    int n_nt;                  // n-tiles
+    int img_s0;
     int pad;
 };
 

@@ -2,8 +2,8 @@
 // (gfx950).  Same contraction as the other kernels (paper, Sec. 2, eq. (3) as
 // one complex GEMM over kappa = (colour, site)), split in two launches:
 //
-//   w_image : W[p][x][c][d3] = exp(-i p.x) q3[x][c][d3] of every (n-tile,
-//             split, chunk), split into BF16 hi/lo planes and written to the
+//   w_image : W[p][x][c][d3] = exp(-i p.x) q3[x][c][d3] of every (split,
+//             n-tile, chunk), split into BF16 hi/lo planes and written to the
 //             workspace in exactly the byte layout of the W tile in LDS.
 //             Every m-tile of a split reads the same images, so the phase
 //             multiplication and the split run once per column instead of
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(THREADS) w_image(WImageArgs a)
     __syncthreads();
 
     uint32_t *img = reinterpret_cast<uint32_t *>(bd.wimg) +
-                    (((size_t)en.y * bd.S + en.z) * bd.cps + ci) * (size_t)Wi::DW;
+                    (((size_t)(en.z - bd.img_s0) * bd.n_nt + en.y) * bd.cps + ci) * (size_t)Wi::DW;
     for (int it = tid; it < Wi::NT * 6; it += THREADS) {
         const int col = it / 6, r6 = it - col * 6, c = r6 >> 1, xg = r6 & 1;
         const int ip = col / B3, i3 = col - ip * B3;
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
         const int xe = min(V, xs + bd.sps);
         const int n_chunks = (xe - xs + CHUNK_SITES - 1) / CHUNK_SITES;
         const uint32_t *img = reinterpret_cast<const uint32_t *>(bd.wimg) +
-                              ((size_t)tl.z * bd.S + tl.w) * bd.cps * (size_t)Wi::DW;
+                              ((size_t)(tl.w - bd.img_s0) * bd.n_nt + tl.z) * bd.cps * (size_t)Wi::DW;
 
         // q1/q2 of this split through buffer resources: loads past the
         // split's sites (or of slots without an element) are out of range and

@@ -199,6 +199,22 @@ def test_precomputed_w_small_workspace_falls_back(torch_dev):
     assert err_max(small, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
 
 
+def test_precomputed_w_in_rounds_matches(torch_dev):
+    """W images larger than the workspace run in rounds of splits (each round:
+    images, then the contraction of its splits; the reduction after the last),
+    bitwise equal to the single-round run with the same split count."""
+    L, ns = 6, (24, 24, 24)
+    qs = fields(L, ns, workload=114)
+    mom = synth.momenta("axis")
+    say("case w3 rounds")
+    # 14 splits: partials 10838016 bytes, images 180224 bytes per split; an
+    # 11.5 MiB cap leaves room for 6 splits' images, so 3 rounds.
+    full = gpu_block(torch_dev, "bf16x3", L, qs, mom)
+    rounds = gpu_block(torch_dev, "bf16x3", L, qs, mom, workspace_cap=12058624)
+    assert np.array_equal(full, rounds)
+    assert err_max(rounds, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_graph_replays_match_eager(torch_dev, prec):
     """One handle: replay the captured grouped launch several times, with eager
