@@ -9,8 +9,9 @@ workload is 32^3 sites, N_dil = 32 for all three quark fields, 7 momenta
 resident in HBM before timing starts.  All three arithmetic paths are timed;
 the headline value is the BF16x3 split-precision path in blocks/s.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--paths fp64,fp32,bf16x3]
-                       [--no-cpu-baseline] [--calib-copy-mib M]
+Usage: python bench.py [--gpus 1] [--steps K=200] [--warmup W=50] [--paths fp64,fp32,bf16x3]
+                       [--workload headline-32|batched-48|uneven-32|large-64|tiny-12]
+                       [--no-cpu-baseline] [--no-parity] [--no-graph] [--calib-copy-mib M]
 """
 from __future__ import annotations
 
