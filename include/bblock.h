@@ -127,6 +127,17 @@ bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const v
 bblock_status bblock_compute_batch(bblock_t h, const bblock_desc *desc, int32_t n_desc,
                                    const int32_t *mom, int32_t n_mom);
 
+/* Spin-projected blocks (paper, eq. (1): a baryon correlator term is a linear
+ * combination over spin triples of eq. (3) blocks).  Descriptors whose out
+ * pointers are equal form one output; each output is overwritten with
+ *   out = sum_i coef_i * B_i
+ * over its descriptors i, coef_i = coef[2i] + i coef[2i+1] (host, complex128,
+ * finite).  Blocks summed into one output must have one shape (n1, n2, n3).
+ * The sum runs in FP64 in descriptor order (reproducible).  Otherwise as
+ * bblock_compute_batch; the B_i themselves are not written. */
+bblock_status bblock_compute_projected(bblock_t h, const bblock_desc *desc, const double *coef, int32_t n_desc,
+                                       const int32_t *mom, int32_t n_mom);
+
 /* Enable (1) or disable (0) hipGraph capture and replay in bblock_compute_batch
  * and bblock_compute (default: enabled). */
 bblock_status bblock_set_graph(bblock_t h, int32_t enable);

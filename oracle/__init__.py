@@ -12,6 +12,9 @@ build()              compile ``liboracle.so`` with gcc (OpenMP, no fast-math).
 bblock(...)          full block B[p][d1][d2][d3] (eq. (3)).
 bblock_rows(...)     B for a list of (d1, d2) pairs, for sampled checks at
                      sizes where the full block would take minutes.
+bblock_projected(...) the spin-projected sum  sum_i c_i B(q1_i, q2_i, q3_i)
+                     (eq. (1): a correlator term is a linear combination over
+                     spin triples of eq. (3) blocks), and its rows variant.
 max_threads()        OpenMP threads the oracle uses.
 """
 from __future__ import annotations
@@ -103,6 +106,25 @@ def bblock_rows(L: int, q1, q2, q3, mom, rows) -> np.ndarray:
                                     _ptr(rows, ctypes.c_int32), _ptr(out, ctypes.c_double))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
+    return out
+
+
+def bblock_projected(L: int, triples, coef, mom) -> np.ndarray:
+    """sum_i coef[i] * B(triples[i]) in complex128, shape [n_mom, n1, n2, n3]
+    (eq. (1) with the spin sum written as a linear combination of blocks)."""
+    out = None
+    for (q1, q2, q3), c in zip(triples, coef):
+        b = complex(c) * bblock(L, q1, q2, q3, mom)
+        out = b if out is None else out + b
+    return out
+
+
+def bblock_rows_projected(L: int, triples, coef, mom, rows) -> np.ndarray:
+    """The rows variant of bblock_projected: shape [n_mom, n_rows, n3]."""
+    out = None
+    for (q1, q2, q3), c in zip(triples, coef):
+        b = complex(c) * bblock_rows(L, q1, q2, q3, mom, rows)
+        out = b if out is None else out + b
     return out
 
 

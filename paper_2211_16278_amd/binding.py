@@ -24,7 +24,8 @@ STATUS = {0: "BBLOCK_OK", 1: "BBLOCK_EINVAL", 2: "BBLOCK_ENOMEM", 3: "BBLOCK_EHI
           5: "BBLOCK_EUNSUPPORTED"}
 
 # Every symbol include/bblock.h declares.
-EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_batch", "bblock_set_graph", "bblock_tune",
+EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_batch", "bblock_compute_projected",
+           "bblock_set_graph", "bblock_tune",
            "bblock_set_plan", "bblock_get_plan", "bblock_profile", "bblock_profile_read", "bblock_sync",
            "bblock_destroy", "bblock_last_error", "bblock_version")
 
@@ -65,6 +66,8 @@ def load(path: str = LIB_PATH):
         "bblock_create": ([ctypes.POINTER(h), i32, i32, i32, i32, ctypes.c_size_t, vp], ctypes.c_int),
         "bblock_compute": ([h, vp, vp, vp, i32, i32, i32, ip, i32, i32, i32, vp], ctypes.c_int),
         "bblock_compute_batch": ([h, ctypes.POINTER(bblock_desc), i32, ip, i32], ctypes.c_int),
+        "bblock_compute_projected": ([h, ctypes.POINTER(bblock_desc), ctypes.POINTER(ctypes.c_double), i32, ip, i32],
+                                     ctypes.c_int),
         "bblock_set_graph": ([h, i32], ctypes.c_int),
         "bblock_tune": ([h, i32, i32, i32, i32], ctypes.c_int),
         "bblock_set_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
@@ -113,8 +116,7 @@ def bblock_compute(h, Q1, Q2, Q3, n1, n2, n3, mom, t_begin, t_end, B):
                                     _ptr(B)))
 
 
-def bblock_compute_batch(h, descs, mom):
-    """descs: sequence of (q1, q2, q3, out) torch tensors (or bblock_desc)."""
+def _descs(descs):
     arr = (bblock_desc * len(descs))()
     for i, d in enumerate(descs):
         if isinstance(d, bblock_desc):
@@ -123,8 +125,25 @@ def bblock_compute_batch(h, descs, mom):
             q1, q2, q3, out = d
             arr[i] = bblock_desc(_ptr(q1), _ptr(q2), _ptr(q3), q1.shape[-1], q2.shape[-1], q3.shape[-1], 0,
                                  _ptr(out))
+    return arr
+
+
+def bblock_compute_batch(h, descs, mom):
+    """descs: sequence of (q1, q2, q3, out) torch tensors (or bblock_desc)."""
     m, mp = _momenta(mom)
-    _check(h, load().bblock_compute_batch(h, arr, len(descs), mp, m.shape[0]))
+    _check(h, load().bblock_compute_batch(h, _descs(descs), len(descs), mp, m.shape[0]))
+
+
+def bblock_compute_projected(h, descs, coef, mom):
+    """descs as for bblock_compute_batch; coef: one complex coefficient per
+    descriptor.  Descriptors sharing an out tensor are summed into it."""
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.complex128).reshape(-1))
+    if c.shape[0] != len(descs):
+        raise ValueError("one coefficient per descriptor")
+    cr = np.ascontiguousarray(np.stack([c.real, c.imag], axis=1).reshape(-1))
+    m, mp = _momenta(mom)
+    _check(h, load().bblock_compute_projected(h, _descs(descs), cr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              len(descs), mp, m.shape[0]))
 
 
 def bblock_set_graph(h, enable: bool):
@@ -202,6 +221,9 @@ class BaryonBlocks:
 
     def compute_batch(self, descs, mom):
         bblock_compute_batch(self.h, descs, mom)
+
+    def compute_projected(self, descs, coef, mom):
+        bblock_compute_projected(self.h, descs, coef, mom)
 
     def tune(self, n1, n2, n3, n_mom):
         bblock_tune(self.h, n1, n2, n3, n_mom)

@@ -59,7 +59,12 @@ struct SubBatch {
     int max_mn;
     int went_off, n_went;   // W-image entries (precomputed-W kernel)
     int cps_max;            // chunks per split, largest of the sub-batch
+    int cg_off, n_cg;       // spin projection: output groups completed by this sub-batch
+    int cgs_off;            // their start indices (n_cg + 1 entries)
 };
+
+// Device table regions of a batch.
+enum TableRegion { T_BLOCKS, T_TILES, T_LIST, T_MOM, T_WENT, T_CMEM, T_CCOEF, T_CGS, T_CACC, T_COUNT };
 
 }  // namespace
 
@@ -94,7 +99,7 @@ struct bblock_s {
     // graph replay) is issued.
     std::vector<unsigned char> last_key;
     std::vector<SubBatch> last_subs;
-    size_t last_offs[5] = {0, 0, 0, 0, 0};  // blocks, tiles, reduce list, momenta, W-image entries
+    size_t last_offs[T_COUNT] = {};  // device table regions of the last batch
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::array<hipEvent_t, 2>> ev_gemm, ev_reduce, ev_prep;
     std::map<std::vector<long long>, hipGraphExec_t> graphs;
@@ -232,6 +237,7 @@ struct BlockPlan {
     size_t ws_bytes;    // partials, then (precomputed-W kernel) the W images of one round
     int rounds = 1;     // precomputed-W kernel: rounds of spr splits each
     int spr = 0;
+    bool need_part = false;  // partials even for one split (spin projection)
 };
 
 // Sites per split for S splits: a multiple of CHUNK_SITES; the split count
@@ -244,7 +250,8 @@ void set_splits(bblock_t h, BlockPlan &bp, int S)
     bp.d.S = (h->V + sps - 1) / sps;
     bp.d.cps = sps / CHUNK_SITES;
     bp.d.n_nt = bp.g.n_nt;
-    bp.part_bytes = bp.d.S > 1 ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
+    bp.part_bytes = bp.d.S > 1 || bp.need_part ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
+    bp.d.direct = bp.part_bytes == 0;
     bp.ws_bytes = bp.part_bytes;
     bp.rounds = 1;
     bp.spr = bp.d.S;
@@ -348,9 +355,10 @@ hipEvent_t take_event(bblock_t h)
 }
 
 // Launch the kernels of all sub-batches on stream st; tables already uploaded.
-bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_blocks, size_t off_tiles,
-                      size_t off_list, size_t off_mom, size_t off_went, int n_mom, hipStream_t st)
+bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_t *offs, int n_mom, hipStream_t st)
 {
+    const size_t off_blocks = offs[T_BLOCKS], off_tiles = offs[T_TILES], off_list = offs[T_LIST];
+    const size_t off_mom = offs[T_MOM], off_went = offs[T_WENT];
     for (const SubBatch &sb : subs) {
         GemmArgs ga;
         ga.blocks = reinterpret_cast<const BlockDesc *>(h->d_table + off_blocks);
@@ -401,6 +409,26 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_
             HIP_OR_FAIL(h, hipEventRecord(ev[1], st));
             h->ev_gemm.push_back(ev);
         }
+        if (sb.n_cg > 0) {
+            CombineArgs ca;
+            ca.blocks = ga.blocks;
+            ca.list = reinterpret_cast<const int *>(h->d_table + offs[T_CMEM]);
+            ca.coef = reinterpret_cast<const double *>(h->d_table + offs[T_CCOEF]);
+            ca.gstart = reinterpret_cast<const int *>(h->d_table + offs[T_CGS]) + sb.cgs_off;
+            ca.accumulate = reinterpret_cast<const int *>(h->d_table + offs[T_CACC]) + sb.cg_off;
+            ca.n_groups = sb.n_cg;
+            if (h->profiling) {
+                ev = {take_event(h), take_event(h)};
+                if (!ev[0] || !ev[1]) return fail(h, BBLOCK_EHIP, "profiling event creation failed");
+                HIP_OR_FAIL(h, hipEventRecord(ev[0], st));
+            }
+            e = launch_combine(h->prec, ca, sb.max_mn, st);
+            if (e != hipSuccess) return hip_fail(h, e, "launch of the spin-projection combination");
+            if (h->profiling) {
+                HIP_OR_FAIL(h, hipEventRecord(ev[1], st));
+                h->ev_reduce.push_back(ev);
+            }
+        }
         if (sb.n_list > 0) {
             ReduceArgs ra;
             ra.blocks = ga.blocks;
@@ -424,24 +452,24 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, size_t off_
 
 // Launch a planned batch whose tables are on the device: eagerly, or by
 // replaying (capturing on first use) the graph of this batch structure.
-bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, const size_t offs[5], int n_mom)
+bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, const size_t *offs, int n_mom)
 {
-    if (!h->graph_enabled || h->profiling)
-        return enqueue(h, subs, offs[0], offs[1], offs[2], offs[3], offs[4], n_mom, h->stream);
+    if (!h->graph_enabled || h->profiling) return enqueue(h, subs, offs, n_mom, h->stream);
     // Graph signature: everything baked into kernel arguments.
     std::vector<long long> sig;
     sig.push_back(n_mom);
     sig.push_back((long long)(uintptr_t)h->d_table);
     sig.push_back((long long)(uintptr_t)h->d_kidx);
     sig.push_back((long long)(uintptr_t)h->d_ws);
-    for (int k = 0; k < 5; ++k) sig.push_back((long long)offs[k]);
+    for (int k = 0; k < T_COUNT; ++k) sig.push_back((long long)offs[k]);
     for (const SubBatch &sb : subs)
         sig.insert(sig.end(), {sb.first, sb.count, sb.tile_off, sb.n_tiles, sb.list_off, sb.n_list, sb.kernel, sb.nb,
-                               sb.b2, sb.b3, sb.persistent, sb.grid, sb.max_mn, sb.went_off, sb.n_went, sb.cps_max});
+                               sb.b2, sb.b3, sb.persistent, sb.grid, sb.max_mn, sb.went_off, sb.n_went, sb.cps_max,
+                               sb.cg_off, sb.n_cg, sb.cgs_off});
     auto it = h->graphs.find(sig);
     if (it == h->graphs.end()) {
         HIP_OR_FAIL(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        bblock_status st = enqueue(h, subs, offs[0], offs[1], offs[2], offs[3], offs[4], n_mom, h->cap_stream);
+        bblock_status st = enqueue(h, subs, offs, n_mom, h->cap_stream);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
         if (st != BBLOCK_OK) {
@@ -460,7 +488,11 @@ bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, cons
     return BBLOCK_OK;
 }
 
-bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const int32_t *mom, int n_mom)
+// coef == nullptr: every descriptor's block is written to its out.  Else
+// (spin projection) descriptors sharing an out pointer form one output group
+// and out = sum of coef_i * B_i over the group.
+bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const int32_t *mom, int n_mom,
+                        const double *coef = nullptr)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
     if (!desc || n_desc < 1) return fail(h, BBLOCK_EINVAL, "empty batch");
@@ -471,15 +503,41 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         if (st != BBLOCK_OK) return st;
     }
 
+    // Spin projection: output groups by out pointer, in order of first use.
+    std::vector<int> group_of(n_desc, -1);
+    int n_groups = 0;
+    if (coef) {
+        std::map<void *, int> gid;    // out pointer -> group
+        std::vector<int> first;       // group -> its first descriptor
+        for (int i = 0; i < n_desc; ++i) {
+            auto it = gid.find(desc[i].out);
+            if (it == gid.end()) {
+                gid.emplace(desc[i].out, n_groups);
+                first.push_back(i);
+                group_of[i] = n_groups++;
+            } else {
+                const bblock_desc &f = desc[first[it->second]];
+                if (f.n1 != desc[i].n1 || f.n2 != desc[i].n2 || f.n3 != desc[i].n3)
+                    return fail(h, BBLOCK_EINVAL, "desc %d: blocks summed into one output must have one shape", i);
+                group_of[i] = it->second;
+            }
+            if (!std::isfinite(coef[2 * i]) || !std::isfinite(coef[2 * i + 1]))
+                return fail(h, BBLOCK_EINVAL, "desc %d: coefficient is not finite", i);
+        }
+    }
     // A repeat of the previous batch reuses its device tables and schedule.
-    std::vector<unsigned char> key(sizeof(bblock_desc) * n_desc + sizeof(int32_t) * 3 * n_mom + 3 * sizeof(int));
+    const size_t coef_bytes = coef ? sizeof(double) * 2 * n_desc : 0;
+    std::vector<unsigned char> key(sizeof(bblock_desc) * n_desc + sizeof(int32_t) * 3 * n_mom + coef_bytes +
+                                   4 * sizeof(int));
     {
         unsigned char *kp = key.data();
         std::memcpy(kp, desc, sizeof(bblock_desc) * n_desc);
         kp += sizeof(bblock_desc) * n_desc;
         std::memcpy(kp, mom, sizeof(int32_t) * 3 * n_mom);
         kp += sizeof(int32_t) * 3 * n_mom;
-        const int tail[3] = {h->plan_gen, n_mom, n_desc};
+        if (coef) std::memcpy(kp, coef, coef_bytes);
+        kp += coef_bytes;
+        const int tail[4] = {h->plan_gen, n_mom, n_desc, coef ? 1 : 0};
         std::memcpy(kp, tail, sizeof tail);
     }
     if (key == h->last_key && !h->last_subs.empty())
@@ -527,6 +585,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             S = std::max(bp.plan.splits, s_min);
         else
             S = (int)std::max<long>(s_min, (2L * h->num_cu + total_tiles_s1 - 1) / total_tiles_s1);
+        bp.need_part = coef != nullptr;
         set_splits(h, bp, S);
         if (!fixed && bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
         if (bp.plan.kernel == K_W3 && (bp.ws_bytes > h->ws_cap || !w3_offsets_fit(h, bp))) {
@@ -574,6 +633,9 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     std::vector<SubBatch> subs;
     std::vector<int4> tiles, went;
     std::vector<int> list;
+    std::vector<int> cmem, cgs, cacc;    // spin projection: members, group starts, accumulate flags
+    std::vector<double> ccoef;
+    std::vector<char> group_started(n_groups, 0);
     std::vector<size_t> ws_off(descs.size(), 0);
     size_t ws_need = 0;
     bool any_pipelined = false;
@@ -634,12 +696,38 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
                 for (int s = s_lo; s < s_hi; ++s)
                     for (int nt = 0; nt < bp.g.n_nt; ++nt) went.push_back(make_int4(un.d, nt, s, 0));
             }
-            if (bp.d.S > 1 && un.r == bp.rounds - 1) {
+            if (!coef && bp.d.S > 1 && un.r == bp.rounds - 1) {
                 list.push_back(un.d);
                 sb.max_mn = std::max(sb.max_mn, bp.d.M * bp.d.N);
             }
         }
         sb.n_list = (int)list.size() - sb.list_off;
+        if (coef) {
+            // Blocks completed in this sub-batch, grouped by output (groups
+            // in order of first use, members in descriptor order).
+            std::map<int, std::vector<int>> members;  // group -> descriptor indices of last rounds
+            for (size_t v = u0; v < u; ++v) {
+                const Unit &un = units[v];
+                if (un.r == bps[un.b].rounds - 1) members[group_of[un.b]].push_back(v);
+            }
+            sb.cg_off = (int)cacc.size();
+            sb.cgs_off = (int)cgs.size();
+            for (auto &kv : members) {
+                cgs.push_back((int)cmem.size());
+                cacc.push_back(group_started[kv.first] ? 1 : 0);
+                group_started[kv.first] = 1;
+                for (int v : kv.second) {
+                    const Unit &un = units[v];
+                    cmem.push_back(un.d);
+                    ccoef.push_back(coef[2 * un.b]);
+                    ccoef.push_back(coef[2 * un.b + 1]);
+                    sb.max_mn = std::max(sb.max_mn, bps[un.b].d.M * bps[un.b].d.N);
+                }
+            }
+            cgs.push_back((int)cmem.size());
+            sb.n_cg = (int)members.size();
+            if (sb.n_cg > 65535) return fail(h, BBLOCK_EUNSUPPORTED, "more than 65535 outputs in one sub-batch");
+        }
         if (went.size() - sb.went_off > 65535)
             return fail(h, BBLOCK_EUNSUPPORTED, "block %d has more than 65535 (n-tile, split) pairs", units[u0].b);
         sb.n_went = (int)went.size() - sb.went_off;
@@ -690,7 +778,11 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     const size_t off_list = align_up(off_tiles + sizeof(int4) * tiles.size(), 256);
     const size_t off_mom = align_up(off_list + sizeof(int) * std::max<size_t>(1, list.size()), 256);
     const size_t off_went = align_up(off_mom + sizeof(int) * 3 * n_mom, 256);
-    const size_t bytes = align_up(off_went + sizeof(int4) * std::max<size_t>(1, went.size()), 256);
+    const size_t off_cmem = align_up(off_went + sizeof(int4) * std::max<size_t>(1, went.size()), 256);
+    const size_t off_ccoef = align_up(off_cmem + sizeof(int) * std::max<size_t>(1, cmem.size()), 256);
+    const size_t off_cgs = align_up(off_ccoef + sizeof(double) * std::max<size_t>(2, ccoef.size()), 256);
+    const size_t off_cacc = align_up(off_cgs + sizeof(int) * std::max<size_t>(1, cgs.size()), 256);
+    const size_t bytes = align_up(off_cacc + sizeof(int) * std::max<size_t>(1, cacc.size()), 256);
     {
         bblock_status st = ensure_table(h, bytes);
         if (st != BBLOCK_OK) return st;
@@ -702,6 +794,10 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     if (!list.empty()) std::memcpy(hs + off_list, list.data(), sizeof(int) * list.size());
     std::memcpy(hs + off_mom, mom_red.data(), sizeof(int) * 3 * n_mom);
     if (!went.empty()) std::memcpy(hs + off_went, went.data(), sizeof(int4) * went.size());
+    if (!cmem.empty()) std::memcpy(hs + off_cmem, cmem.data(), sizeof(int) * cmem.size());
+    if (!ccoef.empty()) std::memcpy(hs + off_ccoef, ccoef.data(), sizeof(double) * ccoef.size());
+    if (!cgs.empty()) std::memcpy(hs + off_cgs, cgs.data(), sizeof(int) * cgs.size());
+    if (!cacc.empty()) std::memcpy(hs + off_cacc, cacc.data(), sizeof(int) * cacc.size());
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_table, hs, bytes, hipMemcpyHostToDevice, h->stream));
     HIP_OR_FAIL(h, hipEventRecord(h->staging_free, h->stream));
     if (any_pipelined) {
@@ -711,11 +807,15 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
 
     h->last_key = std::move(key);
     h->last_subs = subs;
-    h->last_offs[0] = off_blocks;
-    h->last_offs[1] = off_tiles;
-    h->last_offs[2] = off_list;
-    h->last_offs[3] = off_mom;
-    h->last_offs[4] = off_went;
+    h->last_offs[T_BLOCKS] = off_blocks;
+    h->last_offs[T_TILES] = off_tiles;
+    h->last_offs[T_LIST] = off_list;
+    h->last_offs[T_MOM] = off_mom;
+    h->last_offs[T_WENT] = off_went;
+    h->last_offs[T_CMEM] = off_cmem;
+    h->last_offs[T_CCOEF] = off_ccoef;
+    h->last_offs[T_CGS] = off_cgs;
+    h->last_offs[T_CACC] = off_cacc;
     return launch_planned(h, subs, h->last_offs, n_mom);
 }
 
@@ -853,6 +953,13 @@ bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const v
 bblock_status bblock_compute_batch(bblock_t h, const bblock_desc *desc, int32_t n_desc, const int32_t *mom, int32_t n_mom)
 {
     return run_batch(h, desc, n_desc, mom, n_mom);
+}
+
+bblock_status bblock_compute_projected(bblock_t h, const bblock_desc *desc, const double *coef, int32_t n_desc,
+                                       const int32_t *mom, int32_t n_mom)
+{
+    if (!coef) return fail(h, BBLOCK_EINVAL, "coef is NULL");
+    return run_batch(h, desc, n_desc, mom, n_mom, coef);
 }
 
 bblock_status bblock_set_graph(bblock_t h, int32_t enable)

@@ -22,7 +22,7 @@ constexpr int MAX_L = 256;
 struct BlockDesc {
     const void *q1, *q2, *q3;  // [V][3][n_i] complex (c128 or c64)
     double *out;               // [n_mom][n1][n2][n3] complex128
-    void *ws;                  // split-K partials [S][2][M][N] (float or double), null if S == 1
+    void *ws;                  // split-K partials [S][2][M][N] (float or double), null if direct
     int n1, n2, n3;
     int M, N;                  // M = n1*n2 rows (d1,d2); N = n3*n_mom columns (p,d3)
     int S;                     // number of site splits
@@ -41,7 +41,7 @@ struct BlockDesc {
     int cps;                   // chunks per split
     int n_nt;                  // n-tiles
     int img_s0;
-    int pad;
+    int direct;                // 1: one split, the kernel writes out itself; 0: partials in ws
 };
 
 // Arguments of one grouped GEMM launch.
@@ -67,6 +67,18 @@ struct WImageArgs {
     int n_mom;
     int L, V;
     const double *roots;  // [L] complex128 exp(-2 pi i k / L)
+};
+
+// Combination of blocks into outputs (spin projection): output group g sums
+// c_i * B_i over the members i in [gstart[g], gstart[g+1]) of list, in that
+// order; accumulate[g] = 1 adds to what an earlier launch wrote.
+struct CombineArgs {
+    const BlockDesc *blocks;
+    const int *list;      // member block indices
+    const double *coef;   // [n_list][2] complex coefficient per member
+    const int *gstart;    // [n_groups + 1]
+    const int *accumulate;  // [n_groups]
+    int n_groups;
 };
 
 struct ReduceArgs {
@@ -102,6 +114,7 @@ size_t w3_image_bytes(int nb);
 hipError_t launch_w3_image(int nb, int c64, const WImageArgs &a, int cps_max, hipStream_t st);
 hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
+hipError_t launch_combine(int prec, const CombineArgs &a, int max_mn, hipStream_t st);
 hipError_t prepare_kernels(int lds_bytes);  // dynamic-LDS limit of every contraction kernel
 
 }  // namespace bb

@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(THREADS, 1) bb_gemm(GemmArgs a)
                     const int m = m0 + wave * WR + f * HALF + (row % HALF);
                     const int s = row / HALF;
                     if (m >= bd.M) continue;
-                    if (bd.S == 1) {
+                    if (bd.direct) {
                         bd.out[(((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + s] = (double)acc[f][n][e];
                     } else {
                         typename T::Part *ws = reinterpret_cast<typename T::Part *>(bd.ws);
@@ -453,6 +453,47 @@ __global__ void __launch_bounds__(256) bb_reduce(ReduceArgs a)
         }
         const int p = nu / bd.n3, d3 = nu - p * bd.n3;
         reinterpret_cast<double2 *>(bd.out)[((size_t)p * bd.M + m) * bd.n3 + d3] = make_double2(re, im);
+    }
+}
+
+// ---------------------------------------------------- spin projection ---
+// Output group g (paper, eq. (1): the spin-projected block is a linear
+// combination of baryon blocks): out = sum_i c_i * (sum_s partials_i[s]), in
+// FP64, members in list order and splits in split order, so the result is
+// reproducible; with accumulate[g] set the sum is added to out (the group's
+// earlier members ran in an earlier launch).
+template <class PartT>
+__global__ void __launch_bounds__(256) bb_combine(CombineArgs a)
+{
+    const int g = blockIdx.y;
+    const int i0 = a.gstart[g], i1 = a.gstart[g + 1];
+    const BlockDesc b0 = a.blocks[a.list[i0]];
+    const size_t MN = (size_t)b0.M * b0.N;
+    double2 *out = reinterpret_cast<double2 *>(b0.out);
+    const bool acc = a.accumulate[g] != 0;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < MN; idx += (size_t)gridDim.x * blockDim.x) {
+        const int m = (int)(idx / b0.N), nu = (int)(idx - (size_t)m * b0.N);
+        const int p = nu / b0.n3, d3 = nu - p * b0.n3;
+        const size_t o = ((size_t)p * b0.M + m) * b0.n3 + d3;
+        double re = 0.0, im = 0.0;
+        if (acc) {
+            const double2 v = out[o];
+            re = v.x;
+            im = v.y;
+        }
+        for (int i = i0; i < i1; ++i) {
+            const BlockDesc bd = a.blocks[a.list[i]];
+            const PartT *ws = reinterpret_cast<const PartT *>(bd.ws);
+            double br = 0.0, bi = 0.0;
+            for (int s = 0; s < bd.S; ++s) {
+                br += (double)ws[(size_t)(2 * s) * MN + idx];
+                bi += (double)ws[(size_t)(2 * s + 1) * MN + idx];
+            }
+            const double cr = a.coef[2 * i], ci = a.coef[2 * i + 1];
+            re += cr * br - ci * bi;
+            im += cr * bi + ci * br;
+        }
+        out[o] = make_double2(re, im);
     }
 }
 
@@ -528,6 +569,18 @@ hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t 
         hipLaunchKernelGGL(bb_reduce<double>, dim3(gx, a.n_list), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(bb_reduce<float>, dim3(gx, a.n_list), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int prec, const CombineArgs &a, int max_mn, hipStream_t st)
+{
+    if (a.n_groups <= 0) return hipSuccess;
+    if (a.n_groups > 65535) return hipErrorInvalidValue;
+    const int gx = (int)std::min<long>(1024, ((long)max_mn + 255) / 256);
+    if (prec == FP64)
+        hipLaunchKernelGGL(bb_combine<double>, dim3(gx, a.n_groups), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(bb_combine<float>, dim3(gx, a.n_groups), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
                     const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
                     if (d1 >= bd.n1 || d2 >= bd.n2) continue;
                     const int m = d1 * bd.n2 + d2;
-                    if (bd.S == 1)
+                    if (bd.direct)
                         bd.out[(((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + f] = (double)acc[f][n][e];
                     else
                         reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + f) * bd.M + m) * bd.N + nu] = acc[f][n][e];

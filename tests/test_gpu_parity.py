@@ -215,6 +215,98 @@ def test_precomputed_w_in_rounds_matches(torch_dev):
     assert err_max(rounds, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
 
 
+# ------------------------------------------------------ spin projection
+def _projected_case(torch_dev, prec, L, ns_list, groups, coefs, workload, workspace_cap=0, graph=True):
+    """Blocks i with fields of shape ns_list[i] summed with coefs[i] into output groups[i]."""
+    torch, dev = torch_dev
+    fields_i = [fields(L, ns, workload=workload, t=i) for i, ns in enumerate(ns_list)]
+    mom = synth.momenta("axis")
+    outs = {}
+    for g, ns in zip(groups, ns_list):
+        if g not in outs:
+            outs[g] = torch.empty((len(mom), ns[0], ns[1], ns[2]), dtype=torch.complex128, device=dev)
+    tq = [[torch.from_numpy(q).to(dev) for q in f] for f in fields_i]
+    descs = [(t[0], t[1], t[2], outs[g]) for t, g in zip(tq, groups)]
+    with binding.BaryonBlocks(L, prec=prec, in_dtype="c128", max_ndil=64, workspace_cap=workspace_cap) as bb:
+        bb.set_graph(graph)
+        bb.compute_projected(descs, coefs, mom)
+        bb.compute_projected(descs, coefs, mom)  # a repeat (cached tables, graph replay) overwrites
+        bb.sync()
+    got = {g: o.cpu().numpy() for g, o in outs.items()}
+    refs = {}
+    for g in got:
+        idx = [i for i, gg in enumerate(groups) if gg == g]
+        refs[g] = oracle.bblock_projected(L, [fields_i[i] for i in idx], [coefs[i] for i in idx], mom)
+    return got, refs
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_projected_groups(torch_dev, prec):
+    """Three outputs of 1, 2 and 4 spin-triple terms (eq. (1)), complex
+    coefficients, against the oracle's sum of blocks."""
+    L = 5
+    ns_list = [(19, 21, 23)] * 1 + [(16, 17, 18)] * 2 + [(24, 24, 24)] * 4
+    groups = [0, 1, 1, 2, 2, 2, 2]
+    coefs = [1.0 + 0.0j, 0.5 - 1.0j, -2.0 + 0.25j, 1.0j, -1.0, 0.75 + 0.75j, 0.125 - 3.0j]
+    say("case projected", prec)
+    got, refs = _projected_case(torch_dev, prec, L, ns_list, groups, coefs, workload=120)
+    for g in got:
+        assert err_max(got[g], refs[g]) < TOL[prec], (g, err_max(got[g], refs[g]))
+
+
+def test_projected_single_term_equals_block(torch_dev):
+    """One term with coefficient 1 reproduces the plain block bitwise (same
+    partials, same FP64 split sum)."""
+    torch, dev = torch_dev
+    L, ns = 6, (24, 24, 24)
+    qs = fields(L, ns, workload=121)
+    mom = synth.momenta("axis")
+    say("case projected single term")
+    tq = [torch.from_numpy(q).to(dev) for q in qs]
+    a = torch.empty((len(mom),) + ns, dtype=torch.complex128, device=dev)
+    b = torch.empty_like(a)
+    with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
+        bb.compute_batch([(tq[0], tq[1], tq[2], a)], mom)
+        bb.compute_projected([(tq[0], tq[1], tq[2], b)], [1.0], mom)
+        bb.sync()
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", ("fp32", "bf16x3"))
+def test_projected_group_across_sub_batches(torch_dev, prec):
+    """A workspace that holds one block's partials splits a 4-term output over
+    four sub-batches (the later ones add to the output): bitwise equal to the
+    single-launch result, which sums the terms in the same order."""
+    L = 6
+    ns_list = [(24, 24, 24)] * 4
+    groups = [0, 0, 0, 0]
+    coefs = [1.0 - 0.5j, 2.0, -0.25j, 0.5 + 0.5j]
+    say("case projected sub-batches", prec)
+    full, refs = _projected_case(torch_dev, prec, L, ns_list, groups, coefs, workload=122)
+    # One 24^3-dilution block at 7 momenta: 9 splits of 576 x 168 partials
+    # (7.0 MB) plus its W images (2.4 MB); 12 MiB holds one block, not two.
+    small, _ = _projected_case(torch_dev, prec, L, ns_list, groups, coefs, workload=122, workspace_cap=12 << 20)
+    assert np.array_equal(full[0], small[0])
+    assert err_max(full[0], refs[0]) < TOL[prec]
+
+
+def test_projected_argument_errors(torch_dev):
+    torch, dev = torch_dev
+    L = 4
+    q = [torch.zeros((L ** 3, 3, n), dtype=torch.complex128, device=dev) for n in (4, 4, 4)]
+    q5 = torch.zeros((L ** 3, 3, 5), dtype=torch.complex128, device=dev)
+    out = torch.zeros((1, 4, 4, 4), dtype=torch.complex128, device=dev)
+    mom = [[0, 0, 0]]
+    with binding.BaryonBlocks(L, prec="fp32", in_dtype="c128", max_ndil=8) as bb:
+        with pytest.raises(binding.BBlockError):
+            bb.compute_projected([(q[0], q[1], q[2], out), (q[0], q[1], q5, out)], [1.0, 1.0], mom)
+        with pytest.raises(binding.BBlockError):
+            bb.compute_projected([(q[0], q[1], q[2], out)], [float("nan")], mom)
+        with pytest.raises(ValueError):
+            bb.compute_projected([(q[0], q[1], q[2], out)], [1.0, 2.0], mom)
+        bb.sync()
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_graph_replays_match_eager(torch_dev, prec):
     """One handle: replay the captured grouped launch several times, with eager

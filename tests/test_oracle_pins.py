@@ -102,6 +102,34 @@ def test_bruteforce_einsum_permutation_epsilon():
     _close(oracle.bblock(L, q1, q2, q3, MOM_MIXED), ref)
 
 
+def test_projected_sum_against_stacked_einsum():
+    """eq. (1): the spin-projected block is one einsum over (term, site, colours)
+    with the permutation-parity epsilon -- not the oracle's per-block loop."""
+    L = 3
+    ns = (3, 2, 4)
+    triples = [tuple(_rand(L, n, 20 + 3 * t + i) for i, n in enumerate(ns)) for t in range(3)]
+    coef = np.array([0.5 - 1.25j, 2.0 + 0.0j, -0.75 + 0.5j])
+    q1 = np.stack([t[0] for t in triples])
+    q2 = np.stack([t[1] for t in triples])
+    q3 = np.stack([t[2] for t in triples])
+    ref = np.einsum("t,abc,xp,txai,txbj,txck->pijk", coef, _eps_by_permutations(), _phases(L, MOM_MIXED), q1, q2, q3)
+    _close(oracle.bblock_projected(L, triples, coef, MOM_MIXED), ref)
+    rows = np.array([[0, 1], [2, 0]], dtype=np.int32)
+    sub = oracle.bblock_rows_projected(L, triples, coef, MOM_MIXED, rows)
+    _close(sub, np.stack([ref[:, i, j, :] for i, j in rows], axis=1))
+
+
+def test_projected_exchange_combination():
+    """B(a,b,c) - B(b,a,c) = B(a,b,c) + B(a,b,c) with d1 and d2 exchanged
+    (field exchange flips the epsilon sign): an index-order check of the
+    projected sum."""
+    L, n = 2, 3
+    a, b, c = (_rand(L, n, 40 + i) for i in range(3))
+    got = oracle.bblock_projected(L, [(a, b, c), (b, a, c)], [1.0, -1.0], MOM_MIXED)
+    B = oracle.bblock(L, a, b, c, MOM_MIXED)
+    _close(got, B + np.transpose(B, (0, 2, 1, 3)))
+
+
 def test_single_site_single_column_is_determinant():
     """V = 1, n = 1, p = 0: B is one 3x3 complex determinant."""
     g = synth.rng(901)
