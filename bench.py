@@ -10,7 +10,7 @@ resident in HBM before timing starts.  All three arithmetic paths are timed;
 the headline value is the BF16x3 split-precision path in blocks/s.
 
 Usage: python bench.py [--gpus 1] [--steps K=200] [--warmup W=50] [--paths fp64,fp32,bf16x3]
-                       [--workload headline-32|batched-48|uneven-32|large-64|tiny-12]
+                       [--workload headline-32|batched-48|uneven-32|large-64|tiny-12|projected-32]
                        [--no-cpu-baseline] [--no-parity] [--no-graph] [--calib-copy-mib M]
 """
 from __future__ import annotations
@@ -120,6 +120,16 @@ def batch_workload(torch, dev, name):
                 for (a, b, c) in triples:
                     out = torch.empty((len(mom), n, n, n), dtype=torch.complex128, device=dev)
                     descs.append((lines[0][a], lines[1][b], lines[2][c], out))
+    elif name == "projected-32":
+        # 3 quark lines x 4 spin components per timeslice; the spin-triple
+        # terms of synth.PROJECTION_TERMS summed into 2 outputs per timeslice.
+        n = wl["ndil"]
+        for t in range(T):
+            lines = [device_fields(torch, dev, [(V, 3, n)] * 4, wl["dtype"], 100 * t + ln) for ln in range(3)]
+            fields.append(lines)
+            outs = [torch.empty((len(mom), n, n, n), dtype=torch.complex128, device=dev) for _ in range(2)]
+            for g, (a, b, c), coef in synth.PROJECTION_TERMS:
+                descs.append((lines[0][a], lines[1][b], lines[2][c], outs[g]))
     elif name in ("large-64", "tiny-12", "headline-32"):
         n = wl["ndil"]
         for t in range(T):
@@ -139,7 +149,7 @@ def batch_workload(torch, dev, name):
 def run_batch_workload(args, name):
     """Time a grouped workload: a step is one grouped launch over all its blocks."""
     import torch
-    from paper_2211_16278_amd import binding
+    from paper_2211_16278_amd import binding, synth
     dev = torch.device("cuda:0")
     L, mom, descs, fields, f_gemm, f_alg, wl = batch_workload(torch, dev, name)
     torch.cuda.synchronize()
@@ -149,34 +159,53 @@ def run_batch_workload(args, name):
     for pname in [p for p in args.paths.split(",") if p]:
         bb = binding.BaryonBlocks(L, prec=pname, in_dtype=wl["dtype"], max_ndil=max_n, stream=stream,
                                   workspace_cap=args.workspace_gib << 30)
+        if name == "projected-32":
+            coefs = [c for _, _, c in synth.PROJECTION_TERMS] * wl["T"]
+            step = lambda: bb.compute_projected(descs, coefs, mom)  # noqa: E731
+        else:
+            step = lambda: bb.compute_batch(descs, mom)  # noqa: E731
         for _ in range(args.warmup):
-            bb.compute_batch(descs, mom)
+            step()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
         for _ in range(args.steps):
-            bb.compute_batch(descs, mom)
+            step()
         e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         step_ms = max(e0.elapsed_time(e1), wall * 1e3) / args.steps
         bb.profile(True)
         bb.profile_read()
-        bb.compute_batch(descs, mom)
+        step()
         gemm_ms, red_ms, prep_ms, launches = bb.profile_read()
         bb.profile(False)
         bb.close()
+        err = None
+        if name == "projected-32" and not args.no_parity:
+            # Sampled parity of output 0 of timeslice 0 against the oracle's sum of blocks.
+            import numpy as np
+            import oracle
+            rows = np.array([[0, 0], [31, 31], [7, 19]], dtype=np.int32)
+            terms = [(i, tr) for i, (g, tr, _) in enumerate(synth.PROJECTION_TERMS) if g == 0]
+            host = [[f.cpu().numpy() for f in line] for line in fields[0]]
+            trip = [(host[0][a], host[1][b], host[2][c]) for _, (a, b, c) in terms]
+            ref = oracle.bblock_rows_projected(L, trip, [coefs[i] for i, _ in terms], mom, rows)
+            got = descs[terms[0][0]][3].cpu().numpy()
+            sub = np.stack([got[:, d1, d2, :] for d1, d2 in rows], axis=1)
+            err = float(np.abs(sub - ref).max() / np.abs(ref).max())
         res[pname] = {"blocks_per_s": len(descs) * 1e3 / step_ms, "ms_per_step": step_ms,
                       "tflops_gemm_count": f_gemm / (step_ms * 1e-3) / 1e12,
                       "tflops_paper_count": f_alg / (step_ms * 1e-3) / 1e12,
                       "contraction_kernel_ms_per_step": gemm_ms, "reduce_kernel_ms_per_step": red_ms,
                       "w_image_kernel_ms_per_step": prep_ms,
                       "contraction_launches_per_step": launches,
-                      "mfma_frac": MFMA_PASSES[pname] * f_gemm / (gemm_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname]}
-        print("# %s %-6s %d blocks  %.2f ms/step  %.1f blocks/s  MFMA %.1f%%" % (
-            name, pname, len(descs), step_ms, len(descs) * 1e3 / step_ms, 100 * res[pname]["mfma_frac"]),
-            file=sys.stderr, flush=True)
+                      "mfma_frac": MFMA_PASSES[pname] * f_gemm / (gemm_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname],
+                      "err_max_sampled": err}
+        print("# %s %-6s %d blocks  %.2f ms/step  %.1f blocks/s  MFMA %.1f%%  reduce/combine %.2f ms%s" % (
+            name, pname, len(descs), step_ms, len(descs) * 1e3 / step_ms, 100 * res[pname]["mfma_frac"], red_ms,
+            "  err %.2e" % err if err is not None else ""), file=sys.stderr, flush=True)
     head = "bf16x3" if "bf16x3" in res else next(iter(res))
     rec = {"metric": METRIC, "value": res[head]["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[head]["ms_per_step"],
@@ -222,7 +251,7 @@ def main() -> int:
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a captured hipGraph")
     ap.add_argument("--workload", default="headline-32",
                     help="headline-32 (the benchmark line), or a grouped workload: batched-48, uneven-32, "
-                         "large-64, tiny-12")
+                         "large-64, tiny-12, projected-32 (spin projection)")
     ap.add_argument("--workspace-gib", type=int, default=16)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (counter calibration)")

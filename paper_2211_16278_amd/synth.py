@@ -72,7 +72,16 @@ WORKLOADS = {
     "batched-48": dict(L=48, T=48, ndil=32, momenta="cube", dtype="c64", blocks_per_t=4),
     "uneven-32": dict(L=32, T=16, ndil=(16, 32, 64), momenta="axis", dtype="c64", blocks_per_t=160),
     "large-64": dict(L=64, T=4, ndil=64, momenta="shell4", dtype="c128", blocks_per_t=1),
+    # Spin projection: per timeslice 8 spin-triple blocks summed into 2 outputs.
+    "projected-32": dict(L=32, T=2, ndil=32, momenta="axis", dtype="c128", blocks_per_t=8),
 }
+
+# Spin-projection terms of the projected workload: (output, spin triple,
+# coefficient); synthetic, of the +-1, +-i/2 kind spin projectors produce.
+PROJECTION_TERMS = (
+    (0, (0, 1, 0), 1.0), (0, (1, 0, 0), -1.0), (0, (0, 0, 1), 0.5j), (0, (1, 1, 1), -0.5j),
+    (1, (2, 3, 2), 1.0), (1, (3, 2, 2), -1.0), (1, (2, 2, 3), 0.5), (1, (3, 3, 3), -0.5),
+)
 
 MOMENTUM_SETS = {"zero": momenta_zero, "axis": momenta_axis, "cube": momenta_cube,
                  "shell4": momenta_shell4}
