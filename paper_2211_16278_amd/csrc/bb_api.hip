@@ -30,7 +30,7 @@ thread_local std::string g_create_error;
 
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
-constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2;
+constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3;
 
 struct Plan {
     int kernel = K_GENERIC, nb = 0, splits = 0, persistent = 0, grid = 0;
@@ -166,6 +166,20 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_mt = cdiv(n1, g.b1) * g.n_mt2;
         g.n_nt = cdiv(n_mom, g.bp) * g.n_nt3;
         g.lds = kernel == K_W3 ? w3_lds_bytes(nb, g.b2) : fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
+    } else if (kernel == K_PORD) {
+        // Rows (d1,d2,d3): a block of consecutive (d1,d2) pairs x a d3 block;
+        // columns: 32 nb momenta.
+        g.b3 = pipelined_block(n3);
+        if (h->prec != BF16X3 || g.b3 == 0 || (nb != 1 && nb != 2)) return g;
+        const int pairs = pord_pairs(nb, g.b3);
+        if (pairs <= 0) return g;
+        g.m_tile = pairs * g.b3;
+        g.n_tile = 32 * nb;
+        g.bp = 32 * nb;
+        g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
+        g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
+        g.n_nt = cdiv(n_mom, g.n_tile);
+        g.lds = 32768;  // static, well below the limit
     } else {
         const KernelGeom k = kernel_geom(h->prec, nb, n_mom, h->L);
         if (k.lds_bytes <= 0) return g;
@@ -187,6 +201,19 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
 {
     Plan p;
     Geometry best;
+    // BF16X3 with many momenta: the paper-order kernel (its MFMA work per
+    // (site, row) is 32 momenta per column fragment, the fused GEMM's is 24
+    // flops per momentum; past about a dozen momenta it is the cheaper one).
+    if (h->prec == BF16X3 && n_mom > 12) {
+        const Geometry g = geometry(h, K_PORD, n_mom > 32 ? 2 : 1, n1, n2, n3, n_mom);
+        if (g.lds > 0) {
+            p.kernel = K_PORD;
+            p.nb = g.nb;
+            const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
+            p.splits = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
+            return p;
+        }
+    }
     const int tiled = h->prec == BF16X3 ? K_W3 : K_PIPELINED;
     for (int nb : {7, 4}) {
         const Geometry g = geometry(h, tiled, nb, n1, n2, n3, n_mom);
@@ -271,7 +298,7 @@ void set_splits(bblock_t h, BlockPlan &bp, int S)
 // offsets (plus three chunks of read-ahead).
 bool w3_offsets_fit(bblock_t h, const BlockPlan &bp)
 {
-    const size_t per_site = (size_t)3 * std::max(bp.d.n1, bp.d.n2) * in_bytes(h->in_dtype);
+    const size_t per_site = (size_t)3 * std::max({bp.d.n1, bp.d.n2, bp.d.n3}) * in_bytes(h->in_dtype);
     return (size_t)(bp.d.sps + 4 * CHUNK_SITES) * per_site < ((size_t)1 << 31);
 }
 
@@ -318,6 +345,8 @@ bblock_status ensure_ws(bblock_t h, size_t bytes)
     return BBLOCK_OK;
 }
 
+int kstride_of(bblock_t h) { return (h->V + 3) & ~3; }
+
 // Phase-index table kidx[p][x] = (n_p . x) mod L of one momentum set, built on
 // the device when the set changes (reused across calls, paper Sec. 3).
 // d_mom: the reduced momenta already uploaded to the device.
@@ -325,7 +354,7 @@ bblock_status ensure_kidx(bblock_t h, const std::vector<int> &mom_red, const int
 {
     if (mom_red == h->kidx_mom && h->d_kidx) return BBLOCK_OK;
     const int n_mom = (int)mom_red.size() / 3;
-    const size_t bytes = (size_t)n_mom * h->V;
+    const size_t bytes = (size_t)n_mom * kstride_of(h);
     if (bytes > h->kidx_cap) {
         HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
         clear_graphs(h);
@@ -336,7 +365,7 @@ bblock_status ensure_kidx(bblock_t h, const std::vector<int> &mom_red, const int
             return fail(h, BBLOCK_ENOMEM, "phase table allocation of %zu bytes", bytes);
         h->kidx_cap = bytes;
     }
-    const hipError_t e = launch_phase_index(d_mom, n_mom, h->L, h->d_kidx, h->stream);
+    const hipError_t e = launch_phase_index(d_mom, n_mom, h->L, kstride_of(h), h->d_kidx, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "launch of the phase-index kernel");
     h->kidx_mom = mom_red;
     return BBLOCK_OK;
@@ -372,6 +401,7 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
         ga.in_c64 = h->in_dtype == BBLOCK_C64;
         ga.roots = h->d_roots;
         ga.kidx = h->d_kidx;
+        ga.kstride = kstride_of(h);
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
         if (sb.kernel == K_W3) {
@@ -403,6 +433,7 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
         }
         hipError_t e = sb.kernel == K_PIPELINED ? launch_fast(h->prec, sb.nb, sb.b2, sb.b3, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_W3      ? launch_w3(sb.nb, sb.b2, ga.in_c64, ga, grid, st)
+                       : sb.kernel == K_PORD    ? launch_pord(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                                                 : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
         if (h->profiling) {
@@ -601,6 +632,16 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             set_splits(h, bp, S);
             if (bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
         }
+        if (bp.plan.kernel == K_PORD && !w3_offsets_fit(h, bp)) {
+            if (h->forced.count(k))
+                return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the paper-order plan needs splits of at most 2 GiB of "
+                            "q1/q2/q3", i);
+            bp.plan.kernel = K_GENERIC;
+            bp.plan.nb = 4;
+            bp.g = geometry(h, K_GENERIC, bp.plan.nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
+            if (bp.g.lds < 0) return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
+            set_splits(h, bp, S);
+        }
         if (bp.ws_bytes > h->ws_cap)
             return fail(h, BBLOCK_ENOMEM, "block %d needs %zu workspace bytes, cap is %zu", i, bp.ws_bytes, h->ws_cap);
     }
@@ -653,7 +694,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         sb.b3 = b0.g.b3;
         sb.persistent = b0.plan.persistent;
         sb.grid = b0.plan.grid > 0 ? b0.plan.grid : h->num_cu;
-        any_pipelined |= sb.kernel == K_PIPELINED;
+        any_pipelined |= sb.kernel == K_PIPELINED || sb.kernel == K_PORD;
         size_t used = 0;
         long n_went = 0;
         const size_t u0 = u;
@@ -979,7 +1020,7 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         h->forced.erase(k);
         return BBLOCK_OK;
     }
-    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && plan->kernel != K_W3)
+    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && plan->kernel != K_W3 && plan->kernel != K_PORD)
         return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
@@ -1073,6 +1114,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         const int *opts;
         const int n_opts = nb_options(h->prec, &opts);
         std::vector<std::pair<int, int>> kn;
+        for (int nb : {1, 2}) kn.push_back({K_PORD, nb});
         for (int nb : {7, 4}) kn.push_back({K_W3, nb});
         for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
@@ -1080,7 +1122,8 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         for (auto [kernel, nb] : kn) {
             const Geometry g = geometry(h, kernel, nb, n1, n2, n3, n_mom);
             if (g.lds <= 0) continue;
-            if ((long)g.n_nt * g.n_tile > 2L * std::max(N, 32)) continue;  // mostly padding
+            const long padded = (long)g.n_nt * g.n_tile;  // columns, or momenta for the paper-order kernel
+            if (padded > 2L * std::max(kernel == K_PORD ? n_mom : N, 32)) continue;  // mostly padding
             const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
             const int s_base = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
             for (int sf : {1, 2, 4})

@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
         const bool ph_live = tid < Lt::EPH;
         const bool ph_ok = ph_live && ph_ip < bd.bp && (p0 + ph_ip) < a.n_mom;
         const int ph_dst = ph_live ? Lt::E1 + Lt::E2 + Lt::E3 + tid : Lt::SG + lane;
-        const gptr<unsigned char> kp = (gptr<unsigned char>)(a.kidx + (size_t)(ph_ok ? p0 + ph_ip : 0) * V);
+        const gptr<unsigned char> kp = (gptr<unsigned char>)(a.kidx + (size_t)(ph_ok ? p0 + ph_ip : 0) * a.kstride);
         const gptr<IT> q1p = (gptr<IT>)bd.q1;
         const gptr<IT> q2p = (gptr<IT>)bd.q2;
         const gptr<IT> q3p = (gptr<IT>)bd.q3;

@@ -27,22 +27,22 @@ hipError_t prepare_fast_kernels(int bytes)
 }
 
 // kidx[p][x] = (n_p . x) mod L, x = ix + L (iy + L iz); momenta reduced to [0, L).
-__global__ void bb_phase_index(const int *mom, int n_mom, int L, unsigned char *kidx)
+__global__ void bb_phase_index(const int *mom, int n_mom, int L, int kstride, unsigned char *kidx)
 {
     const int V = L * L * L;
-    const size_t total = (size_t)n_mom * V;
+    const size_t total = (size_t)n_mom * kstride;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const int p = (int)(i / V), x = (int)(i - (size_t)p * V);
+        const int p = (int)(i / kstride), x = (int)(i - (size_t)p * kstride);
         const int ix = x % L, iy = (x / L) % L, iz = x / (L * L);
-        kidx[i] = (unsigned char)((mom[3 * p] * ix + mom[3 * p + 1] * iy + mom[3 * p + 2] * iz) % L);
+        kidx[i] = x < V ? (unsigned char)((mom[3 * p] * ix + mom[3 * p + 1] * iy + mom[3 * p + 2] * iz) % L) : 0;
     }
 }
 
-hipError_t launch_phase_index(const int *mom, int n_mom, int L, unsigned char *kidx, hipStream_t st)
+hipError_t launch_phase_index(const int *mom, int n_mom, int L, int kstride, unsigned char *kidx, hipStream_t st)
 {
-    const size_t total = (size_t)n_mom * L * L * L;
+    const size_t total = (size_t)n_mom * kstride;
     const int grid = (int)std::min<size_t>(4096, (total + 255) / 256);
-    hipLaunchKernelGGL(bb_phase_index, dim3(grid), dim3(256), 0, st, mom, n_mom, L, kidx);
+    hipLaunchKernelGGL(bb_phase_index, dim3(grid), dim3(256), 0, st, mom, n_mom, L, kstride, kidx);
     return hipGetLastError();
 }
 }  // namespace bb

@@ -55,7 +55,8 @@ struct GemmArgs {
     int L, V;
     int in_c64;
     const double *roots; // [L] complex128 exp(-2 pi i k / L)
-    const unsigned char *kidx;  // [n_mom][V] phase index (n_p . x) mod L (pipelined kernel)
+    const unsigned char *kidx;  // [n_mom][kstride] phase index (n_p . x) mod L (pipelined, paper-order)
+    int kstride;                // row stride of kidx: V rounded up to a multiple of 4 (padding reads 0)
 };
 
 // Arguments of the W-image launch of the precomputed-W kernel.
@@ -105,14 +106,21 @@ hipError_t launch_gemm(int prec, int nb, const GemmArgs &a, int grid, hipStream_
 int fast_lds_bytes(int prec, int nb, int b2, int b3, int L);
 hipError_t launch_fast(int prec, int nb, int b2, int b3, int in_c64, const GemmArgs &a, int grid, hipStream_t st);
 hipError_t prepare_fast_kernels(int lds_bytes);
-// kidx[p][x] = (n_p . x) mod L for all sites of one timeslice (momenta already in [0, L)).
-hipError_t launch_phase_index(const int *mom, int n_mom, int L, unsigned char *kidx, hipStream_t st);
+// kidx[p][x] = (n_p . x) mod L for all sites of one timeslice (momenta already
+// in [0, L)), rows of kstride >= V bytes, 0 past V.
+hipError_t launch_phase_index(const int *mom, int n_mom, int L, int kstride, unsigned char *kidx, hipStream_t st);
 // Precomputed-W kernel (BF16X3; d2 blocks of 16 or 32, nb 4 or 7): static
 // LDS bytes (-1 when no instantiation), bytes per W image, launches.
 int w3_lds_bytes(int nb, int b2);
 size_t w3_image_bytes(int nb);
 hipError_t launch_w3_image(int nb, int c64, const WImageArgs &a, int cps_max, hipStream_t st);
 hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipStream_t st);
+// Paper-order kernel (BF16X3; singlet on the VALU, momentum GEMM on MFMA;
+// nb column fragments of 32 momenta, d3 blocks of 16 or 32): (d1,d2) pairs
+// per workgroup (-1 when no instantiation), launch.  Its tiles use
+// BlockDesc.n_mt2 for the number of d3 blocks.
+int pord_pairs(int nb, int b3);
+hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
 hipError_t launch_combine(int prec, const CombineArgs &a, int max_mn, hipStream_t st);
 hipError_t prepare_kernels(int lds_bytes);  // dynamic-LDS limit of every contraction kernel

@@ -1,0 +1,344 @@
+// Paper-order BF16X3 contraction (gfx950): the singlet first, then the
+// momentum projection as a small GEMM (paper, Algorithm 1: the singlet loop
+// forms S(x; d1,d2,d3) = sum_c D_c(x; d1,d2) q3_c(x; d3), and the projection
+// multiplies the singlets by the phases, GEMM with m = (d1,d2,d3), n = momenta,
+// k = sites).
+//
+// Per chunk of 8 sites a workgroup builds the diquark D (Algorithm 1, diquark
+// loop) of its (d1,d2) pairs in LDS and stages q3 of its d3 block; each lane
+// then forms the singlets of its own GEMM row (one (d1,d2,d3)) for the 4
+// sites of its k-group on the VALU, splits them into BF16 hi/lo and feeds
+// them as the A operand of v_mfma_f32_32x32x16_bf16 directly from registers.
+// The B operand is conj(exp(-i p.x)) over the chunk's sites for 32 momenta
+// per column fragment, also built in registers (the phases do not depend on
+// the row).  The MFMA work per (site, row) is 8 x 32 NB real flops x 3
+// (BF16x3) instead of 24 N_mom for the fused GEMM, at the cost of 3 complex
+// multiply-adds and a BF16 split per (site, row) on the VALU; two
+// workgroups per CU let one wave's VALU work run under another's MFMAs.
+//
+// Real embedding on the column side (the B operand is built once per chunk
+// and shared by all row fragments): A = (Re S, Im S) along k; the real part
+// of S ph comes from B = (Re ph, -Im ph), the imaginary part from
+// B = (Im ph, Re ph).
+#include "bb_fast.h"
+
+namespace bb {
+namespace pord {
+
+using fast::bf8_t;
+using fast::cmulf;
+using fast::f16_t;
+using fast::pack_bf16;
+using fast::static_for;
+
+typedef const void __attribute__((address_space(1))) *gvoid;
+
+__device__ __forceinline__ uint32_t split_lo(float a, float b, uint32_t hi)
+{
+    const float ha = __uint_as_float(__builtin_amdgcn_perm(hi, hi, 0x01000c0cu));
+    const float hb = __uint_as_float(hi & 0xffff0000u);
+    return pack_bf16(a - ha, b - hb);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized fields only");
+    struct Words {
+        uint32_t w[sizeof(T) / 4];
+    };
+    Words x = __builtin_bit_cast(Words, v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) x.w[i] = __builtin_amdgcn_readfirstlane(x.w[i]);
+    return __builtin_bit_cast(T, x);
+}
+
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+
+// Tile shape: NB column fragments of 32 momenta; F row fragments of 32 rows
+// per wave (rows = PPF pairs x B3 d3 values); 4 waves.
+template <int NB, int B3>
+struct Shape {
+    static constexpr int F = NB == 1 ? 4 : 2;
+    static constexpr int PPF = 32 / B3;        // (d1,d2) pairs per row fragment
+    static constexpr int NPAIR = 4 * F * PPF;  // pairs per workgroup
+    static constexpr int NCOL = 32 * NB;       // momenta per workgroup
+    static constexpr int ND = NPAIR * CHUNK_SITES;       // diquark items per chunk (one per thread at most)
+    static constexpr int NQ = 3 * CHUNK_SITES * B3;     // staged q3 values per chunk
+    static constexpr int JQ = (NQ + THREADS - 1) / THREADS;
+    static_assert(ND <= THREADS, "one diquark item per thread");
+};
+
+template <int NB, int B3, bool C64>
+__global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
+{
+    using Sh = Shape<NB, B3>;
+    using IT = typename fast::InT<C64>::T;
+    constexpr int F = Sh::F, PPF = Sh::PPF, NPAIR = Sh::NPAIR;
+    constexpr int ESZ = sizeof(IT);
+    // D[pair][site][colour] and q3[site][colour][d3], double-buffered over chunks.
+    __shared__ __align__(16) float2 dtile[2][NPAIR * CHUNK_SITES * 3];
+    __shared__ __align__(16) float2 q3s[2][3 * CHUNK_SITES * B3];
+    __shared__ float2 roots[MAX_L];
+    __shared__ int s_tile;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 5, r = lane & 31;
+    const int V = a.V, L = a.L;
+    for (int k = tid; k < L; k += THREADS) roots[k] = make_float2((float)a.roots[2 * k], (float)a.roots[2 * k + 1]);
+    __syncthreads();
+
+    auto next_tile = [&](int current) -> int {
+        if (a.counter == nullptr) return current < 0 ? (int)blockIdx.x : a.n_tiles;
+        __syncthreads();
+        if (tid == 0) s_tile = atomicAdd(&a.counter[0], 1);
+        __syncthreads();
+        return __builtin_amdgcn_readfirstlane(s_tile);
+    };
+
+    for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
+        const int4 tl = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl.x]);
+        // m-tile = (pair block, d3 block); n_mt2 holds the number of d3 blocks.
+        const int pb = tl.y / bd.n_mt2, d3_0 = (tl.y % bd.n_mt2) * B3;
+        const int m12_0 = pb * NPAIR, M12 = bd.n1 * bd.n2;
+        const int p0 = tl.z * Sh::NCOL;
+        const int xs = tl.w * bd.sps;
+        const int xe = min(V, xs + bd.sps);
+        const int n_chunks = (xe - xs + CHUNK_SITES - 1) / CHUNK_SITES;
+
+        // Buffer resources over this split's sites (out of range -> 0).
+        const int nrec1 = (xe - xs) * 3 * bd.n1 * ESZ, nrec2 = (xe - xs) * 3 * bd.n2 * ESZ;
+        const int nrec3 = (xe - xs) * 3 * bd.n3 * ESZ;
+        const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(reinterpret_cast<const IT *>(bd.q1) + (size_t)xs * 3 * bd.n1), (short)0, nrec1, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rs2 = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(reinterpret_cast<const IT *>(bd.q2) + (size_t)xs * 3 * bd.n2), (short)0, nrec2, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rs3 = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(reinterpret_cast<const IT *>(bd.q3) + (size_t)xs * 3 * bd.n3), (short)0, nrec3, 0x00020000);
+        auto ld = [&](__amdgpu_buffer_rsrc_t rs, uint32_t off) -> IT {
+            if constexpr (C64)
+                return __builtin_bit_cast(IT, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+            else
+                return __builtin_bit_cast(IT, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        };
+
+        // Diquark item of this thread: (pair dp, site dx).
+        const int dp = tid / CHUNK_SITES, dx = tid % CHUNK_SITES;
+        const int m12 = m12_0 + dp;
+        const bool d_ok = tid < Sh::ND && m12 < M12;
+        const int d1 = d_ok ? m12 / bd.n2 : 0, d2 = d_ok ? m12 % bd.n2 : 0;
+        const uint32_t o1 = d_ok ? (uint32_t)((dx * 3 * bd.n1 + d1) * ESZ) : 0x80000000u;
+        const uint32_t o2 = d_ok ? (uint32_t)((dx * 3 * bd.n2 + d2) * ESZ) : 0x80000000u;
+        const uint32_t c1 = (uint32_t)(bd.n1 * ESZ), c2 = (uint32_t)(bd.n2 * ESZ);  // colour strides
+        const uint32_t s1 = 24u * bd.n1 * ESZ, s2 = 24u * bd.n2 * ESZ, s3 = 24u * bd.n3 * ESZ;  // chunk strides
+        // q3 staging slots: element e = tid + 256 j -> (site, colour, d3l).
+        uint32_t o3[Sh::JQ];
+#pragma unroll
+        for (int j = 0; j < Sh::JQ; ++j) {
+            const int e = tid + THREADS * j;
+            const int d3l = e % B3, c = (e / B3) % 3, x = e / (3 * B3);
+            const bool ok = e < Sh::NQ && d3_0 + d3l < bd.n3;
+            o3[j] = ok ? (uint32_t)(((x * 3 + c) * bd.n3 + d3_0 + d3l) * ESZ) : 0x80000000u;
+        }
+
+        // Phase indices of the lane's column: kidx[p][x] of its 4 sites as one
+        // dword (rows padded to 4 bytes; momenta past the set read 0).
+        const __amdgpu_buffer_rsrc_t rsk = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)a.kidx, (short)0, (int)((uint32_t)a.n_mom * (uint32_t)a.kstride), 0x00020000);
+        const int pcol = p0 + r;
+        uint32_t ko[NB];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+            ko[n] = pcol + 32 * n < a.n_mom ? (uint32_t)((pcol + 32 * n) * a.kstride + xs + 4 * g) : 0x80000000u;
+
+        IT u[3], v[3], w[Sh::JQ];
+        uint32_t kw[NB], kn[NB];
+        auto load_chunk = [&](int ci) {
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                kn[n] = __builtin_amdgcn_raw_buffer_load_b32(rsk, ko[n] + (uint32_t)ci * CHUNK_SITES, 0, 0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                u[c] = ld(rs1, o1 + c * c1 + (uint32_t)ci * s1);
+                v[c] = ld(rs2, o2 + c * c2 + (uint32_t)ci * s2);
+            }
+#pragma unroll
+            for (int j = 0; j < Sh::JQ; ++j) w[j] = ld(rs3, o3[j] + (uint32_t)ci * s3);
+        };
+        // D_c = eps_abc q1_a q2_b of the thread's item, and the q3 staging, into buffer b.
+        auto store_chunk = [&](int b) {
+            float2 uf[3], vf[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                uf[c] = make_float2((float)u[c].x, (float)u[c].y);
+                vf[c] = make_float2((float)v[c].x, (float)v[c].y);
+            }
+            if (tid < Sh::ND) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int a_ = (c + 1) % 3, b_ = (c + 2) % 3;  // eps_{a b c} = +1
+                    const float2 t1 = cmulf(uf[a_], vf[b_]), t2 = cmulf(uf[b_], vf[a_]);
+                    *reinterpret_cast<f2v_t *>(&dtile[b][(dp * CHUNK_SITES + dx) * 3 + c]) =
+                        f2v_t{t1.x - t2.x, t1.y - t2.y};
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < Sh::JQ; ++j) {
+                const int e = tid + THREADS * j;
+                if (e < Sh::NQ)
+                    *reinterpret_cast<f2v_t *>(&q3s[b][e]) = f2v_t{(float)w[j].x, (float)w[j].y};
+            }
+        };
+
+
+        f16_t acc[F][NB][2];
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) acc[f][n][s][e] = 0.f;
+
+        load_chunk(0);
+        store_chunk(0);
+#pragma unroll
+        for (int n = 0; n < NB; ++n) kw[n] = kn[n];
+        load_chunk(1);
+        __syncthreads();
+
+        for (int i = 0; i < n_chunks; ++i) {
+            const int b = i & 1;
+            // B operands of the lane's column over its 4 sites: (Re ph, -Im ph)
+            // gives the real part of S ph, (Im ph, Re ph) the imaginary part.
+            uint4 bh[NB][2], bl[NB][2];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                uint32_t h4[2][4], l4[2][4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float2 ph = roots[(kw[n] >> (8 * j)) & 0xffu];
+                    h4[0][j] = pack_bf16(ph.x, -ph.y);
+                    l4[0][j] = split_lo(ph.x, -ph.y, h4[0][j]);
+                    h4[1][j] = pack_bf16(ph.y, ph.x);
+                    l4[1][j] = split_lo(ph.y, ph.x, h4[1][j]);
+                }
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    bh[n][s] = make_uint4(h4[s][0], h4[s][1], h4[s][2], h4[s][3]);
+                    bl[n][s] = make_uint4(l4[s][0], l4[s][1], l4[s][2], l4[s][3]);
+                }
+            }
+            // q3 of the lane's d3 for its 4 sites, reused by all row fragments.
+            const int d3l = r % B3;
+            float2 q[4][3];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const f2v_t t = *reinterpret_cast<const f2v_t *>(&q3s[b][((4 * g + j) * 3 + c) * B3 + d3l]);
+                    q[j][c] = make_float2(t.x, t.y);
+                }
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const int pi = (wave * F + f) * PPF + r / B3;  // pair of the lane's row
+                const float2 *D = &dtile[b][(pi * CHUNK_SITES + 4 * g) * 3];
+                uint32_t sh[4], sl[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float re = 0.f, im = 0.f;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float2 dv = D[j * 3 + c];
+                        re = __builtin_fmaf(dv.x, q[j][c].x, re);
+                        re = __builtin_fmaf(-dv.y, q[j][c].y, re);
+                        im = __builtin_fmaf(dv.x, q[j][c].y, im);
+                        im = __builtin_fmaf(dv.y, q[j][c].x, im);
+                    }
+                    sh[j] = pack_bf16(re, im);
+                    sl[j] = split_lo(re, im, sh[j]);
+                }
+                const bf8_t Ah = __builtin_bit_cast(bf8_t, make_uint4(sh[0], sh[1], sh[2], sh[3]));
+                const bf8_t Al = __builtin_bit_cast(bf8_t, make_uint4(sl[0], sl[1], sl[2], sl[3]));
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const bf8_t Bh = __builtin_bit_cast(bf8_t, bh[n][s]), Bl = __builtin_bit_cast(bf8_t, bl[n][s]);
+                        acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[f][n][s], 0, 0, 0);
+                        acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[f][n][s], 0, 0, 0);
+                        acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[f][n][s], 0, 0, 0);
+                    }
+            }
+            // Next chunk's diquark and q3 into the other buffer; loads two ahead.
+            store_chunk(b ^ 1);
+#pragma unroll
+            for (int n = 0; n < NB; ++n) kw[n] = kn[n];
+            load_chunk(i + 2);
+            __syncthreads();
+        }
+
+        // Epilogue: row (pair, d3), column p; Re/Im fragment s.
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                const int p = pcol + 32 * n;
+                if (p >= a.n_mom) continue;
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int row = 8 * (e >> 2) + 4 * g + (e & 3);
+                        const int pi = (wave * F + f) * PPF + row / B3;
+                        const int m = m12_0 + pi, d3 = d3_0 + row % B3;
+                        if (m >= M12 || d3 >= bd.n3) continue;
+                        if (bd.direct)
+                            bd.out[(((size_t)p * M12 + m) * bd.n3 + d3) * 2 + s] = (double)acc[f][n][s][e];
+                        else
+                            reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + s) * M12 + m) * bd.N + p * bd.n3 + d3] =
+                                acc[f][n][s][e];
+                    }
+            }
+    }
+
+    if (a.counter != nullptr && tid == 0) {
+        __threadfence();
+        if (atomicAdd(&a.counter[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&a.counter[0], 0);
+            atomicExch(&a.counter[1], 0);
+        }
+    }
+}
+
+template <int NB, int B3, bool C64>
+hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
+{
+    contract<NB, B3, C64><<<dim3(grid), dim3(THREADS), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace pord
+
+int pord_pairs(int nb, int b3)
+{
+    if (nb == 1 && b3 == 32) return pord::Shape<1, 32>::NPAIR;
+    if (nb == 1 && b3 == 16) return pord::Shape<1, 16>::NPAIR;
+    if (nb == 2 && b3 == 32) return pord::Shape<2, 32>::NPAIR;
+    if (nb == 2 && b3 == 16) return pord::Shape<2, 16>::NPAIR;
+    return -1;
+}
+
+hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st)
+{
+#define BBP_CASE(NB_, B3_) \
+    if (nb == NB_ && b3 == B3_) return c64 ? pord::run<NB_, B3_, true>(a, grid, st) : pord::run<NB_, B3_, false>(a, grid, st);
+    BBP_CASE(1, 32) BBP_CASE(1, 16) BBP_CASE(2, 32) BBP_CASE(2, 16)
+#undef BBP_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bb

@@ -124,7 +124,7 @@ def _plans(prec):
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
     if prec == "bf16x3":
-        kernels += [(2, 4), (2, 7)]
+        kernels += [(2, 4), (2, 7), (3, 1), (3, 2)]
     for kernel, nb in kernels:
         for splits in (1, 3, 16):
             for persistent in (0, 1):
@@ -183,6 +183,25 @@ def test_precomputed_w_matches_pipelined_bitwise(torch_dev, L, ns, dtype):
         assert np.array_equal(a, b)
         assert np.array_equal(b, c)
     assert err_max(b, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
+
+
+@pytest.mark.parametrize("L,ns,mset,dtype", [(5, (19, 21, 33), "cube", "c128"), (4, (16, 17, 64), "shell4", "c128"),
+                                             (5, (24, 9, 40), "shell4", "c64"), (4, (7, 5, 16), "axis", "c128")])
+def test_paper_order_kernel(torch_dev, L, ns, mset, dtype):
+    """BF16x3 paper-order kernel (singlet on the VALU, momentum GEMM on MFMA)
+    for one and two column fragments and both d3 blocks, ragged pair and d3
+    edges, against the oracle; persistent and one-tile-per-workgroup
+    schedules agree bitwise."""
+    qs = fields(L, ns, workload=115, dtype=np.complex64 if dtype == "c64" else np.complex128)
+    mom = synth.momenta(mset)
+    ref = oracle.bblock(L, *qs, mom)
+    for nb in (1, 2):
+        say("case paper-order", L, ns, mset, dtype, nb)
+        a = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=3, nb=nb, splits=3, persistent=0))
+        b = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype,
+                      plan=dict(kernel=3, nb=nb, splits=3, persistent=1, grid=6))
+        assert np.array_equal(a, b)
+        assert err_max(a, ref) < TOL["bf16x3"], err_max(a, ref)
 
 
 def test_precomputed_w_small_workspace_falls_back(torch_dev):
@@ -382,7 +401,7 @@ def test_tune_then_compute(torch_dev):
     with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
         bb.tune(*ns, len(mom))
         plan = bb.get_plan(*ns, len(mom))
-        assert plan["kernel"] in (0, 1, 2) and plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
+        assert plan["kernel"] in (0, 1, 2, 3) and plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
         out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
         bb.sync()
     assert err_max(out[0].cpu().numpy(), oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
