@@ -34,6 +34,9 @@ PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 def kernel_name(path, plan, n2, n3):
     """Name of the contraction kernel a plan launches (as rocprofv3 lists it)."""
+    if plan["kernel"] == 3:
+        b3 = 32 if n3 >= 32 else 16
+        return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)
     if plan["kernel"] == 2:
         b2 = 32 if n2 >= 32 else 16
         return "bb::w3::contract<%d, %d, false>" % (plan["nb"], b2)
@@ -87,6 +90,15 @@ def device_fields(torch, dev, shape_list, dtype, seed):
         t.normal_(0.0, 0.5 ** 0.5, generator=g)
         out.append(torch.view_as_complex(t))
     return out
+
+
+def mfma_flops(plan, V, n1, n2, n3, n_mom):
+    """Algorithmic flops of one MFMA pass of the formulation a plan runs: the
+    fused GEMM (kernels 0-2, 24 n_mom V n1 n2 n3) or, for the paper-order
+    kernel 3, only the momentum projection (8 n_mom V n1 n2 n3; its singlet
+    runs on the vector unit)."""
+    per = 8.0 if plan["kernel"] == 3 else 24.0
+    return per * n_mom * V * n1 * n2 * n3
 
 
 def batch_workload(torch, dev, name):
@@ -181,6 +193,12 @@ def run_batch_workload(args, name):
         step()
         gemm_ms, red_ms, prep_ms, launches = bb.profile_read()
         bb.profile(False)
+        f_mfma, kernels = 0.0, set()
+        for q1, q2, q3, _ in descs:
+            shp = (q1.shape[-1], q2.shape[-1], q3.shape[-1], len(mom))
+            plan = bb.get_plan(*shp)
+            kernels.add(plan["kernel"])
+            f_mfma += mfma_flops(plan, L ** 3, *shp)
         bb.close()
         err = None
         if name == "projected-32" and not args.no_parity:
@@ -201,10 +219,15 @@ def run_batch_workload(args, name):
                       "contraction_kernel_ms_per_step": gemm_ms, "reduce_kernel_ms_per_step": red_ms,
                       "w_image_kernel_ms_per_step": prep_ms,
                       "contraction_launches_per_step": launches,
-                      "mfma_frac": MFMA_PASSES[pname] * f_gemm / (gemm_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname],
+                      "kernels": sorted(kernels),
+                      "mfma_frac": MFMA_PASSES[pname] * f_mfma / (gemm_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname],
+                      "gemm_equivalent_frac": MFMA_PASSES[pname] * f_gemm / (gemm_ms * 1e-3) / 1e12
+                      / PEAK_TFLOPS[pname],
                       "err_max_sampled": err}
-        print("# %s %-6s %d blocks  %.2f ms/step  %.1f blocks/s  MFMA %.1f%%  reduce/combine %.2f ms%s" % (
-            name, pname, len(descs), step_ms, len(descs) * 1e3 / step_ms, 100 * res[pname]["mfma_frac"], red_ms,
+        print("# %s %-6s %d blocks  %.2f ms/step  %.1f blocks/s  kernels %s  MFMA %.1f%% (fused-GEMM equivalent "
+              "%.1f%%)  reduce/combine %.2f ms%s" % (
+            name, pname, len(descs), step_ms, len(descs) * 1e3 / step_ms, sorted(kernels),
+            100 * res[pname]["mfma_frac"], 100 * res[pname]["gemm_equivalent_frac"], red_ms,
             "  err %.2e" % err if err is not None else ""), file=sys.stderr, flush=True)
     head = "bf16x3" if "bf16x3" in res else next(iter(res))
     rec = {"metric": METRIC, "value": res[head]["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,

@@ -94,7 +94,14 @@ typedef struct {
                                workspace for one image per (column tile,
                                chunk of 8 sites): 45056 bytes (nb 7) or 28672
                                bytes (nb 4); the planner falls back to 1 when
-                               the cap does not allow it. */
+                               the cap does not allow it.
+                            3: paper order (section 3: diquark, singlet,
+                               then the momentum projection): the singlet
+                               S[x][d1 d2 d3] is formed in registers and only
+                               the momentum sum runs as an MFMA product over
+                               sites (BF16X3 only, n3 >= 16; nb 1 or 2 column
+                               fragments of 32 momenta; the default for more
+                               than 12 momenta).  Needs no image workspace. */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device.
