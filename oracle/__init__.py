@@ -16,6 +16,9 @@ bblock_projected(...) the spin-projected sum  sum_i c_i B(q1_i, q2_i, q3_i)
                      (eq. (1): a correlator term is a linear combination over
                      spin triples of eq. (3) blocks), and its rows variant.
 max_threads()        OpenMP threads the oracle uses.
+
+The LapH-subspace steps around eq. (3) -- eq. (2) reconstruction, eq. (4)
+mode triplets and the contraction onto them -- are in ``oracle.modes``.
 """
 from __future__ import annotations
 

@@ -38,6 +38,23 @@ def gaussian_fields(L: int, ns, **kw):
     return [gaussian_field(L, n, role=i, **kw) for i, n in enumerate(ns)]
 
 
+def laplacian_modes(L: int, n_ev: int, *, workload: int = 0, t: int = 0, dtype=np.complex128) -> np.ndarray:
+    """Stand-in for the Laplacian eigenvectors phi^{(l)}_{a x} of one timeslice,
+    laid out [L^3][3][n_ev]: iid complex normal entries scaled by 1/sqrt(3 L^3),
+    so every column has unit norm on average and distinct columns are nearly
+    orthogonal, as eigenvectors are (the real ones need a gauge field)."""
+    phi = gaussian_field(L, n_ev, workload=workload, t=t, role=7) / np.sqrt(3.0 * L ** 3)
+    return phi.astype(dtype)
+
+
+def coefficients(n_q: int, n_dil: int, n_ev: int, *, workload: int = 0, t: int = 0, role: int = 0) -> np.ndarray:
+    """Quark-field coefficients Q^{(d)}_{l} of n_q spin components / quark lines,
+    [n_q][n_dil][n_ev], iid complex normal with unit variance (complex128)."""
+    g = rng(workload, t, 100 + role)
+    s = np.sqrt(0.5)
+    return (g.standard_normal((n_q, n_dil, n_ev)) * s + 1j * g.standard_normal((n_q, n_dil, n_ev)) * s)
+
+
 # ---------------------------------------------------------------- momenta ---
 # Integer momentum vectors n; the physical momentum is p = 2 pi n / L.
 
