@@ -10,7 +10,8 @@ resident in HBM before timing starts.  All three arithmetic paths are timed;
 the headline value is the BF16x3 split-precision path in blocks/s.
 
 Usage: python bench.py [--gpus 1] [--steps K=200] [--warmup W=50] [--paths fp64,fp32,bf16x3]
-                       [--workload headline-32|batched-48|uneven-32|large-64|tiny-12|projected-32]
+                       [--workload headline-32|batched-48|uneven-32|large-64|tiny-12|projected-32|
+                                   reconstruct-32|mode-triplet-32]
                        [--no-cpu-baseline] [--no-parity] [--no-graph] [--calib-copy-mib M]
 """
 from __future__ import annotations
@@ -241,6 +242,109 @@ def run_batch_workload(args, name):
     return 0
 
 
+def run_mode_workload(args, name):
+    """LapH-subspace workloads (Sec. 2 of the paper).
+
+    reconstruct-32: eq. (2) for 12 coefficient sets (3 quark lines x 4 spin
+      components) of N_dil = 32 rows on 128 eigenvectors of a 32^3 timeslice,
+      one FP64 complex GEMM (M = 3V, N = 384, K = 128); a step is one call,
+      the value is reconstructed fields (coefficient sets) per second.
+    mode-triplet-32: the mode triplets of eq. (4) for 64 eigenvectors and
+      7 momenta are built once (BF16X3 block kernels, timed as setup); a step
+      is one contraction of three N_dil = 32 coefficient matrices onto them
+      (three FP64 complex GEMMs), the value is blocks per second."""
+    import numpy as np
+    import torch
+    from paper_2211_16278_amd import binding, synth
+    from oracle import modes
+    dev = torch.device("cuda:0")
+    wl = synth.WORKLOADS[name]
+    L, n_ev, n_dil = wl["L"], wl["n_ev"], wl["ndil"]
+    V = L ** 3
+    stream = torch.cuda.current_stream()
+    bb = binding.BaryonBlocks(L, prec="bf16x3", in_dtype=wl["dtype"], max_ndil=n_ev, stream=stream,
+                              workspace_cap=args.workspace_gib << 30)
+    phi_h = synth.laplacian_modes(L, n_ev, workload=50)
+    phi = torch.from_numpy(phi_h).to(dev)
+    extra, err = {}, None
+    if name == "reconstruct-32":
+        n_q = wl["n_q"]
+        Q_h = synth.coefficients(n_q, n_dil, n_ev, workload=50)
+        Q = torch.from_numpy(Q_h).to(dev)
+        dt = torch.complex64 if wl["dtype"] == "c64" else torch.complex128
+        q = torch.empty((n_q, V, 3, n_dil), dtype=dt, device=dev)
+        step = lambda: bb.reconstruct(phi, Q, out=q)  # noqa: E731
+        flops = 8.0 * 3 * V * n_ev * n_dil * n_q
+        nbytes = 3 * V * n_ev * 16 + n_q * n_dil * n_ev * 16 + q.numel() * q.element_size()
+        units, unit = n_q, "fields/s"
+        kernel = "bb::zg::zgemm<2, 2>"
+    else:
+        mom = synth.momenta(wl["momenta"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = bb.mode_triplets(phi.to(torch.complex64) if wl["dtype"] == "c64" else phi, mom)
+        torch.cuda.synchronize()
+        extra["setup_ms"] = (time.perf_counter() - t0) * 1e3
+        Qs_h = [synth.coefficients(1, n_dil, n_ev, workload=51, role=i)[0] for i in range(3)]
+        Qs = [torch.from_numpy(x).to(dev) for x in Qs_h]
+        B = torch.empty((len(mom), n_dil, n_dil, n_dil), dtype=torch.complex128, device=dev)
+        step = lambda: bb.mode_contract(T, *Qs, out=B)  # noqa: E731
+        n_mom = len(mom)
+        flops = 8.0 * n_mom * (n_dil * n_ev ** 3 + n_dil ** 2 * n_ev ** 2 + n_dil ** 3 * n_ev)
+        nbytes = T.numel() * 16 + 3 * n_dil * n_ev * 16 + B.numel() * 16
+        units, unit = 1, "blocks/s"
+        kernel = "bb::zg::zgemm (3 launches: l1, l2, l3)"
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = max(e0.elapsed_time(e1), wall * 1e3) / args.steps
+    bb.profile(True)
+    bb.profile_read()
+    n_prof = min(args.steps, 50)
+    for _ in range(n_prof):
+        step()
+    gemm_ms, _, _, launches = bb.profile_read()
+    bb.profile(False)
+    k_ms = gemm_ms / n_prof
+    if not args.no_parity:
+        if name == "reconstruct-32":
+            xs = np.array([0, 1, V // 3, V - 1])
+            ref = modes.reconstruct(Q_h, phi_h[xs])
+            got = q[:, torch.from_numpy(xs).to(dev)].cpu().numpy()
+        else:
+            ref = modes.mode_contract(*Qs_h, T.cpu().numpy())
+            got = B.cpu().numpy()
+        err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    bb.close()
+    ach = flops / (k_ms * 1e-3) / 1e12
+    print("# %s  %.3f ms/step  %.1f %s  kernels %.3f ms (%d launches)  FP64 MFMA %.1f TF (%.1f%%)%s%s" % (
+        name, step_ms, units * 1e3 / step_ms, unit, k_ms, launches // n_prof, ach, 100 * ach / PEAK_TFLOPS["fp64"],
+        "  setup %.1f ms" % extra["setup_ms"] if "setup_ms" in extra else "",
+        "  err %.2e" % err if err is not None else ""), file=sys.stderr, flush=True)
+    rec = {"metric": unit.replace("/s", "") + " per second, " + name, "value": units * 1e3 / step_ms, "unit": unit,
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded iid complex normal eigenvector stand-ins and coefficients)",
+           "config": {"workload": name, "L": L, "n_ev": n_ev, "n_dil": n_dil,
+                      **({"n_q": wl["n_q"], "out_dtype": wl["dtype"]} if name == "reconstruct-32"
+                         else {"n_mom": len(mom), "triplet_prec": "bf16x3"})},
+           "roofline": {"bound": "mfma", "kernel": kernel, "achieved": ach, "peak": PEAK_TFLOPS["fp64"],
+                        "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["fp64"], "traffic": None,
+                        "flops_per_step": flops, "algorithmic_bytes_per_step": nbytes,
+                        "hbm_GBps_at_kernel_time": nbytes / (k_ms * 1e-3) / 1e9},
+           "kernel_ms_per_step": k_ms, "err_max_sampled": err, **extra}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def cpu_baseline(L, qs, mom, M, target_s=15.0):
     """The oracle, untuned, on a bounded sample of (d1, d2) rows of one block."""
     import numpy as np
@@ -274,7 +378,8 @@ def main() -> int:
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a captured hipGraph")
     ap.add_argument("--workload", default="headline-32",
                     help="headline-32 (the benchmark line), or a grouped workload: batched-48, uneven-32, "
-                         "large-64, tiny-12, projected-32 (spin projection)")
+                         "large-64, tiny-12, projected-32 (spin projection), or a LapH-subspace workload: "
+                         "reconstruct-32 (eq. (2)), mode-triplet-32 (eq. (4) route)")
     ap.add_argument("--workspace-gib", type=int, default=16)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (counter calibration)")
@@ -284,6 +389,8 @@ def main() -> int:
               "communication; see the design notes). Run with --gpus 1.", file=sys.stderr)
         return 2
 
+    if args.workload in ("reconstruct-32", "mode-triplet-32"):
+        return run_mode_workload(args, args.workload)
     if args.workload != "headline-32":
         return run_batch_workload(args, args.workload)
 

@@ -145,6 +145,51 @@ bblock_status bblock_compute_batch(bblock_t h, const bblock_desc *desc, int32_t 
 bblock_status bblock_compute_projected(bblock_t h, const bblock_desc *desc, const double *coef, int32_t n_desc,
                                        const int32_t *mom, int32_t n_mom);
 
+/* ---- LapH subspace (paper, Sec. 2, eqs. (2) and (4)) ----------------------
+ * The quark fields are combinations of the Laplacian eigenvectors phi^{(l)},
+ * l = 0..n_ev-1, of one timeslice, with per-field coefficients Q.  Two routes
+ * lead to the block of eq. (3): reconstruct the fields (bblock_reconstruct)
+ * and run bblock_compute on them, or precompute the mode triplets of eq. (4)
+ * once (bblock_mode_triplets) and contract each set of coefficients onto
+ * them (bblock_mode_contract).  All three run on the handle's stream and
+ * enqueue nothing when they return an error.  n_ev <= 4096. */
+
+/* Quark-field reconstruction, eq. (2):
+ *   q[i][x][a][d] = sum_l Q[i][d][l] * phi[x][a][l]
+ * for n_q coefficient sets i (spin components, quark lines) in one pass over
+ * the eigenvectors.
+ *   phi  [V][3][n_ev] complex128 device buffer (V = L^3 of the handle)
+ *   Q    [n_q][n_dil][n_ev] complex128 device buffer
+ *   q    [n_q][V][3][n_dil] device buffer in the handle's input dtype
+ *        (complex128, or complex64 rounded from the FP64 sum), overwritten:
+ *        exactly the field layout bblock_compute reads.
+ * Arithmetic: FP64 complex multiply-adds on the matrix cores.  Buffers
+ * 16-byte aligned (q: 8 for complex64).  n_dil * n_q <= 262144. */
+bblock_status bblock_reconstruct(bblock_t h, const void *phi, int32_t n_ev, const void *Q, int32_t n_dil,
+                                 int32_t n_q, void *q);
+
+/* Mode triplets, eq. (4):
+ *   T[p][l1][l2][l3] = sum_x exp(-i p.x) eps_abc phi[x][a][l1] phi[x][b][l2] phi[x][c][l3]
+ * i.e. the block of eq. (3) with all three fields set to the eigenvectors:
+ * phi is a [V][3][n_ev] field in the handle's input dtype, T a
+ * [n_mom][n_ev][n_ev][n_ev] complex128 device buffer (overwritten), computed
+ * in the handle's precision by the block kernels (n_ev <= max_ndil). */
+bblock_status bblock_mode_triplets(bblock_t h, const void *phi, int32_t n_ev, const int32_t *mom, int32_t n_mom,
+                                   void *T);
+
+/* The block from the mode triplets (Sec. 2, after eq. (4)):
+ *   B[p][d1][d2][d3] = sum_{l1 l2 l3} Q1[d1][l1] Q2[d2][l2] Q3[d3][l3] T[p][l1][l2][l3]
+ *   T   [n_mom][n_ev][n_ev][n_ev] complex128 device buffer (bblock_mode_triplets)
+ *   Qi  [n_i][n_ev] complex128 device buffers
+ *   B   [n_mom][n1][n2][n3] complex128 device buffer, overwritten
+ * Three FP64 complex GEMMs on the matrix cores, one per eigenvector index
+ * (l1, then l2, then l3), through handle workspace of
+ * (n1 n_ev^2 + n1 n2 n_ev) * 16 bytes per momentum; momenta go in rounds
+ * when the cap holds fewer (BBLOCK_ENOMEM when it holds not even one).
+ * n_i <= 4096, 1 <= n_mom <= 128, buffers 16-byte aligned. */
+bblock_status bblock_mode_contract(bblock_t h, const void *T, int32_t n_ev, int32_t n_mom, const void *Q1, int32_t n1,
+                                   const void *Q2, int32_t n2, const void *Q3, int32_t n3, void *B);
+
 /* Enable (1) or disable (0) hipGraph capture and replay in bblock_compute_batch
  * and bblock_compute (default: enabled). */
 bblock_status bblock_set_graph(bblock_t h, int32_t enable);
@@ -166,7 +211,9 @@ bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
 
 /* Kernel timing.  While enabled (enable = 1), launches run eagerly (never
  * from a captured graph) and every contraction-kernel, reduction-kernel and
- * W-image launch is bracketed by HIP events recorded on the handle's stream. */
+ * W-image launch is bracketed by HIP events recorded on the handle's stream;
+ * the complex GEMMs of bblock_reconstruct and bblock_mode_contract count as
+ * contraction kernels. */
 bblock_status bblock_profile(bblock_t h, int32_t enable);
 
 /* Synchronises on the last recorded event, then returns the summed

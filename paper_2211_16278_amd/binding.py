@@ -25,6 +25,7 @@ STATUS = {0: "BBLOCK_OK", 1: "BBLOCK_EINVAL", 2: "BBLOCK_ENOMEM", 3: "BBLOCK_EHI
 
 # Every symbol include/bblock.h declares.
 EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_batch", "bblock_compute_projected",
+           "bblock_reconstruct", "bblock_mode_triplets", "bblock_mode_contract",
            "bblock_set_graph", "bblock_tune",
            "bblock_set_plan", "bblock_get_plan", "bblock_profile", "bblock_profile_read", "bblock_sync",
            "bblock_destroy", "bblock_last_error", "bblock_version")
@@ -68,6 +69,9 @@ def load(path: str = LIB_PATH):
         "bblock_compute_batch": ([h, ctypes.POINTER(bblock_desc), i32, ip, i32], ctypes.c_int),
         "bblock_compute_projected": ([h, ctypes.POINTER(bblock_desc), ctypes.POINTER(ctypes.c_double), i32, ip, i32],
                                      ctypes.c_int),
+        "bblock_reconstruct": ([h, vp, i32, vp, i32, i32, vp], ctypes.c_int),
+        "bblock_mode_triplets": ([h, vp, i32, ip, i32, vp], ctypes.c_int),
+        "bblock_mode_contract": ([h, vp, i32, i32, vp, i32, vp, i32, vp, i32, vp], ctypes.c_int),
         "bblock_set_graph": ([h, i32], ctypes.c_int),
         "bblock_tune": ([h, i32, i32, i32, i32], ctypes.c_int),
         "bblock_set_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
@@ -144,6 +148,20 @@ def bblock_compute_projected(h, descs, coef, mom):
     m, mp = _momenta(mom)
     _check(h, load().bblock_compute_projected(h, _descs(descs), cr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                               len(descs), mp, m.shape[0]))
+
+
+def bblock_reconstruct(h, phi, n_ev, Q, n_dil, n_q, q):
+    _check(h, load().bblock_reconstruct(h, _ptr(phi), n_ev, _ptr(Q), n_dil, n_q, _ptr(q)))
+
+
+def bblock_mode_triplets(h, phi, n_ev, mom, T):
+    m, mp = _momenta(mom)
+    _check(h, load().bblock_mode_triplets(h, _ptr(phi), n_ev, mp, m.shape[0], _ptr(T)))
+
+
+def bblock_mode_contract(h, T, n_ev, n_mom, Q1, n1, Q2, n2, Q3, n3, B):
+    _check(h, load().bblock_mode_contract(h, _ptr(T), n_ev, n_mom, _ptr(Q1), n1, _ptr(Q2), n2, _ptr(Q3), n3,
+                                          _ptr(B)))
 
 
 def bblock_set_graph(h, enable: bool):
@@ -224,6 +242,40 @@ class BaryonBlocks:
 
     def compute_projected(self, descs, coef, mom):
         bblock_compute_projected(self.h, descs, coef, mom)
+
+    def reconstruct(self, phi, Q, out=None):
+        """eq. (2): phi [V, 3, n_ev] complex128, Q [n_q, n_dil, n_ev] (or
+        [n_dil, n_ev]) complex128 -> q [n_q, V, 3, n_dil] in the handle's
+        input dtype (without the leading axis for a 2-d Q)."""
+        import torch
+        single = Q.dim() == 2
+        Qs = Q.unsqueeze(0) if single else Q
+        n_q, n_dil, n_ev = Qs.shape
+        if out is None:
+            dt = torch.complex64 if self.in_dtype == "c64" else torch.complex128
+            out = torch.empty((n_q, phi.shape[0], 3, n_dil), dtype=dt, device=phi.device)
+        bblock_reconstruct(self.h, phi, n_ev, Qs, n_dil, n_q, out)
+        return out[0] if single else out
+
+    def mode_triplets(self, phi, mom, out=None):
+        """eq. (4): phi [V, 3, n_ev] in the input dtype -> T [n_mom, n_ev, n_ev, n_ev] complex128."""
+        import torch
+        n_ev = phi.shape[-1]
+        m = np.asarray(mom, dtype=np.int32).reshape(-1, 3)
+        if out is None:
+            out = torch.empty((m.shape[0], n_ev, n_ev, n_ev), dtype=torch.complex128, device=phi.device)
+        bblock_mode_triplets(self.h, phi, n_ev, m, out)
+        return out
+
+    def mode_contract(self, T, Q1, Q2, Q3, out=None):
+        """B [n_mom, n1, n2, n3] = sum Q1 Q2 Q3 T (all complex128)."""
+        import torch
+        n_mom, n_ev = T.shape[0], T.shape[1]
+        if out is None:
+            out = torch.empty((n_mom, Q1.shape[0], Q2.shape[0], Q3.shape[0]), dtype=torch.complex128,
+                              device=T.device)
+        bblock_mode_contract(self.h, T, n_ev, n_mom, Q1, Q1.shape[0], Q2, Q2.shape[0], Q3, Q3.shape[0], out)
+        return out
 
     def tune(self, n1, n2, n3, n_mom):
         bblock_tune(self.h, n1, n2, n3, n_mom)

@@ -1003,6 +1003,155 @@ bblock_status bblock_compute_projected(bblock_t h, const bblock_desc *desc, cons
     return run_batch(h, desc, n_desc, mom, n_mom, coef);
 }
 
+namespace {
+
+// One complex GEMM launch on the handle's stream, event-timed with the
+// contraction kernels when profiling is on.
+bblock_status zgemm_timed(bblock_t h, ZgemmArgs za, const char *what)
+{
+    std::array<hipEvent_t, 2> ev{nullptr, nullptr};
+    if (h->profiling) {
+        ev = {take_event(h), take_event(h)};
+        if (!ev[0] || !ev[1]) return fail(h, BBLOCK_EHIP, "profiling event creation failed");
+        HIP_OR_FAIL(h, hipEventRecord(ev[0], h->stream));
+    }
+    const hipError_t e = launch_zgemm(za, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, what);
+    if (h->profiling) {
+        HIP_OR_FAIL(h, hipEventRecord(ev[1], h->stream));
+        h->ev_gemm.push_back(ev);
+    }
+    return BBLOCK_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+bblock_status bblock_reconstruct(bblock_t h, const void *phi, int32_t n_ev, const void *Q, int32_t n_dil, int32_t n_q,
+                                 void *q)
+{
+    if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
+    if (!phi || !Q || !q) return fail(h, BBLOCK_EINVAL, "null buffer");
+    if (n_ev < 1 || n_ev > MAX_MODES) return fail(h, BBLOCK_EINVAL, "n_ev must be in [1,%d]", MAX_MODES);
+    if (n_dil < 1 || n_q < 1 || (long long)n_dil * n_q > MAX_MODES * 64LL)
+        return fail(h, BBLOCK_EINVAL, "n_dil (%d) and n_q (%d) must be >= 1 with n_dil * n_q <= %d", n_dil, n_q,
+                    MAX_MODES * 64);
+    if (!aligned(phi, 16) || !aligned(Q, 16) || !aligned(q, in_bytes(h->in_dtype)))
+        return fail(h, BBLOCK_EINVAL, "misaligned buffer");
+    ZgemmArgs za{};
+    za.A = static_cast<const double *>(phi);
+    za.a_sm = n_ev;
+    za.a_sk = 1;
+    za.B = static_cast<const double *>(Q);
+    za.b_sk = 1;
+    za.b_sn = n_ev;
+    za.C = q;
+    za.c_sm = n_dil;
+    za.c_sn = 1;
+    za.c_ng = n_dil;
+    za.c_sg = 3LL * h->V * n_dil;
+    za.c_c64 = h->in_dtype == BBLOCK_C64;
+    za.M = 3 * h->V;
+    za.N = n_dil * n_q;
+    za.K = n_ev;
+    za.batch = 1;
+    return zgemm_timed(h, za, "launch of the reconstruction GEMM");
+}
+
+bblock_status bblock_mode_triplets(bblock_t h, const void *phi, int32_t n_ev, const int32_t *mom, int32_t n_mom,
+                                   void *T)
+{
+    if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
+    bblock_desc d{};
+    d.q1 = d.q2 = d.q3 = phi;
+    d.n1 = d.n2 = d.n3 = n_ev;
+    d.out = T;
+    return run_batch(h, &d, 1, mom, n_mom);
+}
+
+bblock_status bblock_mode_contract(bblock_t h, const void *T, int32_t n_ev, int32_t n_mom, const void *Q1, int32_t n1,
+                                   const void *Q2, int32_t n2, const void *Q3, int32_t n3, void *B)
+{
+    if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
+    if (!T || !Q1 || !Q2 || !Q3 || !B) return fail(h, BBLOCK_EINVAL, "null buffer");
+    if (n_ev < 1 || n_ev > MAX_MODES) return fail(h, BBLOCK_EINVAL, "n_ev must be in [1,%d]", MAX_MODES);
+    if (n_mom < 1 || n_mom > MAX_MOM) return fail(h, BBLOCK_EINVAL, "n_mom must be in [1,%d]", MAX_MOM);
+    if (n1 < 1 || n2 < 1 || n3 < 1 || n1 > MAX_MODES || n2 > MAX_MODES || n3 > MAX_MODES)
+        return fail(h, BBLOCK_EINVAL, "dilution sizes (%d,%d,%d) outside [1,%d]", n1, n2, n3, MAX_MODES);
+    if (!aligned(T, 16) || !aligned(Q1, 16) || !aligned(Q2, 16) || !aligned(Q3, 16) || !aligned(B, 16))
+        return fail(h, BBLOCK_EINVAL, "misaligned buffer");
+    // Intermediates per momentum: X1[d1][l2][l3] and X2[d1][d2][l3]; momenta
+    // go in rounds that fit the workspace cap.
+    const size_t e = (size_t)n_ev;
+    const size_t x1 = (size_t)n1 * e * e * 16, x2 = (size_t)n1 * n2 * e * 16;
+    const size_t per_mom = x1 + x2;
+    const int pm = (int)std::min<size_t>((size_t)n_mom, h->ws_cap / per_mom);
+    if (pm < 1) return fail(h, BBLOCK_ENOMEM, "one momentum needs %zu bytes of workspace, cap %zu", per_mom, h->ws_cap);
+    if (bblock_status st = ensure_ws(h, (size_t)pm * per_mom)) return st;
+    double *X1 = static_cast<double *>(h->d_ws);
+    double *X2 = reinterpret_cast<double *>(static_cast<unsigned char *>(h->d_ws) + (size_t)pm * x1);
+    const long long ne = n_ev, ne2 = ne * ne;
+    for (int p0 = 0; p0 < n_mom; p0 += pm) {
+        const int np = std::min(pm, n_mom - p0);
+        ZgemmArgs s1{};  // X1[p][d1][l2 l3] = sum_l1 Q1[d1][l1] T[p][l1][l2 l3]
+        s1.A = static_cast<const double *>(Q1);
+        s1.a_sm = ne;
+        s1.a_sk = 1;
+        s1.B = static_cast<const double *>(T) + 2 * p0 * ne2 * ne;
+        s1.b_sk = ne2;
+        s1.b_sn = 1;
+        s1.b_sb = ne2 * ne;
+        s1.C = X1;
+        s1.c_sm = ne2;
+        s1.c_sn = 1;
+        s1.c_ng = (int)ne2;
+        s1.c_sb = n1 * ne2;
+        s1.M = n1;
+        s1.N = (int)ne2;
+        s1.K = n_ev;
+        s1.batch = np;
+        if (bblock_status st = zgemm_timed(h, s1, "launch of the first mode contraction")) return st;
+        ZgemmArgs s2{};  // X2[p][d1][d2][l3] = sum_l2 Q2[d2][l2] X1[p][d1][l2][l3]
+        s2.A = static_cast<const double *>(Q2);
+        s2.a_sm = ne;
+        s2.a_sk = 1;
+        s2.B = X1;
+        s2.b_sk = ne;
+        s2.b_sn = 1;
+        s2.b_sb = ne2;
+        s2.C = X2;
+        s2.c_sm = ne;
+        s2.c_sn = 1;
+        s2.c_ng = n_ev;
+        s2.c_sb = (long long)n2 * ne;
+        s2.M = n2;
+        s2.N = n_ev;
+        s2.K = n_ev;
+        s2.batch = np * n1;
+        if (bblock_status st = zgemm_timed(h, s2, "launch of the second mode contraction")) return st;
+        ZgemmArgs s3{};  // B[p][d1 d2][d3] = sum_l3 X2[p][d1 d2][l3] Q3[d3][l3]
+        s3.A = X2;
+        s3.a_sm = ne;
+        s3.a_sk = 1;
+        s3.a_sb = (long long)n1 * n2 * ne;
+        s3.B = static_cast<const double *>(Q3);
+        s3.b_sk = 1;
+        s3.b_sn = ne;
+        s3.C = static_cast<unsigned char *>(B) + (size_t)p0 * n1 * n2 * n3 * 16;
+        s3.c_sm = n3;
+        s3.c_sn = 1;
+        s3.c_ng = n3;
+        s3.c_sb = (long long)n1 * n2 * n3;
+        s3.M = n1 * n2;
+        s3.N = n3;
+        s3.K = n_ev;
+        s3.batch = np;
+        if (bblock_status st = zgemm_timed(h, s3, "launch of the third mode contraction")) return st;
+    }
+    return BBLOCK_OK;
+}
+
 bblock_status bblock_set_graph(bblock_t h, int32_t enable)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");

@@ -16,6 +16,7 @@ constexpr int CHUNK_SITES = 8;
 constexpr int CHUNK_KAPPA = 3 * CHUNK_SITES;
 constexpr int THREADS = 256;  // four wave64 per workgroup
 constexpr int MAX_MOM = 128;
+constexpr int MAX_MODES = 4096;  // eigenvectors or coefficient rows of the LapH-subspace entry points
 constexpr int MAX_L = 256;
 
 // One baryon block as the kernels see it (device resident table).
@@ -121,6 +122,22 @@ hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipSt
 // BlockDesc.n_mt2 for the number of d3 blocks.
 int pord_pairs(int nb, int b3);
 hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
+// Strided batched complex double GEMM on the FP64 matrix cores:
+// C[b](m, n) = sum_k A[b](m, k) B[b](k, n).  Strides count complex elements;
+// column n of C lives at (n / c_ng) * c_sg + (n % c_ng) * c_sn.
+struct ZgemmArgs {
+    const double *A;                 // complex128
+    long long a_sm, a_sk, a_sb;
+    const double *B;                 // complex128
+    long long b_sk, b_sn, b_sb;
+    void *C;                         // complex128, or complex64 when c_c64
+    long long c_sm, c_sn, c_sb, c_sg;
+    int c_ng, c_c64;
+    int M, N, K, batch;
+    int tiles_m, tiles_n;            // set by the launcher
+};
+int zgemm_shape(int M, int N);  // 0: 32 x 128 tiles, 1: 64 x 64, 2: 128 x 32
+hipError_t launch_zgemm(const ZgemmArgs &a, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
 hipError_t launch_combine(int prec, const CombineArgs &a, int max_mn, hipStream_t st);
 hipError_t prepare_kernels(int lds_bytes);  // dynamic-LDS limit of every contraction kernel
