@@ -164,7 +164,10 @@ bblock_status bblock_compute_projected(bblock_t h, const bblock_desc *desc, cons
  *        (complex128, or complex64 rounded from the FP64 sum), overwritten:
  *        exactly the field layout bblock_compute reads.
  * Arithmetic: FP64 complex multiply-adds on the matrix cores.  Buffers
- * 16-byte aligned (q: 8 for complex64).  n_dil * n_q <= 262144. */
+ * 16-byte aligned (q: 8 for complex64).  n_dil * n_q <= 262144.
+ * The GEMMs of this entry point and of bblock_mode_contract pick one of six
+ * wave layouts per launch; the environment variable BBLOCK_ZGEMM_LAYOUT=0..5
+ * forces one (for tests). */
 bblock_status bblock_reconstruct(bblock_t h, const void *phi, int32_t n_ev, const void *Q, int32_t n_dil,
                                  int32_t n_q, void *q);
 

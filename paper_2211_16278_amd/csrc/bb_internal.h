@@ -136,7 +136,7 @@ struct ZgemmArgs {
     int M, N, K, batch;
     int tiles_m, tiles_n;            // set by the launcher
 };
-int zgemm_shape(int M, int N);  // 0: 32 x 128 tiles, 1: 64 x 64, 2: 128 x 32
+int zgemm_shape(int M, int N, int K, int batch);  // index of the wave layout a launch uses
 hipError_t launch_zgemm(const ZgemmArgs &a, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
 hipError_t launch_combine(int prec, const CombineArgs &a, int max_mn, hipStream_t st);

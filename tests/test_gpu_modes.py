@@ -138,6 +138,30 @@ def test_mode_contract_matches_oracle(torch_dev, n_ev, n1, n2, n3, n_mom):
     assert e < TOL_GEMM
 
 
+@pytest.mark.parametrize("layout", range(6))
+def test_every_gemm_layout(torch_dev, monkeypatch, layout):
+    """Each wave layout of the complex GEMM (2x2, 1x4, 4x1 output blocks; 1x2 and
+    2x1 with two k-groups; 1x1 with four) on ragged reconstruction and
+    contraction shapes."""
+    monkeypatch.setenv("BBLOCK_ZGEMM_LAYOUT", str(layout))
+    say("case gemm layout", layout)
+    L, n_ev, n_dil, n_q = 5, 37, 23, 3
+    phi = synth.laplacian_modes(L, n_ev, workload=308)
+    Q = synth.coefficients(n_q, n_dil, n_ev, workload=308)
+    n_e2, ns, n_mom = 19, (21, 9, 35), 2
+    g = synth.rng(309)
+    T = g.standard_normal((n_mom, n_e2, n_e2, n_e2)) + 1j * g.standard_normal((n_mom, n_e2, n_e2, n_e2))
+    Qs = [synth.coefficients(1, n, n_e2, workload=309, role=i)[0] for i, n in enumerate(ns)]
+    with binding.BaryonBlocks(L, prec="fp64", in_dtype="c128", max_ndil=8) as bb:
+        q = bb.reconstruct(dev(torch_dev, phi), dev(torch_dev, Q))
+        B = bb.mode_contract(dev(torch_dev, T), *[dev(torch_dev, x) for x in Qs])
+        bb.sync()
+    e1 = err_max(q.cpu().numpy(), modes.reconstruct(Q, phi))
+    e2 = err_max(B.cpu().numpy(), modes.mode_contract(*Qs, T))
+    say("  err_max %.3e %.3e" % (e1, e2))
+    assert e1 < TOL_GEMM and e2 < TOL_GEMM
+
+
 def test_mode_contract_in_momentum_rounds_is_bitwise(torch_dev):
     """A workspace cap that holds one momentum's intermediates gives the same bits."""
     n_ev, ns, n_mom = 20, (6, 7, 5), 5
