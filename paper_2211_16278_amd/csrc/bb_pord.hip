@@ -80,13 +80,24 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
     // D[pair][site][colour] and q3[site][colour][d3], double-buffered over chunks.
     __shared__ __align__(16) float2 dtile[2][NPAIR * CHUNK_SITES * 3];
     __shared__ __align__(16) float2 q3s[2][3 * CHUNK_SITES * B3];
-    __shared__ float2 roots[MAX_L];
+    // Column operands per phase index k: conj(exp(-2 pi i k / L)) split into
+    // BF16 hi/lo, as the four dwords (Re-part hi, Re-part lo, Im-part hi,
+    // Im-part lo) a lane needs for one site: the real output takes
+    // (Re ph, -Im ph), the imaginary one (Im ph, Re ph).
+    __shared__ __align__(16) uint32_t bops[MAX_L][4];
     __shared__ int s_tile;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 5, r = lane & 31;
     const int V = a.V, L = a.L;
-    for (int k = tid; k < L; k += THREADS) roots[k] = make_float2((float)a.roots[2 * k], (float)a.roots[2 * k + 1]);
+    for (int k = tid; k < L; k += THREADS) {
+        const float c = (float)a.roots[2 * k], sn = (float)a.roots[2 * k + 1];
+        const uint32_t hr = pack_bf16(c, -sn), hi = pack_bf16(sn, c);
+        bops[k][0] = hr;
+        bops[k][1] = split_lo(c, -sn, hr);
+        bops[k][2] = hi;
+        bops[k][3] = split_lo(sn, c, hi);
+    }
     __syncthreads();
 
     auto next_tile = [&](int current) -> int {
@@ -217,19 +228,14 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
             uint4 bh[NB][2], bl[NB][2];
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
-                uint32_t h4[2][4], l4[2][4];
+                uint32_t k4[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float2 ph = roots[(kw[n] >> (8 * j)) & 0xffu];
-                    h4[0][j] = pack_bf16(ph.x, -ph.y);
-                    l4[0][j] = split_lo(ph.x, -ph.y, h4[0][j]);
-                    h4[1][j] = pack_bf16(ph.y, ph.x);
-                    l4[1][j] = split_lo(ph.y, ph.x, h4[1][j]);
-                }
+                for (int j = 0; j < 4; ++j) k4[j] = (kw[n] >> (8 * j)) & 0xffu;
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    bh[n][s] = make_uint4(h4[s][0], h4[s][1], h4[s][2], h4[s][3]);
-                    bl[n][s] = make_uint4(l4[s][0], l4[s][1], l4[s][2], l4[s][3]);
+                    bh[n][s] = make_uint4(bops[k4[0]][2 * s], bops[k4[1]][2 * s], bops[k4[2]][2 * s], bops[k4[3]][2 * s]);
+                    bl[n][s] = make_uint4(bops[k4[0]][2 * s + 1], bops[k4[1]][2 * s + 1], bops[k4[2]][2 * s + 1],
+                                          bops[k4[3]][2 * s + 1]);
                 }
             }
             // q3 of the lane's d3 for its 4 sites, reused by all row fragments.
