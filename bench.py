@@ -11,7 +11,7 @@ the headline value is the BF16x3 split-precision path in blocks/s.
 
 Usage: python bench.py [--gpus 1] [--steps K=200] [--warmup W=50] [--paths fp64,fp32,bf16x3]
                        [--workload headline-32|batched-48|uneven-32|large-64|tiny-12|projected-32|
-                                   reconstruct-32|mode-triplet-32]
+                                   reconstruct-32|mode-triplet-32|scaling]
                        [--no-cpu-baseline] [--no-parity] [--no-graph] [--calib-copy-mib M]
 """
 from __future__ import annotations
@@ -351,6 +351,60 @@ def run_mode_workload(args, name):
     return 0
 
 
+def run_scaling(args):
+    """Problem-size scaling (the GPU analogue of the paper's Sec. 4 scan over
+    volume and dilution size): time per block of one timeslice, 7 momenta,
+    complex128 inputs, against N_dil (L = 32) and against L (N_dil = 32).  The
+    cost of eq. (3) is O(V N_dil^3), so time / (V N_dil^3) should be flat once
+    the device is saturated; the value is the largest deviation from the
+    reference point (L = 32, N_dil = 32) over the saturated points."""
+    import torch
+    from paper_2211_16278_amd import binding, synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    mom = synth.momenta("axis")
+    points = [(32, n) for n in (16, 24, 32, 40, 48, 64)] + [(L, 32) for L in (16, 24, 40, 48)]
+    res = {}
+    for pname in [p for p in args.paths.split(",") if p]:
+        rows = []
+        for L, n in points:
+            qs = device_fields(torch, dev, [(L ** 3, 3, n)] * 3, "c128", 7 * L + n)
+            out = torch.empty((1, len(mom), n, n, n), dtype=torch.complex128, device=dev)
+            with binding.BaryonBlocks(L, prec=pname, in_dtype="c128", max_ndil=64, stream=stream) as bb:
+                step = lambda: bb.compute(*qs, mom, out=out)  # noqa: E731
+                for _ in range(max(2, args.warmup // 10)):
+                    step()
+                torch.cuda.synchronize()
+                k = max(5, args.steps // 10)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(k):
+                    step()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / k
+            rows.append({"L": L, "n_dil": n, "ms_per_block": ms, "ns_per_unit": ms * 1e6 / (L ** 3 * n ** 3)})
+            del qs, out
+        ref = next(r["ns_per_unit"] for r in rows if r["L"] == 32 and r["n_dil"] == 32)
+        for r in rows:
+            r["relative"] = r["ns_per_unit"] / ref
+        sat = [r for r in rows if r["L"] >= 24 and r["n_dil"] >= 24]
+        dev_max = max(abs(r["relative"] - 1.0) for r in sat)
+        res[pname] = {"points": rows, "max_deviation_saturated": dev_max}
+        print("# scaling %-6s " % pname + "  ".join("L%d/N%d %.3f" % (r["L"], r["n_dil"], r["relative"]) for r in rows)
+              + "  max dev (L, N_dil >= 24) %.3f" % dev_max, file=sys.stderr, flush=True)
+    head = "bf16x3" if "bf16x3" in res else next(iter(res))
+    rec = {"metric": "max deviation of time/(V N_dil^3) from the 32^3, N_dil=32 point (saturated sizes)",
+           "value": res[head]["max_deviation_saturated"], "unit": "fraction", "n_gpus": 1,
+           "steps": max(5, args.steps // 10), "warmup": max(2, args.warmup // 10), "ms_per_step": None,
+           "higher_is_better": False, "scaling": "problem size", "vs_baseline": None, "dtype": head,
+           "data": "synthetic (seeded iid complex normal quark fields, generated on the device)",
+           "config": {"workload": "scaling: L=32 with N_dil 16..64, N_dil=32 with L 16..48, 7 momenta, c128"},
+           "paths": res}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def cpu_baseline(L, qs, mom, M, target_s=15.0):
     """The oracle, untuned, on a bounded sample of (d1, d2) rows of one block."""
     import numpy as np
@@ -385,7 +439,8 @@ def main() -> int:
     ap.add_argument("--workload", default="headline-32",
                     help="headline-32 (the benchmark line), or a grouped workload: batched-48, uneven-32, "
                          "large-64, tiny-12, projected-32 (spin projection), or a LapH-subspace workload: "
-                         "reconstruct-32 (eq. (2)), mode-triplet-32 (eq. (4) route)")
+                         "reconstruct-32 (eq. (2)), mode-triplet-32 (eq. (4) route), or scaling (time per "
+                         "block against volume and dilution size)")
     ap.add_argument("--workspace-gib", type=int, default=16)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (counter calibration)")
@@ -395,6 +450,8 @@ def main() -> int:
               "communication; see the design notes). Run with --gpus 1.", file=sys.stderr)
         return 2
 
+    if args.workload == "scaling":
+        return run_scaling(args)
     if args.workload in ("reconstruct-32", "mode-triplet-32"):
         return run_mode_workload(args, args.workload)
     if args.workload != "headline-32":

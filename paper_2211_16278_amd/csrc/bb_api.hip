@@ -146,6 +146,35 @@ void clear_graphs(bblock_t h)
 
 int pipelined_block(int n) { return n >= 32 ? 32 : (n >= 16 ? 16 : 0); }
 
+// d2 block of the pipelined kernels (a template size, 16 or 32): the one that
+// pads fewer rows, 32 on a tie; 0 below 16.
+int row_block(int n)
+{
+    if (n < 16) return 0;
+    return cdiv(n, 32) * 32 <= cdiv(n, 16) * 16 ? 32 : 16;
+}
+
+// d2 block of the precomputed-W kernel (8, 16 or 32): the one that pads
+// fewer rows, the larger on a tie; 0 below 8.
+int w3_row_block(int n)
+{
+    if (n < 8) return 0;
+    int best = 0;
+    for (int b : {32, 16, 8})
+        if (best == 0 || cdiv(n, b) * b < cdiv(n, best) * best) best = b;
+    return best;
+}
+
+// d3 block of the precomputed-W kernel.  Its columns (momentum, d3) are
+// packed densely into the n-tile and only the W images and the epilogue read
+// the split, so any block in [16, 32] works: the balanced one,
+// ceil(n3 / ceil(n3 / 32)), pads no d3 column; 0 below 16.
+int w3_col_block(int n)
+{
+    if (n < 16) return 0;
+    return cdiv(n, cdiv(n, 32));
+}
+
 // Geometry of (kernel, nb) for one block shape; lds < 0 when unsupported.
 Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_mom)
 {
@@ -153,9 +182,10 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
     g.kernel = kernel;
     g.nb = nb;
     if (kernel == K_PIPELINED || kernel == K_W3) {
-        g.b2 = pipelined_block(n2);
-        g.b3 = pipelined_block(n3);
-        if (h->prec == FP64 || g.b2 == 0 || g.b3 == 0 || (nb != 4 && nb != 7)) return g;
+        g.b2 = kernel == K_W3 ? w3_row_block(n2) : row_block(n2);
+        g.b3 = kernel == K_W3 ? w3_col_block(n3) : pipelined_block(n3);
+        const bool nb_ok = kernel == K_W3 ? (nb >= 4 && nb <= 7) : (nb == 4 || nb == 7);
+        if (h->prec == FP64 || g.b2 == 0 || g.b3 == 0 || !nb_ok) return g;
         if (kernel == K_W3 && h->prec != BF16X3) return g;
         g.b1 = 128 / g.b2;
         g.m_tile = 128;
@@ -193,6 +223,16 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
     return g;
 }
 
+// Splits that fill the device with whole waves of workgroups: the most that
+// keep tiles x splits within one workgroup per CU (two for the paper-order
+// kernel, which runs two per CU).  Rounding up instead would leave a second,
+// nearly empty wave that doubles the time.
+int fill_splits(bblock_t h, int kernel, long tiles)
+{
+    const long slots = (long)h->num_cu * (kernel == K_PORD ? 2 : 1);
+    return (int)std::max<long>(1, slots / std::max(1L, tiles));
+}
+
 // Default plan of one block shape: the pipelined kernel where it applies
 // (fewest padded columns, then the wider tile), else the generic kernel with
 // the N tile covering the columns in as few tiles as possible; the split
@@ -209,13 +249,12 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
         if (g.lds > 0) {
             p.kernel = K_PORD;
             p.nb = g.nb;
-            const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
-            p.splits = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
+            p.splits = fill_splits(h, K_PORD, (long)g.n_mt * g.n_nt);
             return p;
         }
     }
     const int tiled = h->prec == BF16X3 ? K_W3 : K_PIPELINED;
-    for (int nb : {7, 4}) {
+    for (int nb : {7, 6, 5, 4}) {
         const Geometry g = geometry(h, tiled, nb, n1, n2, n3, n_mom);
         if (g.lds < 0) continue;
         if (best.lds < 0 || (long)g.n_nt * g.n_tile < (long)best.n_nt * best.n_tile) best = g;
@@ -235,8 +274,7 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
     }
     p.kernel = best.kernel;
     p.nb = best.nb;
-    const long tiles = std::max(1L, (long)best.n_mt * best.n_nt);
-    p.splits = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
+    p.splits = fill_splits(h, best.kernel, (long)best.n_mt * best.n_nt);
     return p;
 }
 
@@ -269,6 +307,16 @@ struct BlockPlan {
 
 // Sites per split for S splits: a multiple of CHUNK_SITES; the split count
 // actually used is ceil(V / sps).
+// Tile-decoding fields of a block's descriptor from its plan's geometry
+// (again whenever the plan falls back to another kernel).
+void take_geometry(BlockPlan &bp)
+{
+    bp.d.n_mt2 = bp.g.n_mt2;
+    bp.d.n_nt3 = bp.g.n_nt3;
+    bp.d.bp = bp.g.bp;
+    bp.d.b3 = bp.g.b3;
+}
+
 void set_splits(bblock_t h, BlockPlan &bp, int S)
 {
     S = std::max(1, std::min(S, (h->V + CHUNK_SITES - 1) / CHUNK_SITES));
@@ -597,10 +645,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         bp.d.n3 = d.n3;
         bp.d.M = d.n1 * d.n2;
         bp.d.N = d.n3 * n_mom;
-        bp.d.n_mt2 = bp.g.n_mt2;
-        bp.d.n_nt3 = bp.g.n_nt3;
-        bp.d.bp = bp.g.bp;
-        bp.d.b3 = bp.g.b3;
+        take_geometry(bp);
         total_tiles_s1 += (long)bp.g.n_mt * bp.g.n_nt;
     }
     // Split count: a forced plan fixes it; a single block uses its plan's
@@ -615,7 +660,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         else if (n_desc == 1 && bp.plan.splits > 0)
             S = std::max(bp.plan.splits, s_min);
         else
-            S = (int)std::max<long>(s_min, (2L * h->num_cu + total_tiles_s1 - 1) / total_tiles_s1);
+            S = std::max<int>(s_min, (int)std::max<long>(1, 2L * h->num_cu / std::max(1L, total_tiles_s1)));
         bp.need_part = coef != nullptr;
         set_splits(h, bp, S);
         if (!fixed && bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
@@ -626,9 +671,16 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             if (h->forced.count(k))
                 return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the precomputed-W plan needs %zu workspace bytes "
                             "(cap %zu) and splits of at most 2 GiB of q1/q2", i, bp.ws_bytes, h->ws_cap);
+            // Its column fragments: 7 or 4, whichever pads fewer columns.
             bp.plan.kernel = K_PIPELINED;
-            bp.g = geometry(h, K_PIPELINED, bp.plan.nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
+            bp.g = Geometry{};
+            for (int nb : {7, 4}) {
+                const Geometry g = geometry(h, K_PIPELINED, nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
+                if (g.lds >= 0 && (bp.g.lds < 0 || (long)g.n_nt * g.n_tile < (long)bp.g.n_nt * bp.g.n_tile)) bp.g = g;
+            }
+            bp.plan.nb = bp.g.nb;
             if (bp.g.lds < 0) return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
+            take_geometry(bp);
             set_splits(h, bp, S);
             if (bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
         }
@@ -640,6 +692,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             bp.plan.nb = 4;
             bp.g = geometry(h, K_GENERIC, bp.plan.nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
             if (bp.g.lds < 0) return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
+            take_geometry(bp);
             set_splits(h, bp, S);
         }
         if (bp.ws_bytes > h->ws_cap)
@@ -1180,7 +1233,7 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
     if (p.splits == 0) {
         const Geometry g = geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom);
         const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
-        p.splits = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
+        p.splits = fill_splits(h, p.kernel, tiles);
     }
     h->forced[k] = p;
     return BBLOCK_OK;
@@ -1264,7 +1317,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         const int n_opts = nb_options(h->prec, &opts);
         std::vector<std::pair<int, int>> kn;
         for (int nb : {1, 2}) kn.push_back({K_PORD, nb});
-        for (int nb : {7, 4}) kn.push_back({K_W3, nb});
+        for (int nb : {7, 6, 5, 4}) kn.push_back({K_W3, nb});
         for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
         const int N = n3 * n_mom;
@@ -1274,7 +1327,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
             const long padded = (long)g.n_nt * g.n_tile;  // columns, or momenta for the paper-order kernel
             if (padded > 2L * std::max(kernel == K_PORD ? n_mom : N, 32)) continue;  // mostly padding
             const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
-            const int s_base = (int)std::max<long>(1, (h->num_cu + tiles - 1) / tiles);
+            const int s_base = fill_splits(h, kernel, tiles);
             for (int sf : {1, 2, 4})
                 for (int pers = 0; pers < 2; ++pers)
                     cands.push_back(Plan{kernel, nb, std::max(s_base * sf / 2, 1), pers, pers ? h->num_cu : 0});

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(THREADS) w_image(WImageArgs a)
         }
         q3s[e] = v;
     }
-    for (int e = tid; e < bpm * 8; e += THREADS) {
+    for (int e = tid; e < BPM_MAX * 8; e += THREADS) {  // columns past bp * B3 get zero phases
         const int ip = e >> 3, xa = x0 + (e & 7), p = p0 + ip;
         float2 v = make_float2(0.f, 0.f);
         if (ip < bd.bp && p < a.n_mom && xa < a.V) {
@@ -517,28 +517,41 @@ hipError_t run_image(const WImageArgs &a, int cps_max, hipStream_t st)
 
 }  // namespace w3
 
+// Instantiations: NB = 4..7 column fragments (128..224 columns), B2 = 8, 16
+// or 32 d2 values per m-tile (d1 blocks of 16, 8 or 4).
+#define BBW_FOR_EACH(X) \
+    X(7, 32) X(7, 16) X(7, 8) X(6, 32) X(6, 16) X(6, 8) X(5, 32) X(5, 16) X(5, 8) X(4, 32) X(4, 16) X(4, 8)
+
 int w3_lds_bytes(int nb, int b2)
 {
-    if (nb == 7 && b2 == 32) return (int)w3::CLayout<7, 32>::lds_bytes();
-    if (nb == 7 && b2 == 16) return (int)w3::CLayout<7, 16>::lds_bytes();
-    if (nb == 4 && b2 == 32) return (int)w3::CLayout<4, 32>::lds_bytes();
-    if (nb == 4 && b2 == 16) return (int)w3::CLayout<4, 16>::lds_bytes();
+#define BBW_LDS(NB_, B2_) \
+    if (nb == NB_ && b2 == B2_) return (int)w3::CLayout<NB_, B2_>::lds_bytes();
+    BBW_FOR_EACH(BBW_LDS)
+#undef BBW_LDS
     return -1;
 }
 
 size_t w3_image_bytes(int nb)
 {
-    if (nb == 7) return (size_t)w3::WImg<7>::DW * 4;
-    if (nb == 4) return (size_t)w3::WImg<4>::DW * 4;
-    return 0;
+    switch (nb) {
+    case 7: return (size_t)w3::WImg<7>::DW * 4;
+    case 6: return (size_t)w3::WImg<6>::DW * 4;
+    case 5: return (size_t)w3::WImg<5>::DW * 4;
+    case 4: return (size_t)w3::WImg<4>::DW * 4;
+    default: return 0;
+    }
 }
 
 hipError_t launch_w3_image(int nb, int c64, const WImageArgs &a, int cps_max, hipStream_t st)
 {
     if (a.n_entries < 1 || a.n_entries > 65535 || cps_max < 1) return hipErrorInvalidValue;
-    if (nb == 7) return c64 ? w3::run_image<7, true>(a, cps_max, st) : w3::run_image<7, false>(a, cps_max, st);
-    if (nb == 4) return c64 ? w3::run_image<4, true>(a, cps_max, st) : w3::run_image<4, false>(a, cps_max, st);
-    return hipErrorInvalidValue;
+    switch (nb) {
+    case 7: return c64 ? w3::run_image<7, true>(a, cps_max, st) : w3::run_image<7, false>(a, cps_max, st);
+    case 6: return c64 ? w3::run_image<6, true>(a, cps_max, st) : w3::run_image<6, false>(a, cps_max, st);
+    case 5: return c64 ? w3::run_image<5, true>(a, cps_max, st) : w3::run_image<5, false>(a, cps_max, st);
+    case 4: return c64 ? w3::run_image<4, true>(a, cps_max, st) : w3::run_image<4, false>(a, cps_max, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipStream_t st)
@@ -546,9 +559,10 @@ hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipSt
 #define BBW_CASE(NB_, B2_) \
     if (nb == NB_ && b2 == B2_) \
         return c64 ? w3::run_contract<NB_, B2_, true>(a, grid, st) : w3::run_contract<NB_, B2_, false>(a, grid, st);
-    BBW_CASE(7, 32) BBW_CASE(7, 16) BBW_CASE(4, 32) BBW_CASE(4, 16)
+    BBW_FOR_EACH(BBW_CASE)
 #undef BBW_CASE
     return hipErrorInvalidValue;
 }
+#undef BBW_FOR_EACH
 
 }  // namespace bb

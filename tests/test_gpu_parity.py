@@ -124,7 +124,7 @@ def _plans(prec):
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
     if prec == "bf16x3":
-        kernels += [(2, 4), (2, 7), (3, 1), (3, 2)]
+        kernels += [(2, 4), (2, 5), (2, 6), (2, 7), (3, 1), (3, 2)]
     for kernel, nb in kernels:
         for splits in (1, 3, 16):
             for persistent in (0, 1):
@@ -166,17 +166,20 @@ def test_determinism_graph_persistent(torch_dev, prec):
     assert err_max(a, oracle.bblock(L, *qs, mom)) < TOL[prec]
 
 
-@pytest.mark.parametrize("L,ns,dtype", [(6, (24, 24, 24), "c128"), (5, (19, 40, 23), "c128"), (4, (33, 16, 35), "c64")])
+@pytest.mark.parametrize("L,ns,dtype", [(6, (24, 24, 24), "c128"), (5, (19, 40, 23), "c128"), (4, (33, 16, 35), "c64"),
+                                        (4, (12, 56, 47), "c128")])
 def test_precomputed_w_matches_pipelined_bitwise(torch_dev, L, ns, dtype):
     """BF16x3: the kernel with precomputed W images (plan kernel 2) forms the
     same products in the same order as the kernel that builds W in LDS (plan
-    kernel 1), so the two blocks are bitwise equal; persistent and
-    one-tile-per-workgroup schedules of kernel 2 agree too."""
+    kernel 1), whatever its tile shape (4..7 column fragments; d2 blocks of
+    8, 16 or 32; d3 blocks of any size in [16, 32]), so the blocks are
+    bitwise equal; persistent and one-tile-per-workgroup schedules of kernel
+    2 agree too."""
     qs = fields(L, ns, workload=112, dtype=np.complex64 if dtype == "c64" else np.complex128)
     mom = synth.momenta("cube")
-    for nb in (7, 4):
+    a = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=1, nb=7, splits=3, persistent=0))
+    for nb in (7, 6, 5, 4):
         say("case w3 vs pipelined", L, ns, dtype, nb)
-        a = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=1, nb=nb, splits=3, persistent=0))
         b = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=2, nb=nb, splits=3, persistent=0))
         c = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype,
                       plan=dict(kernel=2, nb=nb, splits=3, persistent=1, grid=5))
@@ -222,16 +225,28 @@ def test_precomputed_w_in_rounds_matches(torch_dev):
     """W images larger than the workspace run in rounds of splits (each round:
     images, then the contraction of its splits; the reduction after the last),
     bitwise equal to the single-round run with the same split count."""
+    torch, dev = torch_dev
     L, ns = 6, (24, 24, 24)
     qs = fields(L, ns, workload=114)
     mom = synth.momenta("axis")
     say("case w3 rounds")
-    # 14 splits: partials 10838016 bytes, images 180224 bytes per split; an
-    # 11.5 MiB cap leaves room for 6 splits' images, so 3 rounds.
-    full = gpu_block(torch_dev, "bf16x3", L, qs, mom)
-    rounds = gpu_block(torch_dev, "bf16x3", L, qs, mom, workspace_cap=12058624)
-    assert np.array_equal(full, rounds)
-    assert err_max(rounds, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
+    # Plan kernel 2, nb 7, 9 splits of 3 chunks: partials 9 * 2 * 576 * 168 * 4
+    # = 6967296 bytes; images (one n-tile: 7 momenta x d3 block 24) 3 * 45056
+    # bytes per split; the cap holds 3 splits' images: 3 rounds.
+    plan = dict(kernel=2, nb=7, splits=9, persistent=0)
+    tq = [torch.from_numpy(np.ascontiguousarray(q)).to(dev) for q in qs]
+    outs, launches = [], []
+    for cap in (0, 6967296 + 3 * 3 * 45056 + 1000):
+        with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=64, workspace_cap=cap) as bb:
+            bb.set_plan(*ns, len(mom), plan)
+            bb.profile(True)
+            out = bb.compute(*tq, mom)
+            launches.append(bb.profile_read()[3])
+            outs.append(out[0].cpu().numpy())
+    say("  contraction launches", launches)
+    assert launches == [1, 3]
+    assert np.array_equal(outs[0], outs[1])
+    assert err_max(outs[1], oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
 
 
 # ------------------------------------------------------ spin projection
@@ -401,7 +416,7 @@ def test_tune_then_compute(torch_dev):
     with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
         bb.tune(*ns, len(mom))
         plan = bb.get_plan(*ns, len(mom))
-        assert plan["kernel"] in (0, 1, 2, 3) and plan["nb"] in (1, 2, 4, 7) and plan["splits"] >= 1
+        assert plan["kernel"] in (0, 1, 2, 3) and plan["nb"] in (1, 2, 4, 5, 6, 7) and plan["splits"] >= 1
         out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
         bb.sync()
     assert err_max(out[0].cpu().numpy(), oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
