@@ -90,11 +90,12 @@ typedef struct {
                                n2 >= 16 and n3 >= 16; nb 4 or 7);
                             2: as 1 with the phase-weighted q3 precomputed
                                into workspace images by a separate launch
-                               (BF16X3 only; the default there).  Needs
-                               workspace for one image per (column tile,
-                               chunk of 8 sites): 45056 bytes (nb 7) or 28672
-                               bytes (nb 4); the planner falls back to 1 when
-                               the cap does not allow it.
+                               (BF16X3 only; the default there; n2 >= 8,
+                               n3 >= 16; nb 4 to 7).  Needs workspace for
+                               one image per (column tile, chunk of 8
+                               sites): 28672, 32768, 40960 or 45056 bytes
+                               for nb 4, 5, 6, 7; the planner falls back to
+                               1 when the cap does not allow it.
                             3: paper order (section 3: diquark, singlet,
                                then the momentum projection): the singlet
                                S[x][d1 d2 d3] is formed in registers and only
