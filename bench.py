@@ -17,6 +17,7 @@ Usage: python bench.py [--gpus 1] [--steps K=200] [--warmup W=50] [--paths fp64,
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -59,6 +60,21 @@ def flops(V, n1, n2, n3, n_mom):
 # Sources of the translation unit that holds the headline's dominant kernel
 # (the precomputed-W BF16X3 contraction and its W-image kernel).
 DOMINANT_SOURCES = ("bb_w3.hip", "bb_fast.h", "bb_internal.h")
+
+
+class no_gc:
+    """Python's cyclic garbage collector paused over a timed region: a full
+    collection in a process holding torch takes milliseconds, long enough to
+    drain the GPU queue between two launches."""
+
+    def __enter__(self):
+        gc.collect()
+        self.was = gc.isenabled()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        if self.was:
+            gc.enable()
 
 
 def kernel_source_sha(files=DOMINANT_SOURCES) -> str:
@@ -186,14 +202,15 @@ def run_batch_workload(args, name):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with no_gc():
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            for _ in range(args.steps):
+                step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         step_ms = max(e0.elapsed_time(e1), wall * 1e3) / args.steps
         bb.profile(True)
         bb.profile_read()
@@ -303,14 +320,15 @@ def run_mode_workload(args, name):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with no_gc():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     step_ms = max(e0.elapsed_time(e1), wall * 1e3) / args.steps
     bb.profile(True)
     bb.profile_read()
@@ -376,12 +394,13 @@ def run_scaling(args):
                     step()
                 torch.cuda.synchronize()
                 k = max(5, args.steps // 10)
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(k):
-                    step()
-                e1.record(stream)
-                torch.cuda.synchronize()
+                with no_gc():
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(k):
+                        step()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1) / k
             rows.append({"L": L, "n_dil": n, "ms_per_block": ms, "ns_per_unit": ms * 1e6 / (L ** 3 * n ** 3)})
             del qs, out
@@ -495,14 +514,15 @@ def main() -> int:
         for _ in range(args.warmup):
             bb.compute(*tq, mom, out=out)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            bb.compute(*tq, mom, out=out)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        with no_gc():
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            for _ in range(args.steps):
+                bb.compute(*tq, mom, out=out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
         # Per-kernel durations: HIP events around each launch on the library's stream.
         bb.profile(True)

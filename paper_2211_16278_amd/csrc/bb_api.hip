@@ -223,14 +223,24 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
     return g;
 }
 
-// Splits that fill the device with whole waves of workgroups: the most that
-// keep tiles x splits within one workgroup per CU (two for the paper-order
-// kernel, which runs two per CU).  Rounding up instead would leave a second,
-// nearly empty wave that doubles the time.
-int fill_splits(bblock_t h, int kernel, long tiles)
+// Workgroups of a plan that fit one CU at once: two for the paper-order
+// kernel and for the FP64 generic kernel up to 7 column fragments (registers
+// and LDS allow it, and one workgroup's D/W generation then runs beside the
+// other's MFMAs), one otherwise.
+int wg_per_cu(bblock_t h, const Geometry &g)
 {
-    const long slots = (long)h->num_cu * (kernel == K_PORD ? 2 : 1);
-    return (int)std::max<long>(1, slots / std::max(1L, tiles));
+    if (g.kernel == K_PORD) return 2;
+    if (g.kernel == K_GENERIC && h->prec == FP64 && g.nb <= 7 && 2 * g.lds <= h->lds_max) return 2;
+    return 1;
+}
+
+// Splits that fill the device with whole waves of workgroups: the most that
+// keep tiles x splits within the workgroups the CUs hold at once.  Rounding
+// up instead would leave a second, nearly empty wave that doubles the time.
+int fill_splits(bblock_t h, const Geometry &g)
+{
+    const long slots = (long)h->num_cu * wg_per_cu(h, g);
+    return (int)std::max<long>(1, slots / std::max(1L, (long)g.n_mt * g.n_nt));
 }
 
 // Default plan of one block shape: the pipelined kernel where it applies
@@ -249,7 +259,7 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
         if (g.lds > 0) {
             p.kernel = K_PORD;
             p.nb = g.nb;
-            p.splits = fill_splits(h, K_PORD, (long)g.n_mt * g.n_nt);
+            p.splits = fill_splits(h, g);
             return p;
         }
     }
@@ -263,7 +273,8 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
         const int *opts;
         const int n_opts = nb_options(h->prec, &opts);
         const int frag = kernel_geom(h->prec, opts[0], n_mom, h->L).frag_cols;
-        const int N = n3 * n_mom, max_nb = opts[n_opts - 1];
+        // FP64: at most 7 fragments, so that two workgroups share a CU.
+        const int N = n3 * n_mom, max_nb = h->prec == FP64 ? std::min(7, opts[n_opts - 1]) : opts[n_opts - 1];
         const int n_nt = cdiv(N, max_nb * frag);
         const int want_nb = cdiv(N, n_nt * frag);
         for (int i = n_opts - 1; i >= 0; --i) {
@@ -274,7 +285,7 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
     }
     p.kernel = best.kernel;
     p.nb = best.nb;
-    p.splits = fill_splits(h, best.kernel, (long)best.n_mt * best.n_nt);
+    p.splits = fill_splits(h, best);
     return p;
 }
 
@@ -1231,9 +1242,7 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
                     plan->nb);
     Plan p{plan->kernel, plan->nb, plan->splits, plan->persistent, plan->grid};
     if (p.splits == 0) {
-        const Geometry g = geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom);
-        const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
-        p.splits = fill_splits(h, p.kernel, tiles);
+        p.splits = fill_splits(h, geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom));
     }
     h->forced[k] = p;
     return BBLOCK_OK;
@@ -1326,8 +1335,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
             if (g.lds <= 0) continue;
             const long padded = (long)g.n_nt * g.n_tile;  // columns, or momenta for the paper-order kernel
             if (padded > 2L * std::max(kernel == K_PORD ? n_mom : N, 32)) continue;  // mostly padding
-            const long tiles = std::max(1L, (long)g.n_mt * g.n_nt);
-            const int s_base = fill_splits(h, kernel, tiles);
+            const int s_base = fill_splits(h, g);
             for (int sf : {1, 2, 4})
                 for (int pers = 0; pers < 2; ++pers)
                     cands.push_back(Plan{kernel, nb, std::max(s_base * sf / 2, 1), pers, pers ? h->num_cu : 0});
