@@ -190,9 +190,8 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int a_ = (c + 1) % 3, b_ = (c + 2) % 3;  // eps_{a b c} = +1
-                    const float2 t1 = cmulf(uf[a_], vf[b_]), t2 = cmulf(uf[b_], vf[a_]);
-                    *reinterpret_cast<f2v_t *>(&dtile[b][(dp * CHUNK_SITES + dx) * 3 + c]) =
-                        f2v_t{t1.x - t2.x, t1.y - t2.y};
+                    const float2 d = fast::diqf(uf[a_], uf[b_], vf[a_], vf[b_]);
+                    *reinterpret_cast<f2v_t *>(&dtile[b][(dp * CHUNK_SITES + dx) * 3 + c]) = f2v_t{d.x, d.y};
                 }
             }
 #pragma unroll

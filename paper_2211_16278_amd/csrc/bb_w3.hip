@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
         // Diquark generation of one chunk in 52 sub-steps: for each of the 4
         // sites, one read step (6 staged values) and 12 arithmetic steps (3
         // colours x 4); site x+1 is read one site ahead.
-        float2 u[2][3], v[2][3], t1[3], t2[3];
+        float2 u[2][3], v[2][3], t1[3];
         uint32_t dh[3][4], dl[3][4];
         auto dgen = [&](auto ss, const float2 *sd, uint32_t *dn) {
             constexpr int st = ss;
@@ -320,11 +320,10 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
                     constexpr int a_ = (c + 1) % 3, b_ = (c + 2) % 3;  // eps_{a b c} = +1
                     const float2 *uu = u[x & 1], *vv = v[x & 1];
                     if constexpr (part == 0) {
-                        t1[c] = cmulf(uu[a_], vv[b_]);
+                        t1[c].x = fast::diq_re(uu[a_], uu[b_], vv[a_], vv[b_]);
                     } else if constexpr (part == 1) {
-                        t2[c] = cmulf(uu[b_], vv[a_]);
+                        t1[c].y = fast::diq_im(uu[a_], uu[b_], vv[a_], vv[b_]);
                     } else if constexpr (part == 2) {
-                        t1[c] = make_float2(t1[c].x - t2[c].x, t1[c].y - t2[c].y);
                         dh[c][x] = pack_bf16(t1[c].x, t1[c].y);
                     } else {
                         dl[c][x] = split_lo(t1[c].x, t1[c].y, dh[c][x]);
