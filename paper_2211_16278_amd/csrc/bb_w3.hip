@@ -249,10 +249,17 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
         };
         auto qstore = [&](int q, float2 *s) { lds_put(s + sdst[q], (float)rv[q].x, (float)rv[q].y); };
         // Direct-to-LDS copy of round k of image ci into W buffer wbuf.
+        // The image of chunk ci is addressed through a buffer resource built
+        // from scalar values (the image base, uniform per chunk), the wave's
+        // slice by a scalar offset and the lane by one fixed vector offset,
+        // so a copy costs no vector instructions.
+        const int swave = __builtin_amdgcn_readfirstlane(wave);
+        const uint32_t lane_off = (uint32_t)lane * 16u;
         auto wcopy = [&](uint32_t *wbuf, int k, int ci) {
-            const int ro = (k * 4 + wave) * 256;  // u32 offset of this wave's 1 KiB slice of round k
-            __builtin_amdgcn_global_load_lds((gvoid)(img + (size_t)ci * Wi::DW + ro + lane * 4),
-                                             (lvoid)(wbuf + ro), 16, 0, 0);
+            const int ro = (k * 4 + swave) * 256;  // u32 offset of this wave's 1 KiB slice of round k
+            const __amdgpu_buffer_rsrc_t rsi = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(img + (size_t)ci * Wi::DW), (short)0, Wi::DW * 4, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsi, (lvoid)(wbuf + ro), 16, lane_off, (uint32_t)ro * 4u, 0, 0);
         };
 
         // Diquark generation: lane -> (i1, i2, site group of 4).
