@@ -102,7 +102,7 @@ typedef struct {
                                the momentum sum runs as an MFMA product over
                                sites (BF16X3 only, n3 >= 16; nb 1 or 2 column
                                fragments of 32 momenta; the default for more
-                               than 12 momenta).  Needs no image workspace. */
+                               than 16 momenta).  Needs no image workspace. */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device.

@@ -253,8 +253,9 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
     Geometry best;
     // BF16X3 with many momenta: the paper-order kernel (its MFMA work per
     // (site, row) is 32 momenta per column fragment, the fused GEMM's is 24
-    // flops per momentum; past about a dozen momenta it is the cheaper one).
-    if (h->prec == BF16X3 && n_mom > 12) {
+    // flops per momentum; measured at 32^3, N_dil 32 it is the cheaper one
+    // from 17 momenta on).
+    if (h->prec == BF16X3 && n_mom > 16) {
         const Geometry g = geometry(h, K_PORD, n_mom > 32 ? 2 : 1, n1, n2, n3, n_mom);
         if (g.lds > 0) {
             p.kernel = K_PORD;

@@ -447,6 +447,9 @@ __global__ void __launch_bounds__(256) bb_reduce(ReduceArgs a)
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < MN; idx += (size_t)gridDim.x * blockDim.x) {
         const int m = (int)(idx / bd.N), nu = (int)(idx - (size_t)m * bd.N);
         double re = 0.0, im = 0.0;
+        // Unrolled so that the loads of several splits are in flight at once;
+        // the additions stay in split order.
+#pragma unroll 8
         for (int s = 0; s < bd.S; ++s) {
             re += (double)ws[(size_t)(2 * s) * MN + idx];
             im += (double)ws[(size_t)(2 * s + 1) * MN + idx];
