@@ -91,6 +91,30 @@ def test_ragged_shapes_full_block(torch_dev, prec, L, ns, mset):
     assert e < TOL[prec]
 
 
+def _random_momenta(n, seed):
+    g = synth.rng(120, seed)
+    return g.integers(-9, 10, size=(n, 3)).astype(np.int32)  # components past +-L reduce mod L
+
+
+EDGES = [(1, (3, 4, 5), 3), (3, (5, 6, 7), 128), (2, (70, 3, 40), 2), (5, (8, 16, 17), 19)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L,ns,n_mom", EDGES)
+def test_edge_sizes(torch_dev, prec, L, ns, n_mom):
+    """A single site (L = 1), the largest momentum set (128), dilution sizes far
+    apart and past the tiled kernels' minimum, momentum components beyond
+    +-L: every entry against the oracle."""
+    qs = fields(L, ns, workload=121)
+    mom = _random_momenta(n_mom, L)
+    say("case edge", prec, L, ns, n_mom)
+    ref = oracle.bblock(L, *qs, mom)
+    got = gpu_block(torch_dev, prec, L, qs, mom, max_ndil=128)
+    e = err_max(got, ref)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_complex64_inputs(torch_dev, prec):
     L, ns = 6, (20, 24, 28)
