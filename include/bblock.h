@@ -194,6 +194,17 @@ bblock_status bblock_mode_triplets(bblock_t h, const void *phi, int32_t n_ev, co
 bblock_status bblock_mode_contract(bblock_t h, const void *T, int32_t n_ev, int32_t n_mom, const void *Q1, int32_t n1,
                                    const void *Q2, int32_t n2, const void *Q3, int32_t n3, void *B);
 
+/* bblock_mode_contract for n_c coefficient triples at once (the paper's many
+ * noise and spin combinations per timeslice, Sec. 2 after eq. (3)), sharing
+ * T and the shapes: Qi [n_c][n_i][n_ev] complex128, B [n_c][n_mom][n1][n2][n3]
+ * complex128 (block c at B + c n_mom n1 n2 n3).  The triples share each GEMM
+ * launch (the first stacks them into its rows), so a call costs far less
+ * than n_c single ones.  Workspace (n1 n_ev^2 + n1 n2 n_ev) * 16 * n_c bytes
+ * per momentum; 1 <= n_c <= 65536; otherwise as bblock_mode_contract. */
+bblock_status bblock_mode_contract_batch(bblock_t h, const void *T, int32_t n_ev, int32_t n_mom, int32_t n_c,
+                                         const void *Q1, int32_t n1, const void *Q2, int32_t n2, const void *Q3,
+                                         int32_t n3, void *B);
+
 /* Enable (1) or disable (0) hipGraph capture and replay in bblock_compute_batch
  * and bblock_compute (default: enabled). */
 bblock_status bblock_set_graph(bblock_t h, int32_t enable);

@@ -25,7 +25,7 @@ STATUS = {0: "BBLOCK_OK", 1: "BBLOCK_EINVAL", 2: "BBLOCK_ENOMEM", 3: "BBLOCK_EHI
 
 # Every symbol include/bblock.h declares.
 EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_batch", "bblock_compute_projected",
-           "bblock_reconstruct", "bblock_mode_triplets", "bblock_mode_contract",
+           "bblock_reconstruct", "bblock_mode_triplets", "bblock_mode_contract", "bblock_mode_contract_batch",
            "bblock_set_graph", "bblock_tune",
            "bblock_set_plan", "bblock_get_plan", "bblock_profile", "bblock_profile_read", "bblock_sync",
            "bblock_destroy", "bblock_last_error", "bblock_version")
@@ -72,6 +72,7 @@ def load(path: str = LIB_PATH):
         "bblock_reconstruct": ([h, vp, i32, vp, i32, i32, vp], ctypes.c_int),
         "bblock_mode_triplets": ([h, vp, i32, ip, i32, vp], ctypes.c_int),
         "bblock_mode_contract": ([h, vp, i32, i32, vp, i32, vp, i32, vp, i32, vp], ctypes.c_int),
+        "bblock_mode_contract_batch": ([h, vp, i32, i32, i32, vp, i32, vp, i32, vp, i32, vp], ctypes.c_int),
         "bblock_set_graph": ([h, i32], ctypes.c_int),
         "bblock_tune": ([h, i32, i32, i32, i32], ctypes.c_int),
         "bblock_set_plan": ([h, i32, i32, i32, i32, ctypes.POINTER(bblock_plan)], ctypes.c_int),
@@ -162,6 +163,11 @@ def bblock_mode_triplets(h, phi, n_ev, mom, T):
 def bblock_mode_contract(h, T, n_ev, n_mom, Q1, n1, Q2, n2, Q3, n3, B):
     _check(h, load().bblock_mode_contract(h, _ptr(T), n_ev, n_mom, _ptr(Q1), n1, _ptr(Q2), n2, _ptr(Q3), n3,
                                           _ptr(B)))
+
+
+def bblock_mode_contract_batch(h, T, n_ev, n_mom, n_c, Q1, n1, Q2, n2, Q3, n3, B):
+    _check(h, load().bblock_mode_contract_batch(h, _ptr(T), n_ev, n_mom, n_c, _ptr(Q1), n1, _ptr(Q2), n2, _ptr(Q3),
+                                                n3, _ptr(B)))
 
 
 def bblock_set_graph(h, enable: bool):
@@ -275,6 +281,20 @@ class BaryonBlocks:
             out = torch.empty((n_mom, Q1.shape[0], Q2.shape[0], Q3.shape[0]), dtype=torch.complex128,
                               device=T.device)
         bblock_mode_contract(self.h, T, n_ev, n_mom, Q1, Q1.shape[0], Q2, Q2.shape[0], Q3, Q3.shape[0], out)
+        return out
+
+    def mode_contract_batch(self, T, Q1, Q2, Q3, out=None):
+        """n_c triples: Qi [n_c, n_i, n_ev] complex128 -> B [n_c, n_mom, n1, n2, n3]."""
+        import torch
+        n_mom, n_ev = T.shape[0], T.shape[1]
+        n_c = Q1.shape[0]
+        if Q2.shape[0] != n_c or Q3.shape[0] != n_c:
+            raise ValueError("one coefficient matrix per triple in each of Q1, Q2, Q3")
+        if out is None:
+            out = torch.empty((n_c, n_mom, Q1.shape[1], Q2.shape[1], Q3.shape[1]), dtype=torch.complex128,
+                              device=T.device)
+        bblock_mode_contract_batch(self.h, T, n_ev, n_mom, n_c, Q1, Q1.shape[1], Q2, Q2.shape[1], Q3, Q3.shape[1],
+                                   out)
         return out
 
     def tune(self, n1, n2, n3, n_mom):

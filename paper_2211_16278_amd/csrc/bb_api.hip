@@ -1135,86 +1135,121 @@ bblock_status bblock_mode_triplets(bblock_t h, const void *phi, int32_t n_ev, co
     return run_batch(h, &d, 1, mom, n_mom);
 }
 
-bblock_status bblock_mode_contract(bblock_t h, const void *T, int32_t n_ev, int32_t n_mom, const void *Q1, int32_t n1,
-                                   const void *Q2, int32_t n2, const void *Q3, int32_t n3, void *B)
+namespace {
+
+// The block from the mode triplets for n_c coefficient triples sharing T and
+// shapes (Sec. 2, after eq. (4)), as three batched GEMMs per round of
+// momenta: X1[p][c][d1][l2 l3] = sum_l1 Q1[c][d1][l1] T[p][l1][l2 l3] (the
+// triples stacked into the rows), X2[p][c][d1][d2][l3] = sum_l2
+// Q2[c][d2][l2] X1[p][c][d1][l2][l3], B[c][p][d1 d2][d3] = sum_l3
+// X2[p][c][d1 d2][l3] Q3[c][d3][l3].
+bblock_status mode_contract(bblock_t h, const void *T, int n_ev, int n_mom, int n_c, const void *Q1, int n1,
+                            const void *Q2, int n2, const void *Q3, int n3, void *B)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
     if (!T || !Q1 || !Q2 || !Q3 || !B) return fail(h, BBLOCK_EINVAL, "null buffer");
     if (n_ev < 1 || n_ev > MAX_MODES) return fail(h, BBLOCK_EINVAL, "n_ev must be in [1,%d]", MAX_MODES);
     if (n_mom < 1 || n_mom > MAX_MOM) return fail(h, BBLOCK_EINVAL, "n_mom must be in [1,%d]", MAX_MOM);
+    if (n_c < 1 || n_c > 65536) return fail(h, BBLOCK_EINVAL, "n_c must be in [1,65536]");
     if (n1 < 1 || n2 < 1 || n3 < 1 || n1 > MAX_MODES || n2 > MAX_MODES || n3 > MAX_MODES)
         return fail(h, BBLOCK_EINVAL, "dilution sizes (%d,%d,%d) outside [1,%d]", n1, n2, n3, MAX_MODES);
+    if ((long long)n_c * n1 > 0x7fffffffLL / 2 || (long long)n1 * n2 > 0x7fffffffLL / 2)
+        return fail(h, BBLOCK_EINVAL, "n_c * n1 and n1 * n2 must fit the GEMM row count");
     if (!aligned(T, 16) || !aligned(Q1, 16) || !aligned(Q2, 16) || !aligned(Q3, 16) || !aligned(B, 16))
         return fail(h, BBLOCK_EINVAL, "misaligned buffer");
-    // Intermediates per momentum: X1[d1][l2][l3] and X2[d1][d2][l3]; momenta
-    // go in rounds that fit the workspace cap.
+    // Intermediates per momentum; momenta go in rounds that fit the cap.
     const size_t e = (size_t)n_ev;
-    const size_t x1 = (size_t)n1 * e * e * 16, x2 = (size_t)n1 * n2 * e * 16;
+    const size_t x1 = (size_t)n_c * n1 * e * e * 16, x2 = (size_t)n_c * n1 * n2 * e * 16;
     const size_t per_mom = x1 + x2;
     const int pm = (int)std::min<size_t>((size_t)n_mom, h->ws_cap / per_mom);
     if (pm < 1) return fail(h, BBLOCK_ENOMEM, "one momentum needs %zu bytes of workspace, cap %zu", per_mom, h->ws_cap);
+    if ((long long)pm * n_c * n1 > 0x7fffffffLL) return fail(h, BBLOCK_EINVAL, "batch of the second GEMM too large");
     if (bblock_status st = ensure_ws(h, (size_t)pm * per_mom)) return st;
     double *X1 = static_cast<double *>(h->d_ws);
     double *X2 = reinterpret_cast<double *>(static_cast<unsigned char *>(h->d_ws) + (size_t)pm * x1);
-    const long long ne = n_ev, ne2 = ne * ne;
+    const long long ne = n_ev, ne2 = ne * ne, blk = (long long)n1 * n2 * n3;
     for (int p0 = 0; p0 < n_mom; p0 += pm) {
         const int np = std::min(pm, n_mom - p0);
-        ZgemmArgs s1{};  // X1[p][d1][l2 l3] = sum_l1 Q1[d1][l1] T[p][l1][l2 l3]
+        ZgemmArgs s1{};  // batch p; rows (c, d1)
         s1.A = static_cast<const double *>(Q1);
         s1.a_sm = ne;
         s1.a_sk = 1;
         s1.B = static_cast<const double *>(T) + 2 * p0 * ne2 * ne;
         s1.b_sk = ne2;
         s1.b_sn = 1;
-        s1.b_sb = ne2 * ne;
+        s1.b_b = batch_uniform(ne2 * ne);
         s1.C = X1;
         s1.c_sm = ne2;
         s1.c_sn = 1;
         s1.c_ng = (int)ne2;
-        s1.c_sb = n1 * ne2;
-        s1.M = n1;
+        s1.c_b = batch_uniform((long long)n_c * n1 * ne2);
+        s1.M = n_c * n1;
         s1.N = (int)ne2;
         s1.K = n_ev;
         s1.batch = np;
         if (bblock_status st = zgemm_timed(h, s1, "launch of the first mode contraction")) return st;
-        ZgemmArgs s2{};  // X2[p][d1][d2][l3] = sum_l2 Q2[d2][l2] X1[p][d1][l2][l3]
+        ZgemmArgs s2{};  // batch b = (p n_c + c) n1 + d1
         s2.A = static_cast<const double *>(Q2);
         s2.a_sm = ne;
         s2.a_sk = 1;
+        s2.a_b.s0 = (long long)n2 * ne;  // Q2[c], c = (b / n1) % n_c
+        s2.a_b.d0 = n1;
+        s2.a_b.m0 = n_c;
         s2.B = X1;
         s2.b_sk = ne;
         s2.b_sn = 1;
-        s2.b_sb = ne2;
+        s2.b_b = batch_uniform(ne2);
         s2.C = X2;
         s2.c_sm = ne;
         s2.c_sn = 1;
         s2.c_ng = n_ev;
-        s2.c_sb = (long long)n2 * ne;
+        s2.c_b = batch_uniform((long long)n2 * ne);
         s2.M = n2;
         s2.N = n_ev;
         s2.K = n_ev;
-        s2.batch = np * n1;
+        s2.batch = np * n_c * n1;
         if (bblock_status st = zgemm_timed(h, s2, "launch of the second mode contraction")) return st;
-        ZgemmArgs s3{};  // B[p][d1 d2][d3] = sum_l3 X2[p][d1 d2][l3] Q3[d3][l3]
+        ZgemmArgs s3{};  // batch b = p n_c + c
         s3.A = X2;
         s3.a_sm = ne;
         s3.a_sk = 1;
-        s3.a_sb = (long long)n1 * n2 * ne;
+        s3.a_b = batch_uniform((long long)n1 * n2 * ne);
         s3.B = static_cast<const double *>(Q3);
         s3.b_sk = 1;
         s3.b_sn = ne;
-        s3.C = static_cast<unsigned char *>(B) + (size_t)p0 * n1 * n2 * n3 * 16;
+        s3.b_b.s0 = (long long)n3 * ne;  // Q3[c], c = b % n_c
+        s3.b_b.m0 = n_c;
+        s3.C = static_cast<unsigned char *>(B) + (size_t)p0 * blk * 16;
         s3.c_sm = n3;
         s3.c_sn = 1;
         s3.c_ng = n3;
-        s3.c_sb = (long long)n1 * n2 * n3;
+        s3.c_b.s0 = (long long)n_mom * blk;  // B[c][p0 + p]: c = b % n_c, p = b / n_c
+        s3.c_b.m0 = n_c;
+        s3.c_b.s1 = blk;
+        s3.c_b.d1 = n_c;
+        s3.c_b.m1 = 0x7fffffff;
         s3.M = n1 * n2;
         s3.N = n3;
         s3.K = n_ev;
-        s3.batch = np;
+        s3.batch = np * n_c;
         if (bblock_status st = zgemm_timed(h, s3, "launch of the third mode contraction")) return st;
     }
     return BBLOCK_OK;
+}
+
+}  // namespace
+
+bblock_status bblock_mode_contract(bblock_t h, const void *T, int32_t n_ev, int32_t n_mom, const void *Q1, int32_t n1,
+                                   const void *Q2, int32_t n2, const void *Q3, int32_t n3, void *B)
+{
+    return mode_contract(h, T, n_ev, n_mom, 1, Q1, n1, Q2, n2, Q3, n3, B);
+}
+
+bblock_status bblock_mode_contract_batch(bblock_t h, const void *T, int32_t n_ev, int32_t n_mom, int32_t n_c,
+                                         const void *Q1, int32_t n1, const void *Q2, int32_t n2, const void *Q3,
+                                         int32_t n3, void *B)
+{
+    return mode_contract(h, T, n_ev, n_mom, n_c, Q1, n1, Q2, n2, Q3, n3, B);
 }
 
 bblock_status bblock_set_graph(bblock_t h, int32_t enable)

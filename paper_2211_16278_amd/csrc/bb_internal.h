@@ -122,16 +122,33 @@ hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipSt
 // BlockDesc.n_mt2 for the number of d3 blocks.
 int pord_pairs(int nb, int b3);
 hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
+// Offset of batch entry b of one GEMM operand, in complex elements: two
+// terms ((b / d) % m) * s, so that an operand can run with the whole batch
+// index, with an outer part of it only, or stay fixed (s = 0).
+struct BatchOff {
+    long long s0 = 0, s1 = 0;
+    int d0 = 1, m0 = 0x7fffffff, d1 = 1, m1 = 1;
+};
+inline BatchOff batch_uniform(long long s)
+{
+    BatchOff o;
+    o.s0 = s;
+    return o;
+}
+
 // Strided batched complex double GEMM on the FP64 matrix cores:
 // C[b](m, n) = sum_k A[b](m, k) B[b](k, n).  Strides count complex elements;
 // column n of C lives at (n / c_ng) * c_sg + (n % c_ng) * c_sn.
 struct ZgemmArgs {
     const double *A;                 // complex128
-    long long a_sm, a_sk, a_sb;
+    long long a_sm, a_sk;
+    BatchOff a_b;
     const double *B;                 // complex128
-    long long b_sk, b_sn, b_sb;
+    long long b_sk, b_sn;
+    BatchOff b_b;
     void *C;                         // complex128, or complex64 when c_c64
-    long long c_sm, c_sn, c_sb, c_sg;
+    long long c_sm, c_sn, c_sg;
+    BatchOff c_b;
     int c_ng, c_c64;
     int M, N, K, batch;
     int tiles_m, tiles_n;            // set by the launcher

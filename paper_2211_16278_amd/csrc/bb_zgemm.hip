@@ -55,6 +55,11 @@ struct Tile {
     static_assert(AE >= 1 && BE >= 1, "tile too small for the thread count");
 };
 
+__device__ __forceinline__ long long batch_off(const BatchOff &o, int b)
+{
+    return (long long)((b / o.d0) % o.m0) * o.s0 + (long long)((b / o.d1) % o.m1) * o.s1;
+}
+
 template <int WM, int WN, int WK>
 __global__ void __launch_bounds__(THREADS, 2) zgemm(ZgemmArgs a)
 {
@@ -78,8 +83,9 @@ __global__ void __launch_bounds__(THREADS, 2) zgemm(ZgemmArgs a)
     const int t = (int)(bid % per_b);
     const int m0 = (t % a.tiles_m) * TM, n0 = (t / a.tiles_m) * TN;
 
-    const d2_t *A = reinterpret_cast<const d2_t *>(a.A) + (long long)b * a.a_sb;
-    const d2_t *B = reinterpret_cast<const d2_t *>(a.B) + (long long)b * a.b_sb;
+    const d2_t *A = reinterpret_cast<const d2_t *>(a.A) + batch_off(a.a_b, b);
+    const d2_t *B = reinterpret_cast<const d2_t *>(a.B) + batch_off(a.b_b, b);
+    const long long c_base = batch_off(a.c_b, b);
 
     // Element -> (row, k) of the loads: k fastest when k is the contiguous
     // axis of the operand, the row (column) fastest otherwise.  Two register
@@ -222,7 +228,7 @@ __global__ void __launch_bounds__(THREADS, 2) zgemm(ZgemmArgs a)
                 const int gm = m0 + wm * 32 + i * 16 + 4 * r + fk;
                 const int gn = n0 + wn * 32 + jj * 16 + fr;
                 if (gm >= a.M || gn >= a.N) continue;
-                const long long off = (long long)b * a.c_sb + (long long)gm * a.c_sm +
+                const long long off = c_base + (long long)gm * a.c_sm +
                                       (long long)(gn / a.c_ng) * a.c_sg + (long long)(gn % a.c_ng) * a.c_sn;
                 if (a.c_c64)
                     reinterpret_cast<float2 *>(a.C)[off] = make_float2((float)cr[i][jj][r], (float)ci[i][jj][r]);

@@ -93,7 +93,7 @@ WORKLOADS = {
     "projected-32": dict(L=32, T=2, ndil=32, momenta="axis", dtype="c128", blocks_per_t=8),
     # LapH subspace: eigenvector count n_ev, coefficient sets n_q per call.
     "reconstruct-32": dict(L=32, T=1, ndil=32, n_ev=128, n_q=12, dtype="c128"),
-    "mode-triplet-32": dict(L=32, T=1, ndil=32, n_ev=64, momenta="axis", dtype="c128"),
+    "mode-triplet-32": dict(L=32, T=1, ndil=32, n_ev=64, momenta="axis", dtype="c128", n_c=16),
 }
 
 # Spin-projection terms of the projected workload: (output, spin triple,

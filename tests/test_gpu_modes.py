@@ -178,6 +178,46 @@ def test_mode_contract_in_momentum_rounds_is_bitwise(torch_dev):
     assert err_max(outs[0], modes.mode_contract(*Qs, T)) < TOL_GEMM
 
 
+@pytest.mark.parametrize("n_ev,n1,n2,n3,n_mom,n_c", [(13, 5, 7, 3, 2, 3), (24, 32, 16, 9, 3, 16), (7, 1, 1, 1, 1, 5)])
+def test_mode_contract_batch_matches_oracle(torch_dev, n_ev, n1, n2, n3, n_mom, n_c):
+    """n_c coefficient triples in one call (rows of the first GEMM stacked,
+    the others batched over the triples): each block against the oracle and
+    against the single-triple call."""
+    say("case mode contract batch", n_ev, n1, n2, n3, n_mom, n_c)
+    g = synth.rng(310, n_ev, n_c)
+    T = g.standard_normal((n_mom, n_ev, n_ev, n_ev)) + 1j * g.standard_normal((n_mom, n_ev, n_ev, n_ev))
+    Qs = [synth.coefficients(n_c, n, n_ev, workload=310, role=i) for i, n in enumerate((n1, n2, n3))]
+    tT, tQ = dev(torch_dev, T), [dev(torch_dev, Q) for Q in Qs]
+    with binding.BaryonBlocks(4, prec="fp64", in_dtype="c128", max_ndil=8) as bb:
+        got = bb.mode_contract_batch(tT, *tQ).cpu().numpy()
+        one = bb.mode_contract(tT, *[Q[n_c - 1] for Q in tQ]).cpu().numpy()
+        bb.sync()
+    assert got.shape == (n_c, n_mom, n1, n2, n3)
+    for c in range(n_c):
+        e = err_max(got[c], modes.mode_contract(Qs[0][c], Qs[1][c], Qs[2][c], T))
+        assert e < TOL_GEMM, (c, e)
+    assert err_max(got[n_c - 1], one) < TOL_GEMM
+
+
+def test_mode_contract_batch_rounds_and_errors(torch_dev):
+    """A cap that holds one momentum's intermediates of all triples runs the
+    momenta in rounds with the same result; bad triple counts are rejected."""
+    n_ev, ns, n_mom, n_c = 12, (5, 6, 7), 3, 4
+    g = synth.rng(311)
+    T = g.standard_normal((n_mom, n_ev, n_ev, n_ev)) + 1j * g.standard_normal((n_mom, n_ev, n_ev, n_ev))
+    Qs = [synth.coefficients(n_c, n, n_ev, workload=311, role=i) for i, n in enumerate(ns)]
+    tT, tQ = dev(torch_dev, T), [dev(torch_dev, Q) for Q in Qs]
+    per_mom = n_c * (ns[0] * n_ev * n_ev + ns[0] * ns[1] * n_ev) * 16
+    outs = []
+    for cap in (0, per_mom + 100):
+        with binding.BaryonBlocks(4, prec="fp64", in_dtype="c128", max_ndil=8, workspace_cap=cap) as bb:
+            outs.append(bb.mode_contract_batch(tT, *tQ).cpu().numpy())
+            with pytest.raises(binding.BBlockError):
+                binding.bblock_mode_contract_batch(bb.h, tT, n_ev, n_mom, 0, tQ[0], ns[0], tQ[1], ns[1], tQ[2], ns[2],
+                                                   tT)
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_both_routes_agree_on_the_gpu(torch_dev):
     """Sec. 2: reconstruct + block (eq. (2), (3)) and mode triplets + contraction
     (eq. (4)) give the same block, both computed on the GPU in FP64."""
