@@ -481,8 +481,8 @@ def main() -> int:
                     help="after timing, run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (blocks shard across GPUs with no "
-              "communication; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (blocks shard across GPUs with no "
+              "communication). Run with --gpus 1.", file=sys.stderr)
         return 2
 
     if args.workload == "scaling":

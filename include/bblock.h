@@ -56,7 +56,7 @@ typedef enum {
     BBLOCK_ENOMEM = 2,       /* device or host allocation failed, or workspace cap too small */
     BBLOCK_EHIP = 3,         /* HIP runtime error (launch failure, device fault) */
     BBLOCK_ENODEV = 4,       /* no usable gfx950 device */
-    BBLOCK_EUNSUPPORTED = 5  /* valid request this build does not implement */
+    BBLOCK_EUNSUPPORTED = 5  /* valid request the library does not implement */
 } bblock_status;
 
 /* Arithmetic of the contraction.  FP64: complex double end to end (MFMA f64).

@@ -13,7 +13,7 @@
  *   B[p][d1][d2][d3] = sum_x exp(-i p.x) sum_{a,b,c} eps_abc
  *                      q1[x][a][d1] q2[x][b][d2] q3[x][c][d3]
  *
- * Readings of points the paper leaves open (all listed in the design notes):
+ * Readings of points the paper leaves open:
  *   - momenta are integer vectors n with p = 2 pi n / L; the phase is formed
  *     from the exact integer reduction k = (n . x) mod L, so
  *     exp(-i p.x) = cos(2 pi k / L) - i sin(2 pi k / L);
