@@ -454,12 +454,17 @@ def cpu_baseline(L, qs, mom, M, target_s=15.0):
     per_row = dt / pilot
     n_rows = int(min(M, max(pilot, round(target_s / per_row))))
     rows = np.array([[r // n2, r % n2] for r in range(n_rows)], dtype=np.int32)
-    t0 = time.perf_counter()
-    oracle.bblock_rows(L, *qs, mom, rows)
-    dt = time.perf_counter() - t0
-    return {"value": (n_rows / M) / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d (d1,d2) rows of one block (all d3, all %d momenta), %.1f s; value scaled to "
-                      "whole blocks" % (n_rows, M, len(mom), dt)}
+    # When the whole block takes less than the target, it is repeated until
+    # the timed work reaches about target_s (at most 8 passes).
+    reps, dt = 0, 0.0
+    while reps < 8 and (reps == 0 or (n_rows == M and dt < target_s * 0.67)):
+        t0 = time.perf_counter()
+        oracle.bblock_rows(L, *qs, mom, rows)
+        dt += time.perf_counter() - t0
+        reps += 1
+    return {"value": reps * (n_rows / M) / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d (d1,d2) rows of one block (all d3, all %d momenta) x %d passes, %.1f s; value "
+                      "scaled to whole blocks" % (n_rows, M, len(mom), reps, dt)}
 
 
 def main() -> int:
