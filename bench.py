@@ -475,7 +475,9 @@ def main() -> int:
     ap.add_argument("--paths", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a captured hipGraph")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="always launch eagerly (default: the library's choice, hipGraph replay for schedules of 4 "
+                         "or more launches)")
     ap.add_argument("--workload", default="headline-32",
                     help="headline-32 (the benchmark line), or a grouped workload: batched-48, uneven-32, "
                          "large-64, tiny-12, projected-32 (spin projection), or a LapH-subspace workload: "

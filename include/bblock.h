@@ -205,8 +205,12 @@ bblock_status bblock_mode_contract_batch(bblock_t h, const void *T, int32_t n_ev
                                          const void *Q1, int32_t n1, const void *Q2, int32_t n2, const void *Q3,
                                          int32_t n3, void *B);
 
-/* Enable (1) or disable (0) hipGraph capture and replay in bblock_compute_batch
- * and bblock_compute (default: enabled). */
+/* hipGraph use in bblock_compute_batch, bblock_compute and
+ * bblock_compute_projected: 0 = eager launches, 1 = capture each schedule
+ * once and replay it, 2 = replay only schedules of 4 or more kernel launches
+ * (the default: a replayed graph leaves more idle time between its kernels
+ * than eager launches on one stream, so it pays only when it saves many
+ * launches).  Other values: BBLOCK_EINVAL. */
 bblock_status bblock_set_graph(bblock_t h, int32_t enable);
 
 /* Autotune the launch plan for one block shape: times the candidate plans

@@ -170,8 +170,10 @@ def bblock_mode_contract_batch(h, T, n_ev, n_mom, n_c, Q1, n1, Q2, n2, Q3, n3, B
                                                 n3, _ptr(B)))
 
 
-def bblock_set_graph(h, enable: bool):
-    _check(h, load().bblock_set_graph(h, 1 if enable else 0))
+def bblock_set_graph(h, mode):
+    """mode: False/0 eager, True/1 capture and replay, "auto"/2 replay schedules of 4+ launches."""
+    m = 2 if mode == "auto" else (1 if mode is True else (0 if mode is False else int(mode)))
+    _check(h, load().bblock_set_graph(h, m))
 
 
 def bblock_tune(h, n1, n2, n3, n_mom):
@@ -306,8 +308,8 @@ class BaryonBlocks:
     def get_plan(self, n1, n2, n3, n_mom):
         return bblock_get_plan(self.h, n1, n2, n3, n_mom)
 
-    def set_graph(self, enable: bool):
-        bblock_set_graph(self.h, enable)
+    def set_graph(self, mode):
+        bblock_set_graph(self.h, mode)
 
     def profile(self, enable: bool):
         bblock_profile(self.h, enable)

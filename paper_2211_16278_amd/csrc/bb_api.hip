@@ -91,7 +91,7 @@ struct bblock_s {
     size_t kidx_cap = 0;
     std::vector<int> kidx_mom;        // momentum set (reduced mod L) the table holds
 
-    bool graph_enabled = true;
+    int graph_mode = 2;               // 0: eager, 1: capture and replay, 2: replay schedules of 4+ launches
     bool profiling = false;
     int plan_gen = 0;                 // bumped whenever forced or tuned plans change
     // The last batch: when a call repeats it (same descriptors, momenta and
@@ -545,7 +545,16 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
 // replaying (capturing on first use) the graph of this batch structure.
 bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, const size_t *offs, int n_mom)
 {
-    if (!h->graph_enabled || h->profiling) return enqueue(h, subs, offs, n_mom, h->stream);
+    if (h->graph_mode == 0 || h->profiling) return enqueue(h, subs, offs, n_mom, h->stream);
+    if (h->graph_mode == 2) {
+        // A replayed graph separates its kernels by more idle time than eager
+        // launches on one stream (≈1 % of a single-block call); it pays only
+        // when it saves many launches.
+        int launches = 0;
+        for (const SubBatch &sb : subs)
+            launches += 1 + (sb.kernel == K_W3) + (sb.n_cg > 0) + (sb.n_list > 0);
+        if (launches < 4) return enqueue(h, subs, offs, n_mom, h->stream);
+    }
     // Graph signature: everything baked into kernel arguments.
     std::vector<long long> sig;
     sig.push_back(n_mom);
@@ -1255,7 +1264,8 @@ bblock_status bblock_mode_contract_batch(bblock_t h, const void *T, int32_t n_ev
 bblock_status bblock_set_graph(bblock_t h, int32_t enable)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
-    h->graph_enabled = enable != 0;
+    if (enable < 0 || enable > 2) return fail(h, BBLOCK_EINVAL, "graph mode must be 0, 1 or 2");
+    h->graph_mode = enable;
     return BBLOCK_OK;
 }
 
@@ -1315,7 +1325,8 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         mom[3 * i + 1] = i % 3 == 1 ? i / 3 : 0;
         mom[3 * i + 2] = i % 3 == 2 ? i / 3 : 0;
     }
-    const bool saved_graph = h->graph_enabled, saved_prof = h->profiling;
+    const int saved_graph = h->graph_mode;
+    const bool saved_prof = h->profiling;
     const bool had_forced = h->forced.count(key) != 0;
     const Plan saved_forced = had_forced ? h->forced[key] : Plan{};
     Plan best{};
@@ -1330,7 +1341,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         if (out) (void)hipFree(out);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        h->graph_enabled = saved_graph;
+        h->graph_mode = saved_graph;
         h->profiling = saved_prof;
         if (had_forced)
             h->forced[key] = saved_forced;
@@ -1352,7 +1363,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         cleanup();
         return st;
     }
-    h->graph_enabled = false;
+    h->graph_mode = 0;
     h->profiling = false;
 
     // Candidates: kernel x column fragments x split count x scheduling.

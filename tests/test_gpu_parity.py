@@ -391,6 +391,16 @@ def test_graph_replays_match_eager(torch_dev, prec):
             _ = (torch.ones(1000, device=dev) * rep).sum().item()  # eager work between replays
             for o, e in zip(outs, eager):
                 assert np.array_equal(o.cpu().numpy(), e)
+        # The default mode replays only long schedules; this one runs eagerly.
+        bb.set_graph("auto")
+        for o in outs:
+            o.fill_(float("nan"))
+        bb.compute_batch(descs, mom)
+        bb.sync()
+        for o, e in zip(outs, eager):
+            assert np.array_equal(o.cpu().numpy(), e)
+        with pytest.raises(binding.BBlockError):
+            bb.set_graph(3)
     for trip, e in zip(qs, eager):
         assert err_max(e, oracle.bblock(L, *trip, mom)) < TOL[prec]
 
