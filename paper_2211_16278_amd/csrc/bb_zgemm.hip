@@ -35,8 +35,9 @@ namespace zg {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
-// Complex k values per staged chunk: 4 k-steps of the MFMA per k-group wave
-// pair for WK = 4, 2 otherwise (smaller chunks keep more workgroups resident).
+// Complex k values per staged chunk: 16 (four MFMA k-steps, one per k-group
+// wave) for WK = 4, else 8 (two k-steps); smaller chunks keep more
+// workgroups resident.
 constexpr int chunk_k(int WK) { return WK == 4 ? 16 : 8; }
 
 template <int WM, int WN, int WK>
