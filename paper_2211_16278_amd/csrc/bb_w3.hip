@@ -76,6 +76,17 @@ __device__ __forceinline__ bf8_t im_rows(uint4 v)
                                                 __builtin_amdgcn_perm(v.w, v.w, 0x01000302u) ^ 0x80000000u));
 }
 
+// Keeps a computed value at this point of the instruction stream: the empty
+// asm statement reads and rewrites it, so the arithmetic that produces it
+// cannot sink past the scheduling barrier that follows (the diquark work is
+// spread one step per MFMA slot, and without this the compiler gathers the
+// steps of a colour next to their first use).
+template <class T>
+__device__ __forceinline__ void pin(T &x)
+{
+    asm volatile("" : "+v"(x));
+}
+
 // A value every lane of the wave holds alike, moved to scalar registers (loads
 // of the tile tables are vector loads, the compiler cannot tell on its own).
 template <class T>
@@ -328,10 +339,13 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
                     const float2 *uu = u[x & 1], *vv = v[x & 1];
                     if constexpr (part == 0) {
                         t1[c].x = fast::diq_re(uu[a_], uu[b_], vv[a_], vv[b_]);
+                        pin(t1[c].x);
                     } else if constexpr (part == 1) {
                         t1[c].y = fast::diq_im(uu[a_], uu[b_], vv[a_], vv[b_]);
+                        pin(t1[c].y);
                     } else if constexpr (part == 2) {
                         dh[c][x] = pack_bf16(t1[c].x, t1[c].y);
+                        pin(dh[c][x]);
                     } else {
                         dl[c][x] = split_lo(t1[c].x, t1[c].y, dh[c][x]);
                         if constexpr (x == 3) {
