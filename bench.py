@@ -39,9 +39,9 @@ def kernel_name(path, plan, n2, n3):
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
         return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)
-    if plan["kernel"] == 2:
+    if plan["kernel"] in (2, 4):
         b2 = 32 if n2 >= 32 else 16
-        return "bb::w3::contract<%d, %d, false>" % (plan["nb"], b2)
+        return "bb::w3::contract%s<%d, %d, false>" % ("8" if plan["kernel"] == 4 else "", plan["nb"], b2)
     if plan["kernel"] == 1:
         b2, b3 = (32 if n2 >= 32 else 16), (32 if n3 >= 32 else 16)
         return "bb::fast::bb_fast<%d, %d, %d, %d, false>" % (PREC_ID[path], plan["nb"], b2, b3)

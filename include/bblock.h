@@ -90,7 +90,7 @@ typedef struct {
                                n2 >= 16 and n3 >= 16; nb 4 or 7);
                             2: as 1 with the phase-weighted q3 precomputed
                                into workspace images by a separate launch
-                               (BF16X3 only; the default there; n2 >= 8,
+                               (BF16X3 only; n2 >= 8,
                                n3 >= 16; nb 4 to 7).  Needs workspace for
                                one image per (column tile, chunk of 8
                                sites): 28672, 32768, 40960 or 45056 bytes
@@ -102,7 +102,12 @@ typedef struct {
                                the momentum sum runs as an MFMA product over
                                sites (BF16X3 only, n3 >= 16; nb 1 or 2 column
                                fragments of 32 momenta; the default for more
-                               than 16 momenta).  Needs no image workspace. */
+                               than 16 momenta).  Needs no image workspace.
+                            4: kernel 2 with eight waves per workgroup, two
+                               per SIMD, which split the column fragments
+                               (same shapes, images and workspace as 2, and
+                               bitwise the same results; the BF16X3 default
+                               up to 16 momenta). */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device.

@@ -30,7 +30,9 @@ thread_local std::string g_create_error;
 
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
-constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3;
+constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4;
+// Kernel 2 and its eight-wave form 4 share geometry, images and workspace.
+inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 
 struct Plan {
     int kernel = K_GENERIC, nb = 0, splits = 0, persistent = 0, grid = 0;
@@ -181,12 +183,12 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
     Geometry g;
     g.kernel = kernel;
     g.nb = nb;
-    if (kernel == K_PIPELINED || kernel == K_W3) {
-        g.b2 = kernel == K_W3 ? w3_row_block(n2) : row_block(n2);
-        g.b3 = kernel == K_W3 ? w3_col_block(n3) : pipelined_block(n3);
-        const bool nb_ok = kernel == K_W3 ? (nb >= 4 && nb <= 7) : (nb == 4 || nb == 7);
+    if (kernel == K_PIPELINED || is_w3(kernel)) {
+        g.b2 = is_w3(kernel) ? w3_row_block(n2) : row_block(n2);
+        g.b3 = is_w3(kernel) ? w3_col_block(n3) : pipelined_block(n3);
+        const bool nb_ok = is_w3(kernel) ? (nb >= 4 && nb <= 7) : (nb == 4 || nb == 7);
         if (h->prec == FP64 || g.b2 == 0 || g.b3 == 0 || !nb_ok) return g;
-        if (kernel == K_W3 && h->prec != BF16X3) return g;
+        if (is_w3(kernel) && h->prec != BF16X3) return g;
         g.b1 = 128 / g.b2;
         g.m_tile = 128;
         g.n_tile = 32 * nb;
@@ -195,7 +197,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_nt3 = cdiv(n3, g.b3);
         g.n_mt = cdiv(n1, g.b1) * g.n_mt2;
         g.n_nt = cdiv(n_mom, g.bp) * g.n_nt3;
-        g.lds = kernel == K_W3 ? w3_lds_bytes(nb, g.b2) : fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
+        g.lds = is_w3(kernel) ? w3_lds_bytes(nb, g.b2) : fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
     } else if (kernel == K_PORD) {
         // Rows (d1,d2,d3): a block of consecutive (d1,d2) pairs x a d3 block;
         // columns: 32 nb momenta.
@@ -264,7 +266,7 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
             return p;
         }
     }
-    const int tiled = h->prec == BF16X3 ? K_W3 : K_PIPELINED;
+    const int tiled = h->prec == BF16X3 ? K_W3W8 : K_PIPELINED;
     for (int nb : {7, 6, 5, 4}) {
         const Geometry g = geometry(h, tiled, nb, n1, n2, n3, n_mom);
         if (g.lds < 0) continue;
@@ -342,7 +344,7 @@ void set_splits(bblock_t h, BlockPlan &bp, int S)
     bp.ws_bytes = bp.part_bytes;
     bp.rounds = 1;
     bp.spr = bp.d.S;
-    if (bp.plan.kernel == K_W3) {
+    if (is_w3(bp.plan.kernel)) {
         // W images of all splits if they fit beside the partials, else rounds
         // of as many splits as fit (at least one; 0 = does not fit).
         const size_t per_split = (size_t)bp.g.n_nt * bp.d.cps * w3_image_bytes(bp.plan.nb);
@@ -464,7 +466,7 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
         ga.kstride = kstride_of(h);
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
-        if (sb.kernel == K_W3) {
+        if (is_w3(sb.kernel)) {
             WImageArgs wa;
             wa.blocks = ga.blocks;
             wa.entries = reinterpret_cast<const int4 *>(h->d_table + off_went) + sb.went_off;
@@ -492,7 +494,8 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
             HIP_OR_FAIL(h, hipEventRecord(ev[0], st));
         }
         hipError_t e = sb.kernel == K_PIPELINED ? launch_fast(h->prec, sb.nb, sb.b2, sb.b3, ga.in_c64, ga, grid, st)
-                       : sb.kernel == K_W3      ? launch_w3(sb.nb, sb.b2, ga.in_c64, ga, grid, st)
+                       : is_w3(sb.kernel)       ? launch_w3(sb.nb, sb.b2, sb.kernel == K_W3W8 ? 8 : 4, ga.in_c64, ga,
+                                                            grid, st)
                        : sb.kernel == K_PORD    ? launch_pord(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                                                 : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
@@ -552,7 +555,7 @@ bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, cons
         // when it saves many launches.
         int launches = 0;
         for (const SubBatch &sb : subs)
-            launches += 1 + (sb.kernel == K_W3) + (sb.n_cg > 0) + (sb.n_list > 0);
+            launches += 1 + is_w3(sb.kernel) + (sb.n_cg > 0) + (sb.n_list > 0);
         if (launches < 4) return enqueue(h, subs, offs, n_mom, h->stream);
     }
     // Graph signature: everything baked into kernel arguments.
@@ -685,7 +688,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         bp.need_part = coef != nullptr;
         set_splits(h, bp, S);
         if (!fixed && bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
-        if (bp.plan.kernel == K_W3 && (bp.ws_bytes > h->ws_cap || !w3_offsets_fit(h, bp))) {
+        if (is_w3(bp.plan.kernel) && (bp.ws_bytes > h->ws_cap || !w3_offsets_fit(h, bp))) {
             // Not even one split's W images fit beside the partials (or the
             // split is too long for 32-bit offsets): the pipelined kernel
             // builds W in LDS instead.
@@ -776,7 +779,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             const BlockPlan &bp = bps[units[u].b];
             if (u > u0 && (bp.rounds > 1 || b0.rounds > 1)) break;
             if (!same_kernel(bp, sb) || used + bp.ws_bytes > h->ws_cap) break;
-            if (sb.kernel == K_W3) {  // image entries form the y dimension of one launch
+            if (is_w3(sb.kernel)) {  // image entries form the y dimension of one launch
                 const long e = (long)bp.g.n_nt * bp.spr;
                 if (u > u0 && n_went + e > 65535) break;
                 n_went += e;
@@ -806,7 +809,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
                 for (int nt = 0; nt < bp.g.n_nt; ++nt)
                     for (int mt = 0; mt < bp.g.n_mt; ++mt) items.push_back({cost, make_int4(un.d, mt, nt, s)});
             }
-            if (sb.kernel == K_W3) {
+            if (is_w3(sb.kernel)) {
                 sb.cps_max = std::max(sb.cps_max, bp.d.cps);
                 for (int s = s_lo; s < s_hi; ++s)
                     for (int nt = 0; nt < bp.g.n_nt; ++nt) went.push_back(make_int4(un.d, nt, s, 0));
@@ -880,7 +883,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         BlockDesc d = bp.d;
         unsigned char *base = static_cast<unsigned char *>(h->d_ws) + ws_off[un.d];
         d.ws = bp.part_bytes ? base : nullptr;
-        d.wimg = bp.plan.kernel == K_W3 ? base + align_up(bp.part_bytes, 4096) : nullptr;
+        d.wimg = is_w3(bp.plan.kernel) ? base + align_up(bp.part_bytes, 4096) : nullptr;
         d.img_s0 = un.r * bp.spr;
         descs[un.d] = d;
     }
@@ -1279,7 +1282,7 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         h->forced.erase(k);
         return BBLOCK_OK;
     }
-    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && plan->kernel != K_W3 && plan->kernel != K_PORD)
+    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && !is_w3(plan->kernel) && plan->kernel != K_PORD)
         return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
@@ -1373,6 +1376,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         const int n_opts = nb_options(h->prec, &opts);
         std::vector<std::pair<int, int>> kn;
         for (int nb : {1, 2}) kn.push_back({K_PORD, nb});
+        for (int nb : {7, 6, 5, 4}) kn.push_back({K_W3W8, nb});
         for (int nb : {7, 6, 5, 4}) kn.push_back({K_W3, nb});
         for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});

@@ -110,12 +110,14 @@ hipError_t prepare_fast_kernels(int lds_bytes);
 // kidx[p][x] = (n_p . x) mod L for all sites of one timeslice (momenta already
 // in [0, L)), rows of kstride >= V bytes, 0 past V.
 hipError_t launch_phase_index(const int *mom, int n_mom, int L, int kstride, unsigned char *kidx, hipStream_t st);
-// Precomputed-W kernel (BF16X3; d2 blocks of 16 or 32, nb 4 or 7): static
-// LDS bytes (-1 when no instantiation), bytes per W image, launches.
+// Precomputed-W kernel (BF16X3; d2 blocks of 8, 16 or 32, nb 4 to 7): static
+// LDS bytes (-1 when no instantiation), bytes per W image, launches.  The
+// contraction runs with 4 waves per workgroup (one per SIMD) or 8 (two per
+// SIMD, the column fragments split between the two).
 int w3_lds_bytes(int nb, int b2);
 size_t w3_image_bytes(int nb);
 hipError_t launch_w3_image(int nb, int c64, const WImageArgs &a, int cps_max, hipStream_t st);
-hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipStream_t st);
+hipError_t launch_w3(int nb, int b2, int waves, int c64, const GemmArgs &a, int grid, hipStream_t st);
 // Paper-order kernel (BF16X3; singlet on the VALU, momentum GEMM on MFMA;
 // nb column fragments of 32 momenta, d3 blocks of 16 or 32): (d1,d2) pairs
 // per workgroup (-1 when no instantiation), launch.  Its tiles use

@@ -521,6 +521,337 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
     }
 }
 
+// ----------------------------------------------------- contract, 8 waves ---
+// The same contraction with eight waves per workgroup, two per SIMD: waves w
+// and w + 4 share the 32 complex rows of row group w and split its column
+// fragments (waves 0-3 take the first ceil(NB / 2)), so that one wave's
+// vector work and waits run while the other's MFMAs issue.  The D/W tiles,
+// the staging and the W copies are shared by all eight waves; each lane
+// builds the diquark of two sites instead of four.  Every accumulator sees
+// the same MFMAs in the same order as in the four-wave kernel, so the two
+// kernels give bitwise identical results.
+constexpr int THREADS8 = 512;
+
+template <int NB, int B2, bool C64>
+__global__ void __launch_bounds__(THREADS8, 1) contract8(GemmArgs a)
+{
+    using Lt = CLayout<NB, B2>;
+    using Wi = WImg<NB>;
+    using IT = typename fast::InT<C64>::T;
+    constexpr int ESZ = sizeof(IT);
+    constexpr int B1 = Lt::B1;
+    constexpr int NBA = (NB + 1) / 2;  // column fragments of waves 0-3 (waves 4-7: NB - NBA)
+    constexpr int J1 = (Lt::E1 + THREADS8 - 1) / THREADS8, J2 = (Lt::E2 + THREADS8 - 1) / THREADS8;
+    constexpr int JL = J1 + J2;
+    constexpr int NW = (Wi::DW + 2047) / 2048;  // W copy rounds of 8 KiB (eight waves x 1 KiB)
+    __shared__ __align__(16) uint32_t w_a[Wi::DW];
+    __shared__ __align__(16) uint32_t w_b[Wi::DW];
+    __shared__ __align__(16) uint32_t dtile[2][2 * Lt::DPL];
+    __shared__ __align__(16) float2 stg[2][Lt::SG + Lt::SINK];
+    __shared__ int s_tile;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int swave = __builtin_amdgcn_readfirstlane(wave);
+    const int g = lane >> 5, r = lane & 31;
+    const int V = a.V;
+
+    auto next_tile = [&](int current) -> int {
+        if (a.counter == nullptr) return current < 0 ? (int)blockIdx.x : a.n_tiles;
+        __syncthreads();
+        if (tid == 0) s_tile = atomicAdd(&a.counter[0], 1);
+        __syncthreads();
+        return __builtin_amdgcn_readfirstlane(s_tile);
+    };
+
+    for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
+        const int4 tl = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl.x]);
+        const int d1_0 = (tl.y / bd.n_mt2) * B1, d2_0 = (tl.y % bd.n_mt2) * B2;
+        const int p0 = (tl.z / bd.n_nt3) * bd.bp, d3_0 = (tl.z % bd.n_nt3) * bd.b3;
+        const int xs = tl.w * bd.sps;
+        const int xe = min(V, xs + bd.sps);
+        const int n_chunks = (xe - xs + CHUNK_SITES - 1) / CHUNK_SITES;
+        const uint32_t *img = reinterpret_cast<const uint32_t *>(bd.wimg) +
+                              ((size_t)(tl.w - bd.img_s0) * bd.n_nt + tl.z) * bd.cps * (size_t)Wi::DW;
+
+        const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(reinterpret_cast<const IT *>(bd.q1) + (size_t)xs * 3 * bd.n1), (short)0,
+            (xe - xs) * 3 * bd.n1 * ESZ, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rs2 = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(reinterpret_cast<const IT *>(bd.q2) + (size_t)xs * 3 * bd.n2), (short)0,
+            (xe - xs) * 3 * bd.n2 * ESZ, 0x00020000);
+        const uint32_t cstep1 = 24u * bd.n1 * ESZ, cstep2 = 24u * bd.n2 * ESZ;
+
+        // Staging slots: element e = tid + 512 j of array k is (colour c,
+        // site x, index i) with e = i + B_k (x + 8c).
+        uint32_t voff[JL];
+        int sdst[JL];
+        auto plan_slot = [&](int q, int j, int n_k, int d0_k, int B_k, int E_k, int sofs_k) {
+            const int e = tid + THREADS8 * j;
+            const int i = e % B_k, x = (e / B_k) % 8, c = e / (8 * B_k);
+            const bool live = e < E_k;
+            const bool ok = live && (d0_k + i < n_k);
+            voff[q] = ok ? (uint32_t)(((x * 3 + c) * n_k + d0_k + i) * ESZ) : 0x80000000u;
+            sdst[q] = live ? sofs_k + e : Lt::SG + lane;
+        };
+#pragma unroll
+        for (int j = 0; j < J1; ++j) plan_slot(j, j, bd.n1, d1_0, B1, Lt::E1, 0);
+#pragma unroll
+        for (int j = 0; j < J2; ++j) plan_slot(J1 + j, j, bd.n2, d2_0, B2, Lt::E2, Lt::E1);
+
+        IT rv[JL];
+        auto qload = [&](int q, int ci) {
+            const bool first = q < J1;
+            const uint32_t off = voff[q] + (uint32_t)ci * (first ? cstep1 : cstep2);
+            if constexpr (C64)
+                rv[q] = __builtin_bit_cast(IT, __builtin_amdgcn_raw_buffer_load_b64(first ? rs1 : rs2, off, 0, 0));
+            else
+                rv[q] = __builtin_bit_cast(IT, __builtin_amdgcn_raw_buffer_load_b128(first ? rs1 : rs2, off, 0, 0));
+        };
+        auto qstore = [&](int q, float2 *s) { lds_put(s + sdst[q], (float)rv[q].x, (float)rv[q].y); };
+        // Direct-to-LDS copy of round k of image ci: wave w copies the 1 KiB
+        // slice 8k + w; slices past the image (the second half of the last
+        // round when the image holds an odd number of KiB) are skipped.
+        const uint32_t lane_off = (uint32_t)lane * 16u;
+        auto wcopy = [&](uint32_t *wbuf, int k, int ci) {
+            const int ro = (k * 8 + swave) * 256;
+            if (ro < Wi::DW) {
+                const __amdgpu_buffer_rsrc_t rsi = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(img + (size_t)ci * Wi::DW), (short)0, Wi::DW * 4, 0x00020000);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsi, (lvoid)(wbuf + ro), 16, lane_off, (uint32_t)ro * 4u, 0, 0);
+            }
+        };
+
+        // Diquark generation: thread -> (i1, i2, site pair xq).
+        const int i2 = tid % B2, xq = (tid / B2) & 3, i1 = tid / (4 * B2);
+        const int doff = drow(i1 * B2 + i2) + 2 * xq;
+        const int wr = swave & 3;
+        const int aoff = drow(wr * 32 + r) + 4 * g;
+        const int boff = wrow(r) + 4 * g;
+
+        auto body = [&](auto nbw_, auto n0_) {
+            constexpr int NBW = decltype(nbw_)::value, N0 = decltype(n0_)::value;
+            constexpr int FR = 3 * NBW;  // B fragments of this wave per chunk
+
+            f16_t acc[2][NBW];
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int n = 0; n < NBW; ++n)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) acc[f][n][e] = 0.f;
+
+            bf8_t A[4], An[4];
+            uint4 ra[2];
+            uint4 bh[2], bl[2];
+            auto load_a = [&](const uint32_t *dbuf, int c) {
+                ra[0] = *reinterpret_cast<const uint4 *>(dbuf + aoff + 8 * c);
+                ra[1] = *reinterpret_cast<const uint4 *>(dbuf + Lt::DPL + aoff + 8 * c);
+            };
+            auto load_b = [&](const uint32_t *wbuf, int c, int n, int slot) {
+                bh[slot] = *reinterpret_cast<const uint4 *>(wbuf + boff + 8 * c + (N0 + n) * wrow(32));
+                bl[slot] = *reinterpret_cast<const uint4 *>(wbuf + Wi::WPL + boff + 8 * c + (N0 + n) * wrow(32));
+            };
+            auto embed_step = [&](int s) {
+                if (s == 0) An[0] = __builtin_bit_cast(bf8_t, ra[0]);
+                if (s == 1) An[1] = __builtin_bit_cast(bf8_t, ra[1]);
+                if (s == 2) An[2] = im_rows(ra[0]);
+                if (s == 3) An[3] = im_rows(ra[1]);
+            };
+
+            // Diquark generation of one chunk in 26 sub-steps: the reads of
+            // the two sites, then per site 12 arithmetic steps (3 colours x 4).
+            float2 u[2][3], v[2][3], t1[3];
+            uint32_t dh[3][2], dl[3][2];
+            auto dgen = [&](auto ss, const float2 *sd, uint32_t *dn) {
+                constexpr int st = ss;
+                const float2 *S1 = sd, *S2 = sd + Lt::E1;
+                if constexpr (st < 2) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        u[st][q] = lds_get(S1 + (q * 8 + 2 * xq + st) * B1 + i1);
+                        v[st][q] = lds_get(S2 + (q * 8 + 2 * xq + st) * B2 + i2);
+                    }
+                } else {
+                    constexpr int s2 = st - 2, x = s2 / 12, w = s2 % 12;
+                    constexpr int c = w / 4, part = w % 4;
+                    constexpr int a_ = (c + 1) % 3, b_ = (c + 2) % 3;  // eps_{a b c} = +1
+                    const float2 *uu = u[x], *vv = v[x];
+                    if constexpr (part == 0) {
+                        t1[c].x = fast::diq_re(uu[a_], uu[b_], vv[a_], vv[b_]);
+                        pin(t1[c].x);
+                    } else if constexpr (part == 1) {
+                        t1[c].y = fast::diq_im(uu[a_], uu[b_], vv[a_], vv[b_]);
+                        pin(t1[c].y);
+                    } else if constexpr (part == 2) {
+                        dh[c][x] = pack_bf16(t1[c].x, t1[c].y);
+                        pin(dh[c][x]);
+                    } else {
+                        dl[c][x] = split_lo(t1[c].x, t1[c].y, dh[c][x]);
+                        if constexpr (x == 1) {
+                            *reinterpret_cast<uint2 *>(dn + doff + 8 * c) = make_uint2(dh[c][0], dh[c][1]);
+                            *reinterpret_cast<uint2 *>(dn + Lt::DPL + doff + 8 * c) = make_uint2(dl[c][0], dl[c][1]);
+                        }
+                    }
+                }
+            };
+            constexpr int NDGEN = 2 + 2 * 12;
+
+            // ---- prologue (as in the four-wave kernel)
+#pragma unroll
+            for (int q = 0; q < JL; ++q) qload(q, 0);
+#pragma unroll
+            for (int k = 0; k < NW; ++k) wcopy(w_a, k, 0);
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+#pragma unroll
+            for (int q = 0; q < JL; ++q) qstore(q, stg[0]);
+#pragma unroll
+            for (int q = 0; q < JL; ++q) qload(q, 1);
+            __syncthreads();
+            static_for<0, NDGEN>([&](auto ss) { dgen(ss, stg[0], dtile[0]); });
+            __builtin_amdgcn_s_waitcnt(0x0f70);
+#pragma unroll
+            for (int q = 0; q < JL; ++q) qstore(q, stg[1]);
+#pragma unroll
+            for (int q = 0; q < JL; ++q) qload(q, 2);
+            __syncthreads();
+            load_a(dtile[0], 0);
+            load_b(w_a, 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) embed_step(s);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) A[s] = An[s];
+
+            // ---- steady state: the schedule of the four-wave kernel over
+            // this wave's 6 FR MFMA slots.
+            constexpr int NSLOT = 6 * FR - 6;
+            constexpr int NQ = JL;
+            constexpr int W_STAGE = 0, W_COPY = NQ, W_LOAD = NQ + NW, W_DGEN = 2 * NQ + NW;
+            constexpr int NFIRST = NQ + NW;
+            constexpr int NWORK = W_DGEN + NDGEN;
+            static_assert(NFIRST < NSLOT, "too few MFMA slots for the per-chunk work");
+            auto chunk = [&](auto par, int i) {
+                constexpr int P = decltype(par)::value;
+                uint32_t *Wc = P ? w_b : w_a;
+                uint32_t *Wn = P ? w_a : w_b;
+                const uint32_t *Dc = dtile[P];
+                uint32_t *Dn = dtile[P ^ 1];
+                const float2 *Sd = stg[P ^ 1];
+                float2 *Ss = stg[P];
+                const int cnext = min(i + 1, n_chunks - 1);
+                auto work = [&](auto ww) {
+                    constexpr int w = ww;
+                    if constexpr (w < W_COPY)
+                        qstore(w - W_STAGE, Ss);
+                    else if constexpr (w < W_LOAD)
+                        wcopy(Wn, w - W_COPY, cnext);
+                    else if constexpr (w < W_DGEN)
+                        qload(w - W_LOAD, i + 3);
+                    else
+                        dgen(std::integral_constant<int, w - W_DGEN>{}, Sd, Dn);
+                };
+                static_for<0, 3>([&](auto cc) {
+                    constexpr int c = cc;
+                    static_for<0, NBW>([&](auto nn) {
+                        constexpr int n = nn;
+                        constexpr int fr = c * NBW + n;
+                        constexpr int slot_b = (P * FR + fr) & 1;
+                        if constexpr (fr == FR - 1) {
+                            __builtin_amdgcn_sched_barrier(0);
+                            __syncthreads();
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                        if constexpr (fr + 1 < FR)
+                            load_b(Wc, (fr + 1) / NBW, (fr + 1) % NBW, slot_b ^ 1);
+                        static_for<0, 6>([&](auto kk) {
+                            constexpr int k = kk, f = k & 1, prod = k >> 1;
+                            const bf8_t Av = A[2 * f + (prod == 0 ? 1 : 0)];
+                            const bf8_t Bv = __builtin_bit_cast(bf8_t, prod == 1 ? bl[slot_b] : bh[slot_b]);
+                            acc[f][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Av, Bv, acc[f][n], 0, 0, 0);
+                            __builtin_amdgcn_sched_barrier(0);
+                            constexpr int s = fr * 6 + k;
+                            if constexpr (fr < FR - 1) {
+                                if constexpr (s < NFIRST) {
+                                    work(std::integral_constant<int, s>{});
+                                } else {
+                                    constexpr int s2 = s - NFIRST, NS2 = NSLOT - NFIRST, NW2 = NWORK - NFIRST;
+                                    static_for<NFIRST + (s2 * NW2 + NS2 - 1) / NS2, NFIRST + ((s2 + 1) * NW2 + NS2 - 1) / NS2>(work);
+                                }
+                                constexpr int cs = s - c * 6 * NBW;
+                                if constexpr (c < 2) {
+                                    if constexpr (cs == 3 * NBW) load_a(Dc, c + 1);
+                                    if constexpr (cs >= 6 * NBW - 4) embed_step(cs - (6 * NBW - 4));
+                                }
+                            } else {
+                                if constexpr (k == 0) {
+                                    load_a(Dn, 0);
+                                    load_b(Wn, 0, 0, slot_b ^ 1);
+                                }
+                                if constexpr (k >= 2) embed_step(k - 2);
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+                        });
+                        if constexpr (n == NBW - 1) {
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) A[s] = An[s];
+                        }
+                    });
+                });
+            };
+            int i = 0;
+            for (; i + 2 <= n_chunks; i += 2) {
+                chunk(std::integral_constant<int, 0>{}, i);
+                chunk(std::integral_constant<int, 1>{}, i + 1);
+            }
+            if (i < n_chunks) chunk(std::integral_constant<int, 0>{}, i);
+
+            // Epilogue: fragment f = Re (0) / Im (1) part of complex row
+            // 32 wr + row; column -> (p, d3).
+            const int B3 = bd.b3;
+#pragma unroll
+            for (int n = 0; n < NBW; ++n) {
+                const int nl = (N0 + n) * 32 + r;
+                const int ip = nl / B3, d3 = d3_0 + nl % B3, p = p0 + ip;
+                if (ip >= bd.bp || p >= a.n_mom || d3 >= bd.n3) continue;
+                const int nu = p * bd.n3 + d3;
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int row = 8 * (e >> 2) + 4 * g + (e & 3);
+                        const int ml = wr * 32 + row;
+                        const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
+                        if (d1 >= bd.n1 || d2 >= bd.n2) continue;
+                        const int m = d1 * bd.n2 + d2;
+                        if (bd.direct)
+                            bd.out[(((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + f] = (double)acc[f][n][e];
+                        else
+                            reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + f) * bd.M + m) * bd.N + nu] = acc[f][n][e];
+                    }
+            }
+        };
+        if (swave < 4)
+            body(std::integral_constant<int, NBA>{}, std::integral_constant<int, 0>{});
+        else
+            body(std::integral_constant<int, NB - NBA>{}, std::integral_constant<int, NBA>{});
+    }
+
+    if (a.counter != nullptr && tid == 0) {
+        __threadfence();
+        if (atomicAdd(&a.counter[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&a.counter[0], 0);
+            atomicExch(&a.counter[1], 0);
+        }
+    }
+}
+
+template <int NB, int B2, bool C64>
+hipError_t run_contract8(const GemmArgs &a, int grid, hipStream_t st)
+{
+    contract8<NB, B2, C64><<<dim3(grid), dim3(THREADS8), 0, st>>>(a);
+    return hipGetLastError();
+}
+
 template <int NB, int B2, bool C64>
 hipError_t run_contract(const GemmArgs &a, int grid, hipStream_t st)
 {
@@ -574,11 +905,15 @@ hipError_t launch_w3_image(int nb, int c64, const WImageArgs &a, int cps_max, hi
     }
 }
 
-hipError_t launch_w3(int nb, int b2, int c64, const GemmArgs &a, int grid, hipStream_t st)
+hipError_t launch_w3(int nb, int b2, int waves, int c64, const GemmArgs &a, int grid, hipStream_t st)
 {
+    if (waves != 4 && waves != 8) return hipErrorInvalidValue;
 #define BBW_CASE(NB_, B2_) \
-    if (nb == NB_ && b2 == B2_) \
-        return c64 ? w3::run_contract<NB_, B2_, true>(a, grid, st) : w3::run_contract<NB_, B2_, false>(a, grid, st);
+    if (nb == NB_ && b2 == B2_) { \
+        if (waves == 8) \
+            return c64 ? w3::run_contract8<NB_, B2_, true>(a, grid, st) : w3::run_contract8<NB_, B2_, false>(a, grid, st); \
+        return c64 ? w3::run_contract<NB_, B2_, true>(a, grid, st) : w3::run_contract<NB_, B2_, false>(a, grid, st); \
+    }
     BBW_FOR_EACH(BBW_CASE)
 #undef BBW_CASE
     return hipErrorInvalidValue;

@@ -148,7 +148,7 @@ def _plans(prec):
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
     if prec == "bf16x3":
-        kernels += [(2, 4), (2, 5), (2, 6), (2, 7), (3, 1), (3, 2)]
+        kernels += [(2, 4), (2, 5), (2, 6), (2, 7), (3, 1), (3, 2), (4, 4), (4, 5), (4, 6), (4, 7)]
     for kernel, nb in kernels:
         for splits in (1, 3, 16):
             for persistent in (0, 1):
@@ -198,7 +198,8 @@ def test_precomputed_w_matches_pipelined_bitwise(torch_dev, L, ns, dtype):
     kernel 1), whatever its tile shape (4..7 column fragments; d2 blocks of
     8, 16 or 32; d3 blocks of any size in [16, 32]), so the blocks are
     bitwise equal; persistent and one-tile-per-workgroup schedules of kernel
-    2 agree too."""
+    2 agree too.  Its eight-wave form (plan kernel 4: two waves per SIMD
+    splitting the column fragments) gives the same blocks bitwise."""
     qs = fields(L, ns, workload=112, dtype=np.complex64 if dtype == "c64" else np.complex128)
     mom = synth.momenta("cube")
     a = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=1, nb=7, splits=3, persistent=0))
@@ -209,6 +210,12 @@ def test_precomputed_w_matches_pipelined_bitwise(torch_dev, L, ns, dtype):
                       plan=dict(kernel=2, nb=nb, splits=3, persistent=1, grid=5))
         assert np.array_equal(a, b)
         assert np.array_equal(b, c)
+        say("case w3 eight waves", L, ns, dtype, nb)
+        d = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype, plan=dict(kernel=4, nb=nb, splits=3, persistent=0))
+        e = gpu_block(torch_dev, "bf16x3", L, qs, mom, dtype=dtype,
+                      plan=dict(kernel=4, nb=nb, splits=3, persistent=1, grid=5))
+        assert np.array_equal(a, d)
+        assert np.array_equal(a, e)
     assert err_max(b, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
 
 
@@ -245,7 +252,8 @@ def test_precomputed_w_small_workspace_falls_back(torch_dev):
     assert err_max(small, oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
 
 
-def test_precomputed_w_in_rounds_matches(torch_dev):
+@pytest.mark.parametrize("kernel", [2, 4])
+def test_precomputed_w_in_rounds_matches(torch_dev, kernel):
     """W images larger than the workspace run in rounds of splits (each round:
     images, then the contraction of its splits; the reduction after the last),
     bitwise equal to the single-round run with the same split count."""
@@ -253,11 +261,11 @@ def test_precomputed_w_in_rounds_matches(torch_dev):
     L, ns = 6, (24, 24, 24)
     qs = fields(L, ns, workload=114)
     mom = synth.momenta("axis")
-    say("case w3 rounds")
-    # Plan kernel 2, nb 7, 9 splits of 3 chunks: partials 9 * 2 * 576 * 168 * 4
+    say("case w3 rounds, kernel", kernel)
+    # Plan kernel 2 (or 4), nb 7, 9 splits of 3 chunks: partials 9 * 2 * 576 * 168 * 4
     # = 6967296 bytes; images (one n-tile: 7 momenta x d3 block 24) 3 * 45056
     # bytes per split; the cap holds 3 splits' images: 3 rounds.
-    plan = dict(kernel=2, nb=7, splits=9, persistent=0)
+    plan = dict(kernel=kernel, nb=7, splits=9, persistent=0)
     tq = [torch.from_numpy(np.ascontiguousarray(q)).to(dev) for q in qs]
     outs, launches = [], []
     for cap in (0, 6967296 + 3 * 3 * 45056 + 1000):
@@ -450,7 +458,7 @@ def test_tune_then_compute(torch_dev):
     with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
         bb.tune(*ns, len(mom))
         plan = bb.get_plan(*ns, len(mom))
-        assert plan["kernel"] in (0, 1, 2, 3) and plan["nb"] in (1, 2, 4, 5, 6, 7) and plan["splits"] >= 1
+        assert plan["kernel"] in (0, 1, 2, 3, 4) and plan["nb"] in (1, 2, 4, 5, 6, 7) and plan["splits"] >= 1
         out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
         bb.sync()
     assert err_max(out[0].cpu().numpy(), oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
