@@ -243,7 +243,7 @@ bblock_status bblock_profile(bblock_t h, int32_t enable);
 /* Synchronises on the last recorded event, then returns the summed
  * event-timed milliseconds of the contraction kernels (gemm_ms), of the
  * split-K reduction kernels (reduce_ms) and of the W-image kernels of plan
- * kernel 2 (prep_ms) recorded since the previous read, and the number of
+ * kernels 2 and 4 (prep_ms) recorded since the previous read, and the number of
  * contraction launches among them.  Any output pointer may be NULL. */
 bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms, double *prep_ms,
                                   int32_t *gemm_launches);
