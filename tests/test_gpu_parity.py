@@ -356,6 +356,38 @@ def test_projected_group_across_sub_batches(torch_dev, prec):
     assert err_max(full[0], refs[0]) < TOL[prec]
 
 
+def test_plan_validation_and_defaults(torch_dev):
+    """Plan control around the precomputed-W kernels: kernel 4 (eight waves)
+    and kernel 2 are accepted for BF16X3 with 4-7 column fragments and
+    rejected otherwise (other fragment counts, other precisions, unknown
+    kernel ids); the default BF16X3 plan is kernel 4 up to 16 momenta and the
+    paper-order kernel 3 beyond."""
+    say("case plan validation")
+    L, n = 6, 24
+    with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=64) as bb:
+        for kernel in (2, 4):
+            for nb in (4, 5, 6, 7):
+                bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
+                got = bb.get_plan(n, n, n, 7)
+                assert (got["kernel"], got["nb"]) == (kernel, nb) and got["splits"] >= 1
+            for nb in (1, 2, 3, 8):
+                with pytest.raises(binding.BBlockError):
+                    bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
+        for kernel in (5, -1):
+            with pytest.raises(binding.BBlockError):
+                bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=7, splits=0, persistent=0, grid=0))
+        bb.set_plan(n, n, n, 7, None)
+        assert bb.get_plan(n, n, n, 7)["kernel"] == 4
+        assert bb.get_plan(n, n, n, 16)["kernel"] == 4
+        assert bb.get_plan(n, n, n, 17)["kernel"] == 3
+    for prec in ("fp32", "fp64"):
+        with binding.BaryonBlocks(L, prec=prec, in_dtype="c128", max_ndil=64) as bb:
+            for kernel in (2, 4):
+                with pytest.raises(binding.BBlockError):
+                    bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=7, splits=0, persistent=0, grid=0))
+            assert bb.get_plan(n, n, n, 7)["kernel"] in (0, 1)
+
+
 def test_projected_argument_errors(torch_dev):
     torch, dev = torch_dev
     L = 4
