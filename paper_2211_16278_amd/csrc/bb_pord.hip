@@ -56,6 +56,13 @@ __device__ __forceinline__ T wave_uniform(const T &v)
 typedef float f2v_t __attribute__((ext_vector_type(2)));
 typedef float f4v_t __attribute__((ext_vector_type(4)));
 
+// Keeps a computed value at this point of the instruction stream (the empty
+// asm statement reads and rewrites it), so that the singlet steps spread over
+// the MFMA slots stay where they are placed instead of gathering at their
+// first use.
+__device__ __forceinline__ void pin(float &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin(uint32_t &x) { asm volatile("" : "+v"(x)); }
+
 // Tile shape: NB column fragments of 32 momenta; F row fragments of 32 rows
 // per wave (rows = PPF pairs x B3 d3 values); 4 waves.
 template <int NB, int B3>
@@ -247,36 +254,105 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                     const f2v_t t = *reinterpret_cast<const f2v_t *>(&q3s[b][((4 * g + j) * 3 + c) * B3 + d3l]);
                     q[j][c] = make_float2(t.x, t.y);
                 }
+            if constexpr (NB == 1) {
+                // Singlet S = sum_c D_c q3_c of row fragment f split into BF16
+                // hi/lo, in 17 steps: the 12 D reads, then per site the Re chain,
+                // the Im chain, the hi pack and the lo split.  Fragment 0's runs
+                // before its MFMAs, fragment f+1's between fragment f's (double-
+                // buffered hi/lo), one slice per MFMA slot.
+                float2 dvf[12];
+                float sre = 0.f, sim = 0.f;
+                uint32_t sh[2][4], sl[2][4];
+                auto singlet = [&](auto ff, auto ss) {
+                    constexpr int f = ff, st = ss, B = f & 1;
+                    if constexpr (st == 0) {
+                        const int pi = (wave * F + f) * PPF + r / B3;  // pair of the lane's row
+                        const float2 *D = &dtile[b][(pi * CHUNK_SITES + 4 * g) * 3];
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                const int pi = (wave * F + f) * PPF + r / B3;  // pair of the lane's row
-                const float2 *D = &dtile[b][(pi * CHUNK_SITES + 4 * g) * 3];
-                uint32_t sh[4], sl[4];
+                        for (int k = 0; k < 12; ++k) dvf[k] = D[k];
+                    } else {
+                        constexpr int s1 = st - 1, j = s1 / 4, part = s1 % 4;
+                        if constexpr (part == 0) {
+                            sre = 0.f;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float re = 0.f, im = 0.f;
+                            for (int c = 0; c < 3; ++c) {
+                                sre = __builtin_fmaf(dvf[j * 3 + c].x, q[j][c].x, sre);
+                                sre = __builtin_fmaf(-dvf[j * 3 + c].y, q[j][c].y, sre);
+                            }
+                            pin(sre);
+                        } else if constexpr (part == 1) {
+                            sim = 0.f;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const float2 dv = D[j * 3 + c];
-                        re = __builtin_fmaf(dv.x, q[j][c].x, re);
-                        re = __builtin_fmaf(-dv.y, q[j][c].y, re);
-                        im = __builtin_fmaf(dv.x, q[j][c].y, im);
-                        im = __builtin_fmaf(dv.y, q[j][c].x, im);
+                            for (int c = 0; c < 3; ++c) {
+                                sim = __builtin_fmaf(dvf[j * 3 + c].x, q[j][c].y, sim);
+                                sim = __builtin_fmaf(dvf[j * 3 + c].y, q[j][c].x, sim);
+                            }
+                            pin(sim);
+                        } else if constexpr (part == 2) {
+                            sh[B][j] = pack_bf16(sre, sim);
+                            pin(sh[B][j]);
+                        } else {
+                            sl[B][j] = split_lo(sre, sim, sh[B][j]);
+                            pin(sl[B][j]);
+                        }
                     }
-                    sh[j] = pack_bf16(re, im);
-                    sl[j] = split_lo(re, im, sh[j]);
+                };
+                constexpr int NSTEP = 17, NSLOT = 6 * NB;
+                static_for<0, NSTEP>([&](auto ss) { singlet(std::integral_constant<int, 0>{}, ss); });
+                static_for<0, F>([&](auto ff) {
+                    constexpr int f = ff, B = f & 1;
+                    const bf8_t Ah = __builtin_bit_cast(bf8_t, make_uint4(sh[B][0], sh[B][1], sh[B][2], sh[B][3]));
+                    const bf8_t Al = __builtin_bit_cast(bf8_t, make_uint4(sl[B][0], sl[B][1], sl[B][2], sl[B][3]));
+                    // Products in the order lo.hi, hi.lo, hi.hi for every
+                    // accumulator, the accumulators interleaved.
+                    static_for<0, NSLOT>([&](auto kk) {
+                        constexpr int k = kk, prod = k / (2 * NB), n = (k % (2 * NB)) / 2, sp = k % 2;
+                        const bf8_t Bh = __builtin_bit_cast(bf8_t, bh[n][sp]), Bl = __builtin_bit_cast(bf8_t, bl[n][sp]);
+                        acc[f][n][sp] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(prod == 0 ? Al : Ah, prod == 1 ? Bl : Bh,
+                                                                                 acc[f][n][sp], 0, 0, 0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        if constexpr (f + 1 < F)
+                            static_for<(k * NSTEP + NSLOT - 1) / NSLOT, ((k + 1) * NSTEP + NSLOT - 1) / NSLOT>(
+                                [&](auto ss) { singlet(std::integral_constant<int, f + 1>{}, ss); });
+                        __builtin_amdgcn_sched_barrier(0);
+                    });
+                });
+            } else {
+                // Two column fragments: the pipelined form above needs more
+                // registers than the two-workgroup occupancy leaves (it spills
+                // in the loop and runs slower), so the singlet of each row
+                // fragment is formed before its MFMAs.
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int pi = (wave * F + f) * PPF + r / B3;  // pair of the lane's row
+                    const float2 *D = &dtile[b][(pi * CHUNK_SITES + 4 * g) * 3];
+                    uint32_t sh[4], sl[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        float re = 0.f, im = 0.f;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const float2 dv = D[j * 3 + c];
+                            re = __builtin_fmaf(dv.x, q[j][c].x, re);
+                            re = __builtin_fmaf(-dv.y, q[j][c].y, re);
+                            im = __builtin_fmaf(dv.x, q[j][c].y, im);
+                            im = __builtin_fmaf(dv.y, q[j][c].x, im);
+                        }
+                        sh[j] = pack_bf16(re, im);
+                        sl[j] = split_lo(re, im, sh[j]);
+                    }
+                    const bf8_t Ah = __builtin_bit_cast(bf8_t, make_uint4(sh[0], sh[1], sh[2], sh[3]));
+                    const bf8_t Al = __builtin_bit_cast(bf8_t, make_uint4(sl[0], sl[1], sl[2], sl[3]));
+#pragma unroll
+                    for (int n = 0; n < NB; ++n)
+#pragma unroll
+                        for (int s = 0; s < 2; ++s) {
+                            const bf8_t Bh = __builtin_bit_cast(bf8_t, bh[n][s]), Bl = __builtin_bit_cast(bf8_t, bl[n][s]);
+                            acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[f][n][s], 0, 0, 0);
+                            acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[f][n][s], 0, 0, 0);
+                            acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[f][n][s], 0, 0, 0);
+                        }
                 }
-                const bf8_t Ah = __builtin_bit_cast(bf8_t, make_uint4(sh[0], sh[1], sh[2], sh[3]));
-                const bf8_t Al = __builtin_bit_cast(bf8_t, make_uint4(sl[0], sl[1], sl[2], sl[3]));
-#pragma unroll
-                for (int n = 0; n < NB; ++n)
-#pragma unroll
-                    for (int s = 0; s < 2; ++s) {
-                        const bf8_t Bh = __builtin_bit_cast(bf8_t, bh[n][s]), Bl = __builtin_bit_cast(bf8_t, bl[n][s]);
-                        acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[f][n][s], 0, 0, 0);
-                        acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[f][n][s], 0, 0, 0);
-                        acc[f][n][s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[f][n][s], 0, 0, 0);
-                    }
             }
             // Next chunk's diquark and q3 into the other buffer; loads two ahead.
             store_chunk(b ^ 1);
