@@ -222,7 +222,9 @@ bblock_status bblock_set_graph(bblock_t h, int32_t enable);
  * (column fragments per wave, split count, persistent or not) on synthetic
  * data with HIP events, checks each candidate's result against the first
  * candidate's, keeps the fastest, and appends it to the file named by the
- * BBLOCK_TUNE_CACHE environment variable when that is set.  Synchronous. */
+ * BBLOCK_TUNE_CACHE environment variable when that is set; with
+ * BBLOCK_TUNE_VERBOSE set it prints each candidate's time (or rejection) to
+ * stderr.  Synchronous. */
 bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom);
 
 /* Force (or, with plan == NULL, forget) the plan used for one block shape. */

@@ -1393,9 +1393,11 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         }
     }
     const double tol = h->prec == FP64 ? 1e-11 : 1e-4;
+    const bool verbose = std::getenv("BBLOCK_TUNE_VERBOSE") != nullptr;
     bool have_ref = false;
     for (const Plan &cand : cands) {
         h->forced[key] = cand;
+        ++h->plan_gen;  // else run_batch would replay the previous candidate's cached schedule
         const bblock_desc d{q[0], q[1], q[2], n1, n2, n3, 0, out};
         st = run_batch(h, &d, 1, mom.data(), n_mom);
         if (st == BBLOCK_EUNSUPPORTED || st == BBLOCK_ENOMEM) {  // candidate does not fit this shape
@@ -1415,7 +1417,13 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
                 dmax = std::max(dmax, std::fabs(hout[i] - href[i]));
                 rmax = std::max(rmax, std::fabs(href[i]));
             }
-            if (!(dmax <= tol * std::max(rmax, 1e-300))) continue;  // rejected candidate
+            if (!(dmax <= tol * std::max(rmax, 1e-300))) {  // rejected candidate
+                if (verbose)
+                    std::fprintf(stderr, "bblock_tune: kernel %d nb %d splits %d persistent %d grid %d: rejected "
+                                 "(max difference %.3g of %.3g)\n", cand.kernel, cand.nb, cand.splits, cand.persistent,
+                                 cand.grid, dmax, rmax);
+                continue;
+            }
         }
         have_ref = true;
         float best_of = 1e30f;
@@ -1429,6 +1437,9 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
             best_of = std::min(best_of, ms);
         }
         if (st != BBLOCK_OK) break;
+        if (verbose)
+            std::fprintf(stderr, "bblock_tune: kernel %d nb %d splits %d persistent %d grid %d: %.4f ms\n", cand.kernel,
+                         cand.nb, cand.splits, cand.persistent, cand.grid, best_of);
         if (best_of < best_ms) {
             best_ms = best_of;
             best = cand;

@@ -496,6 +496,41 @@ def test_tune_then_compute(torch_dev):
     assert err_max(out[0].cpu().numpy(), oracle.bblock(L, *qs, mom)) < TOL["bf16x3"]
 
 
+def test_tune_times_each_candidate(torch_dev):
+    """The autotuner times every candidate plan on its own schedule: at
+    32^3, N_dil = 32 the candidates differ by more than 10x (generic tiles
+    against the precomputed-W kernels), so a tuned plan slower than the
+    default by 30 % means the candidates were not told apart (as when a
+    cached schedule of an earlier candidate was replayed for all of them)."""
+    torch, dev = torch_dev
+    L, n = 32, 32
+    mom = synth.momenta("axis")
+    say("case tune timing")
+    g = torch.Generator(device="cpu").manual_seed(7)
+    qs = [torch.randn((L ** 3, 3, n), dtype=torch.complex128, generator=g).to(dev) for _ in range(3)]
+    out = torch.empty((1, len(mom), n, n, n), dtype=torch.complex128, device=dev)
+
+    def ms(bb):
+        for _ in range(5):
+            bb.compute(*qs, mom, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(bb.stream)
+        for _ in range(30):
+            bb.compute(*qs, mom, out=out)
+        e1.record(bb.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 30
+
+    with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=32) as bb:
+        t_default = ms(bb)
+        bb.tune(n, n, n, len(mom))
+        plan = bb.get_plan(n, n, n, len(mom))
+        t_tuned = ms(bb)
+    say("  default %.3f ms, tuned %.3f ms with %s" % (t_default, t_tuned, plan))
+    assert t_tuned < 1.3 * t_default, (plan, t_default, t_tuned)
+
+
 # ---------------------------------------------------- full-size sampled
 def _sampled(torch_dev, prec, L, n, mset, dtype, rows, workload):
     qs = synth.gaussian_fields(L, (n, n, n), workload=workload,
