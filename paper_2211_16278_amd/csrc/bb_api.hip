@@ -308,6 +308,17 @@ int min_splits(bblock_t h)
     return (h->V + ACCURACY_MAX_SITES - 1) / ACCURACY_MAX_SITES;
 }
 
+// Split count of a single block from its plan's count: at least s_min, and
+// raised in whole multiples of the plan's count, which fills one wave of
+// workgroups (rounding up to s_min alone can leave a second wave with a few
+// workgroups: 36 tiles x 8 splits = 288 workgroups on 256 CUs take the time
+// of two full waves at N_dil = 48).
+int single_splits(int plan_splits, int s_min)
+{
+    if (plan_splits >= s_min) return plan_splits;
+    return cdiv(s_min, plan_splits) * plan_splits;
+}
+
 struct BlockPlan {
     BlockDesc d;
     Plan plan;
@@ -682,7 +693,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         if (fixed)
             S = bp.plan.splits;
         else if (n_desc == 1 && bp.plan.splits > 0)
-            S = std::max(bp.plan.splits, s_min);
+            S = single_splits(bp.plan.splits, s_min);
         else
             S = std::max<int>(s_min, (int)std::max<long>(1, 2L * h->num_cu / std::max(1L, total_tiles_s1)));
         bp.need_part = coef != nullptr;
@@ -1303,7 +1314,7 @@ bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
     if (bblock_status st = shape_ok(h, n1, n2, n3, n_mom)) return st;
     const Plan p = plan_for(h, n1, n2, n3, n_mom);
     plan->nb = p.nb;
-    plan->splits = std::max(p.splits, min_splits(h));
+    plan->splits = h->forced.count(ShapeKey{n1, n2, n3, n_mom}) ? p.splits : single_splits(p.splits, min_splits(h));
     plan->persistent = p.persistent;
     plan->grid = p.grid;
     plan->kernel = p.kernel;
@@ -1386,10 +1397,16 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
             if (g.lds <= 0) continue;
             const long padded = (long)g.n_nt * g.n_tile;  // columns, or momenta for the paper-order kernel
             if (padded > 2L * std::max(kernel == K_PORD ? n_mom : N, 32)) continue;  // mostly padding
-            const int s_base = fill_splits(h, g);
-            for (int sf : {1, 2, 4})
-                for (int pers = 0; pers < 2; ++pers)
-                    cands.push_back(Plan{kernel, nb, std::max(s_base * sf / 2, 1), pers, pers ? h->num_cu : 0});
+            // Split counts as a tuned plan will run them (at least the
+            // accuracy floor, in whole multiples of the wave-filling count).
+            const int s_base = fill_splits(h, g), s_min = min_splits(h);
+            int last = -1;
+            for (int sf : {1, 2, 4}) {
+                const int S = single_splits(std::max(s_base * sf / 2, 1), s_min);
+                if (S == last) continue;
+                last = S;
+                for (int pers = 0; pers < 2; ++pers) cands.push_back(Plan{kernel, nb, S, pers, pers ? h->num_cu : 0});
+            }
         }
     }
     const double tol = h->prec == FP64 ? 1e-11 : 1e-4;
