@@ -12,10 +12,13 @@ build()              compile ``liboracle.so`` with gcc (OpenMP, no fast-math).
 bblock(...)          full block B[p][d1][d2][d3] (eq. (3)).
 bblock_rows(...)     B for a list of (d1, d2) pairs, for sampled checks at
                      sizes where the full block would take minutes.
+bblock_entries(...)  B for a list of (d1, d2, d3) triples (every momentum),
+                     for sampled checks spread over all tiles of a large block.
 bblock_projected(...) the spin-projected sum  sum_i c_i B(q1_i, q2_i, q3_i)
                      (eq. (1): a correlator term is a linear combination over
                      spin triples of eq. (3) blocks), and its rows variant.
 max_threads()        OpenMP threads the oracle uses.
+set_threads(n)       set that count (the CPU baseline runs on 1 and on all).
 
 The LapH-subspace steps around eq. (3) -- eq. (2) reconstruction, eq. (4)
 mode triplets and the contraction onto them -- are in ``oracle.modes``.
@@ -66,6 +69,11 @@ def load_library(path: str):
     lib.oracle_bblock_rows.argtypes = ([ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int, ip,
                                        ctypes.c_int, ip, dp])
     lib.oracle_bblock_rows.restype = ctypes.c_int
+    lib.oracle_bblock_entries.argtypes = ([ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int, ip,
+                                          ctypes.c_int, ip, dp])
+    lib.oracle_bblock_entries.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ctypes.c_int
     return lib
@@ -112,6 +120,22 @@ def bblock_rows(L: int, q1, q2, q3, mom, rows) -> np.ndarray:
     return out
 
 
+def bblock_entries(L: int, q1, q2, q3, mom, entries) -> np.ndarray:
+    """B[p][d1][d2][d3] for the (d1, d2, d3) triples in ``entries``; shape [n_mom, n_entries]."""
+    q1, q2, q3 = _field(q1, L), _field(q2, L), _field(q3, L)
+    mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    entries = np.ascontiguousarray(np.asarray(entries, dtype=np.int32).reshape(-1, 3))
+    n1, n2, n3 = q1.shape[2], q2.shape[2], q3.shape[2]
+    out = np.zeros((mom.shape[0], entries.shape[0]), dtype=np.complex128)
+    rc = _load().oracle_bblock_entries(L, n1, n2, n3, _ptr(q1, ctypes.c_double),
+                                       _ptr(q2, ctypes.c_double), _ptr(q3, ctypes.c_double),
+                                       mom.shape[0], _ptr(mom, ctypes.c_int32), entries.shape[0],
+                                       _ptr(entries, ctypes.c_int32), _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return out
+
+
 def bblock_projected(L: int, triples, coef, mom) -> np.ndarray:
     """sum_i coef[i] * B(triples[i]) in complex128, shape [n_mom, n1, n2, n3]
     (eq. (1) with the spin sum written as a linear combination of blocks)."""
@@ -133,3 +157,8 @@ def bblock_rows_projected(L: int, triples, coef, mom, rows) -> np.ndarray:
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads for later oracle calls; returns the count in force."""
+    return int(_load().oracle_set_threads(int(n)))

@@ -120,6 +120,70 @@ int oracle_bblock_rows(int L, int n1, int n2, int n3,
     return 0;
 }
 
+/*
+ * Entries variant: B[p][d1][d2][d3] for a list of (d1, d2, d3) index triples
+ * and every momentum, each entry summed over sites exactly as in the rows
+ * variant (serial in x, the epsilon sum per site, then the phase).  For
+ * sampled checks of large blocks where even whole rows are expensive.
+ *   entries : [n_ent][3] int32 (d1, d2, d3)
+ *   out     : [n_mom][n_ent] complex128 interleaved
+ * Returns 0 on success, -1 on invalid arguments.
+ */
+int oracle_bblock_entries(int L, int n1, int n2, int n3,
+                          const double *q1, const double *q2, const double *q3,
+                          int n_mom, const int32_t *mom,
+                          int n_ent, const int32_t *entries,
+                          double *out)
+{
+    if (L <= 0 || n1 <= 0 || n2 <= 0 || n3 <= 0 || n_mom <= 0 || n_ent < 0)
+        return -1;
+    if (!q1 || !q2 || !q3 || !mom || !out || (n_ent > 0 && !entries))
+        return -1;
+    for (int e = 0; e < n_ent; ++e)
+        if (entries[3 * e] < 0 || entries[3 * e] >= n1 || entries[3 * e + 1] < 0 || entries[3 * e + 1] >= n2 ||
+            entries[3 * e + 2] < 0 || entries[3 * e + 2] >= n3)
+            return -1;
+
+    const int64_t V = (int64_t)L * L * L;
+    const double complex *Q1 = (const double complex *)q1;
+    const double complex *Q2 = (const double complex *)q2;
+    const double complex *Q3 = (const double complex *)q3;
+    double complex *OUT = (double complex *)out;
+    /* The L phases exp(-2 pi i k / L), tabulated once (the same values the
+     * rows variant forms per site). */
+    double complex *root = (double complex *)malloc((size_t)L * sizeof(double complex));
+    if (!root) return -1;
+    for (int k = 0; k < L; ++k) root[k] = phase_of_index(k, L);
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int e = 0; e < n_ent; ++e) {
+        const int d1 = entries[3 * e], d2 = entries[3 * e + 1], d3 = entries[3 * e + 2];
+        double complex *acc = (double complex *)calloc((size_t)n_mom, sizeof(double complex));
+        for (int64_t x = 0; x < V; ++x) {
+            const int64_t ix = x % L, iy = (x / L) % L, iz = x / ((int64_t)L * L);
+            double complex s = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    for (int c = 0; c < 3; ++c) {
+                        const int eps = levi_civita(a, b, c);
+                        if (eps == 0) continue;
+                        s += (double)eps * Q1[(x * 3 + a) * n1 + d1]
+                                         * Q2[(x * 3 + b) * n2 + d2]
+                                         * Q3[(x * 3 + c) * n3 + d3];
+                    }
+            for (int p = 0; p < n_mom; ++p) {
+                const int64_t nx = mom[3 * p], ny = mom[3 * p + 1], nz = mom[3 * p + 2];
+                acc[p] += root[mod_nonneg(nx * ix + ny * iy + nz * iz, L)] * s;
+            }
+        }
+        for (int p = 0; p < n_mom; ++p)
+            OUT[(size_t)p * n_ent + e] = acc[p];
+        free(acc);
+    }
+    free(root);
+    return 0;
+}
+
 /* Full block B[p][d1][d2][d3] (eq. (3)); out is [n_mom][n1][n2][n3] complex128. */
 int oracle_bblock(int L, int n1, int n2, int n3,
                   const double *q1, const double *q2, const double *q3,
@@ -137,6 +201,19 @@ int oracle_bblock(int L, int n1, int n2, int n3,
     const int rc = oracle_bblock_rows(L, n1, n2, n3, q1, q2, q3, n_mom, mom, n_rows, rows, out);
     free(rows);
     return rc;
+}
+
+/* Sets the OpenMP thread count of later calls (the CPU baseline times the
+ * oracle on one thread and on all of them); returns the count now in force. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* Threads the OpenMP runtime will use (reported beside CPU timings). */

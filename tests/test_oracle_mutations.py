@@ -1,6 +1,8 @@
 """The pins in test_oracle_pins.py are sensitive: each plausible mistake
 planted in a copy of the oracle source (on the CPU) makes at least one pin
-fail.  This guards against pins that would pass for a wrong oracle."""
+fail.  This guards against pins that would pass for a wrong oracle.  A
+mistake in an expression the rows and entries variants share is planted in
+both; one in the entries variant alone is caught by its determinant pin."""
 from __future__ import annotations
 
 import os
@@ -22,6 +24,11 @@ MUTATIONS = {
     "colour/dilution transposed": ("* Q2[(x * 3 + b) * n2 + d2]", "* Q2[(x * n2 + d2) * 3 + b]"),
     "colour of q2 rotated": ("* Q2[(x * 3 + b) * n2 + d2]", "* Q2[(x * 3 + (b + 1) % 3) * n2 + d2]"),
     "phase off by one site": ("ph[p] = phase_of_index(mod_nonneg(nx * ix", "ph[p] = phase_of_index(mod_nonneg(nx * (ix + 1)"),
+    "entries: phase index shifted": ("acc[p] += root[mod_nonneg(nx * ix + ny * iy + nz * iz, L)]",
+                                     "acc[p] += root[(mod_nonneg(nx * ix + ny * iy + nz * iz, L) + 1) % L]"),
+    "entries: epsilon term dropped": ("if (eps == 0) continue;", "if (eps == 0 || (a == 0 && b == 2)) continue;"),
+    "entries: d2 read as d1": ("const int d1 = entries[3 * e], d2 = entries[3 * e + 1],",
+                               "const int d1 = entries[3 * e], d2 = entries[3 * e] % n2,"),
 }
 
 PINS = [
@@ -33,6 +40,7 @@ PINS = [
     pins.test_field_swap_antisymmetry,
     pins.test_dilution_permutation_and_trilinearity,
     pins.test_mode_triplet_route,
+    pins.test_entries_against_determinants,
 ]
 
 
@@ -40,9 +48,9 @@ PINS = [
 def test_pins_catch_planted_mistake(name, tmp_path, monkeypatch):
     old, new = MUTATIONS[name]
     text = open(SRC).read()
-    assert text.count(old) == 1, name
+    assert text.count(old) >= 1, name
     src = tmp_path / "mutant.c"
-    src.write_text(text.replace(old, new))
+    src.write_text(text.replace(old, new))  # every occurrence: the variants stay consistent
     lib = oracle.load_library(oracle.build(str(src), str(tmp_path / "mutant.so")))
     monkeypatch.setattr(oracle, "_lib", lib)
     failed = []

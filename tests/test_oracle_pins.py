@@ -311,6 +311,34 @@ def test_rows_variant_matches_full():
         assert np.array_equal(R[:, r, :], B[:, d1, d2, :])
 
 
+def test_entries_variant_matches_full():
+    """The entries variant forms every entry with the rows variant's
+    arithmetic: bitwise equal to the full block at those positions."""
+    L, ns = 3, (4, 3, 5)
+    q1, q2, q3 = (_rand(L, n, 95 + i) for i, n in enumerate(ns))
+    B = oracle.bblock(L, q1, q2, q3, MOM_MIXED)
+    ent = np.array([[3, 2, 4], [0, 0, 0], [1, 2, 3], [3, 0, 1], [2, 1, 2]], dtype=np.int32)
+    E = oracle.bblock_entries(L, q1, q2, q3, MOM_MIXED, ent)
+    for e, (d1, d2, d3) in enumerate(ent):
+        assert np.array_equal(E[:, e], B[:, d1, d2, d3])
+
+
+def test_entries_against_determinants():
+    """Entries of a 4^3 block against numpy determinants of the three colour
+    vectors at each site with the unreduced phase (eps_abc u_a v_b w_c = det)."""
+    L, ns = 4, (6, 5, 7)
+    q1, q2, q3 = (_rand(L, n, 97 + i) for i, n in enumerate(ns))
+    g = np.random.default_rng(3)
+    ent = np.stack([g.integers(0, n, 24) for n in ns], axis=1).astype(np.int32)
+    E = oracle.bblock_entries(L, q1, q2, q3, MOM_MIXED, ent)
+    ph = _phases(L, MOM_MIXED)
+    m = np.empty((L ** 3, len(ent), 3, 3), dtype=np.complex128)
+    m[:, :, 0, :] = np.transpose(q1[:, :, ent[:, 0]], (0, 2, 1))
+    m[:, :, 1, :] = np.transpose(q2[:, :, ent[:, 1]], (0, 2, 1))
+    m[:, :, 2, :] = np.transpose(q3[:, :, ent[:, 2]], (0, 2, 1))
+    _close(E, ph.T @ np.linalg.det(m), 1e-12)
+
+
 def test_tiny_workload_sampled_against_determinants():
     """The 12^3, N_dil = 32, p = 0 workload, sampled (d1, d2) rows vs numpy determinants."""
     L, n = 12, 32
@@ -334,3 +362,5 @@ def test_oracle_rejects_bad_arguments():
         oracle.bblock(3, q, q, q, [[0, 0, 0]])  # V mismatch
     with pytest.raises(ValueError):
         oracle.bblock_rows(2, q, q, q, [[0, 0, 0]], [[2, 0]])  # d1 out of range
+    with pytest.raises(ValueError):
+        oracle.bblock_entries(2, q, q, q, [[0, 0, 0]], [[0, 0, 2]])  # d3 out of range
