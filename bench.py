@@ -7,7 +7,10 @@ complex GEMM) plus the FP64 split-K reduction that writes B.  The default
 workload is 32^3 sites, N_dil = 32 for all three quark fields, 7 momenta
 (0 and the six unit vectors), complex128 inputs, one timeslice; inputs are
 resident in HBM before timing starts.  All three arithmetic paths are timed;
-the headline value is the BF16x3 split-precision path in blocks/s.
+the headline value is the FP64 path in blocks/s (the paper's arithmetic is
+complex double), with the FP32 and BF16x3 split-precision paths beside it,
+each with its own roofline object and its error against the oracle over the
+whole block.
 
 Usage: python bench.py [--gpus 1] [--steps K=200] [--warmup W=50] [--paths fp64,fp32,bf16x3]
                        [--workload headline-32|batched-48|uneven-32|large-64|tiny-12|projected-32|
@@ -57,9 +60,32 @@ def flops(V, n1, n2, n3, n_mom):
     return f_gemm, f_alg
 
 
-# Sources of the translation unit that holds the headline's dominant kernel
-# (the precomputed-W BF16X3 contraction and its W-image kernel).
-DOMINANT_SOURCES = ("bb_w3.hip", "bb_fast.h", "bb_internal.h")
+# Sources each contraction kernel family is compiled from (a change to any
+# of them invalidates counter figures taken before it).
+KERNEL_SOURCES = {
+    "bb::w3::": ("bb_w3.hip", "bb_fast.h", "bb_internal.h"),
+    "bb::fast::": ("bb_fast.h", "bb_fast_fp32.hip", "bb_fast_bf16.hip", "bb_internal.h"),
+    "bb::pord::": ("bb_pord.hip", "bb_fast.h", "bb_internal.h"),
+    "bb::bb_gemm": ("bb_kernels.hip", "bb_internal.h"),
+}
+
+
+def sources_of(kname: str):
+    for prefix, files in KERNEL_SOURCES.items():
+        if kname.startswith(prefix):
+            return files
+    raise KeyError(kname)
+
+
+def mfma_flops_executed(path, plan, f_gemm):
+    """Matrix-core flops one headline launch executes: the fused complex GEMM
+    (F_gemm = 24 n_mom V n^3, 8 real flops per complex multiply-add), three
+    times over for the three BF16 products of BF16x3."""
+    return MFMA_PASSES[path] * f_gemm
+
+
+def flops_note(path, plan):
+    return "%d x 24 n_mom V n^3" % MFMA_PASSES[path]
 
 
 class no_gc:
@@ -77,7 +103,7 @@ class no_gc:
             gc.enable()
 
 
-def kernel_source_sha(files=DOMINANT_SOURCES) -> str:
+def kernel_source_sha(files) -> str:
     """Hash of the sources a kernel is compiled from: counter figures taken
     for another hash no longer describe the kernel that runs."""
     h = hashlib.sha256()
@@ -88,15 +114,16 @@ def kernel_source_sha(files=DOMINANT_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(path_name: str, workload: str):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when there is none or the kernel source changed since."""
+def read_traffic(path_name: str, workload: str, kname: str):
+    """HBM bytes per launch of a path's contraction kernel from the committed
+    counter summary, or None when there is none, it is of another kernel, or
+    the kernel's sources changed since the counters were taken."""
     fn = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (path_name, workload))
     if not os.path.exists(fn):
         return None
     with open(fn) as f:
         rec = json.load(f)
-    if rec.get("kernel_source_sha") != kernel_source_sha():
+    if rec.get("kernel") != kname or rec.get("kernel_source_sha") != kernel_source_sha(sources_of(kname)):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -225,6 +252,23 @@ def run_batch_workload(args, name):
             f_mfma += mfma_flops(plan, L ** 3, *shp)
         bb.close()
         err = None
+        if name != "projected-32" and not args.no_parity:
+            # Sampled parity: 64 seeded entries (every momentum) of the first,
+            # the middle and the last block against the oracle.
+            import numpy as np
+            import oracle
+            g = np.random.default_rng(11)
+            err = 0.0
+            for i in sorted({0, len(descs) // 2, len(descs) - 1}):
+                q1, q2, q3, o = descs[i]
+                ns = (q1.shape[-1], q2.shape[-1], q3.shape[-1])
+                ents = np.stack([g.integers(0, k, 64) for k in ns], axis=1).astype(np.int32)
+                host = [q.cpu().numpy().astype(np.complex128) for q in (q1, q2, q3)]
+                ref = oracle.bblock_entries(L, *host, mom, ents)
+                idx = torch.from_numpy(ents.astype(np.int64)).to(dev)
+                got = o[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+                err = max(err, float(np.abs(got - ref).max() / np.abs(ref).max()))
+                del host
         if name == "projected-32" and not args.no_parity:
             # Sampled parity of output 0 of timeslice 0 against the oracle's sum of blocks.
             import numpy as np
@@ -440,31 +484,85 @@ def run_scaling(args):
     return 0
 
 
-def cpu_baseline(L, qs, mom, M, target_s=15.0):
-    """The oracle, untuned, on a bounded sample of (d1, d2) rows of one block."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def _rows_rate(oracle, L, qs, mom, rows, reps=3):
+    """Median over reps of seconds per (d1, d2) row of the oracle's rows variant."""
+    import numpy as np
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        oracle.bblock_rows(L, *qs, mom, np.asarray(rows, dtype=np.int32))
+        times.append((time.perf_counter() - t0) / len(rows))
+    return _median(times)
+
+
+def cpu_baseline(L, qs, mom, M):
+    """The oracle, untuned, on the host cores: the whole headline block on all
+    threads and a row sample on one thread (median of 3 each), and the
+    per-block oracle time of the other workloads' block shapes extrapolated
+    from row samples on all threads (time per row x rows per block)."""
     import numpy as np
     import oracle
-    threads = oracle.max_threads()
+    from paper_2211_16278_amd import synth
+    all_threads = oracle.max_threads()
     n2 = qs[1].shape[2]
-    pilot = max(1, min(M, threads))
-    rows = np.array([[r // n2, r % n2] for r in range(pilot)], dtype=np.int32)
-    t0 = time.perf_counter()
-    oracle.bblock_rows(L, *qs, mom, rows)
-    dt = time.perf_counter() - t0
-    per_row = dt / pilot
-    n_rows = int(min(M, max(pilot, round(target_s / per_row))))
-    rows = np.array([[r // n2, r % n2] for r in range(n_rows)], dtype=np.int32)
-    # When the whole block takes less than the target, it is repeated until
-    # the timed work reaches about target_s (at most 8 passes).
-    reps, dt = 0, 0.0
-    while reps < 8 and (reps == 0 or (n_rows == M and dt < target_s * 0.67)):
+    t_start = time.perf_counter()
+    # All threads, whole block, median of 3.
+    full = []
+    for _ in range(3):
         t0 = time.perf_counter()
-        oracle.bblock_rows(L, *qs, mom, rows)
-        dt += time.perf_counter() - t0
-        reps += 1
-    return {"value": reps * (n_rows / M) / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d (d1,d2) rows of one block (all d3, all %d momenta) x %d passes, %.1f s; value "
-                      "scaled to whole blocks" % (n_rows, M, len(mom), reps, dt)}
+        oracle.bblock(L, *qs, mom)
+        full.append(time.perf_counter() - t0)
+    t_all = _median(full)
+    # One thread: 48 rows (of 1024), median of 3, scaled to the block.
+    oracle.set_threads(1)
+    try:
+        rows1 = [[r // n2, r % n2] for r in range(0, M, max(1, M // 48))][:48]
+        t_row1 = _rows_rate(oracle, L, qs, mom, rows1)
+    finally:
+        oracle.set_threads(all_threads)
+    t_one = t_row1 * M
+    # Other block shapes, all threads: one row per thread, one run each.
+    extrap = {}
+    shapes = [("batched-48", 48, 32, "cube", 192), ("uneven-32 N_dil 16", 32, 16, "axis", 960),
+              ("uneven-32 N_dil 32", 32, 32, "axis", 960), ("uneven-32 N_dil 64", 32, 64, "axis", 640),
+              ("large-64", 64, 64, "shell4", 4)]
+    for name, Lx, n, mset, blocks in shapes:
+        qx = synth.gaussian_fields(Lx, (n, n, n), workload=90)
+        mx = synth.momenta(mset)
+        rows = [[(7 * i) % n, (3 * i + 1) % n] for i in range(all_threads)]
+        per_row = _rows_rate(oracle, Lx, qx, mx, rows, reps=1)
+        extrap[name] = {"L": Lx, "n_dil": n, "n_mom": len(mx), "s_per_block": per_row * n * n,
+                        "blocks_in_workload": blocks, "s_workload": per_row * n * n * blocks}
+        del qx
+    return {"value": 1.0 / t_all, "unit": "blocks/s", "cores": all_threads, "kind": "oracle",
+            "sample": "whole 32^3 N_dil 32 block (7 momenta) on %d threads, median of 3 runs (%.2f s each); "
+                      "1 thread: %d of %d (d1,d2) rows, median of 3, scaled to the block" % (
+                          all_threads, t_all, len(rows1), M),
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "all_threads": {"threads": all_threads, "s_per_block": t_all, "blocks_per_s": 1.0 / t_all,
+                            "runs_s": full},
+            "one_thread": {"threads": 1, "s_per_block": t_one, "blocks_per_s": 1.0 / t_one,
+                           "rows_timed": len(rows1)},
+            "extrapolated_other_workloads": {"note": "EXTRAPOLATED: time per (d1,d2) row on all threads "
+                                                     "(one run over %d rows) x rows per block x blocks"
+                                                     % all_threads, **extrap},
+            "wall_s": time.perf_counter() - t_start}
 
 
 def main() -> int:
@@ -522,11 +620,10 @@ def main() -> int:
     f_gemm, f_alg = flops(V, n, n, n, n_mom)
     stream = torch.cuda.current_stream()
 
-    rows = np.array([[0, 0], [31, 31], [7, 19], [16, 3]], dtype=np.int32)
-    ref_rows = None
+    ref_block = None
     if not args.no_parity:
         import oracle
-        ref_rows = oracle.bblock_rows(L, *qs, mom, rows)
+        ref_block = oracle.bblock(L, *qs, mom)  # every entry is compared
 
     paths = {}
     for pname in [p for p in args.paths.split(",") if p]:
@@ -547,6 +644,16 @@ def main() -> int:
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
+        # Per-step durations: an event pair around every step of a second pass.
+        with no_gc():
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            for a, b in evs:
+                a.record(stream)
+                bb.compute(*tq, mom, out=out)
+                b.record(stream)
+            torch.cuda.synchronize()
+        per_step = sorted(a.elapsed_time(b) for a, b in evs)
         # Per-kernel durations: HIP events around each launch on the library's stream.
         bb.profile(True)
         bb.profile_read()
@@ -555,36 +662,43 @@ def main() -> int:
         gemm_ms, red_ms, prep_ms, launches = bb.profile_read()
         bb.profile(False)
         err = None
-        if ref_rows is not None:
-            got = out[0].cpu().numpy()
-            sub = np.stack([got[:, d1, d2, :] for d1, d2 in rows], axis=1)
-            err = float(np.abs(sub - ref_rows).max() / np.abs(ref_rows).max())
+        if ref_block is not None:
+            err = float(np.abs(out[0].cpu().numpy() - ref_block).max() / np.abs(ref_block).max())
         bb.close()
         step_ms = max(ms, wall * 1e3) / args.steps
         g_avg = gemm_ms / max(1, launches)
-        ach = MFMA_PASSES[pname] * f_gemm / (g_avg * 1e-3) / 1e12
+        f_exec = mfma_flops_executed(pname, plan, f_gemm)
+        ach = f_exec / (g_avg * 1e-3) / 1e12
+        kname = kernel_name(pname, plan, n, n)
         paths[pname] = {
             "blocks_per_s": 1e3 / step_ms,
             "ms_per_step": step_ms,
             "event_ms_per_step": ms / args.steps,
             "wall_ms_per_step": wall * 1e3 / args.steps,
+            "step_ms_min_median_max": [per_step[0], per_step[len(per_step) // 2], per_step[-1]],
             "tflops_gemm_count": f_gemm / (step_ms * 1e-3) / 1e12,
             "tflops_paper_count": f_alg / (step_ms * 1e-3) / 1e12,
             "contraction_kernel_ms": g_avg,
             "reduce_kernel_ms": red_ms / max(1, launches),
             "w_image_kernel_ms": prep_ms / max(1, launches),
-            "mfma_tflops": ach,
-            "mfma_peak_tflops": PEAK_TFLOPS[pname],
-            "mfma_frac": ach / PEAK_TFLOPS[pname],
-            "err_max_sampled": err,
+            "outside_kernels_ms": per_step[len(per_step) // 2] - (gemm_ms + red_ms + prep_ms) / max(1, launches),
+            "err_max": err,
+            "err_entries_compared": None if err is None else int(ref_block.size),
             "tol": TOL[pname],
             "plan": plan,
+            "roofline": {"bound": "mfma", "kernel": kname, "achieved": ach, "peak": PEAK_TFLOPS[pname],
+                         "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[pname],
+                         "step_frac": f_exec / (step_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname],
+                         "traffic": read_traffic(pname, "headline-32", kname),
+                         "flops_per_launch": f_exec,
+                         "note": "achieved = MFMA flops one launch executes (%s) / mean event-timed duration of the "
+                                 "contraction kernel; step_frac uses the whole step" % flops_note(pname, plan)},
         }
         print("# %-6s %.3f ms/block  %.1f blocks/s  contraction %.3f ms  reduce %.3f ms  w-image %.3f ms  "
-              "MFMA %.1f TF (%.1f%%)  err %s" % (pname, step_ms, 1e3 / step_ms, g_avg, red_ms / max(1, launches),
-                                                 prep_ms / max(1, launches), ach,
-                          100 * ach / PEAK_TFLOPS[pname], "%.2e" % err if err is not None else "-"),
-              file=sys.stderr, flush=True)
+              "MFMA %.1f TF (%.1f%% kernel, %.1f%% step)  err %s" % (
+                  pname, step_ms, 1e3 / step_ms, g_avg, red_ms / max(1, launches), prep_ms / max(1, launches), ach,
+                  100 * ach / PEAK_TFLOPS[pname], 100 * paths[pname]["roofline"]["step_frac"],
+                  "%.2e" % err if err is not None else "-"), file=sys.stderr, flush=True)
 
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib << 20
@@ -598,9 +712,10 @@ def main() -> int:
         print("# calibration: device copy and elementwise neg, each %d bytes read, %d bytes written"
               % (nbytes, nbytes), file=sys.stderr)
 
-    head = "bf16x3" if "bf16x3" in paths else next(iter(paths))
+    # The headline is the paper's arithmetic (complex double, Sec. 4): the FP64
+    # path; the split-precision paths are reported beside it.
+    head = "fp64" if "fp64" in paths else next(iter(paths))
     hp = paths[head]
-    traffic = read_traffic(head, "headline-32")
     rec = {
         "metric": METRIC,
         "value": hp["blocks_per_s"],
@@ -618,12 +733,7 @@ def main() -> int:
                                "complex128 inputs, one timeslice per step",
                    "L": L, "n_dil": n, "n_mom": n_mom, "in_dtype": "c128", "blocks_per_step": 1},
         "tflops": {"gemm_count": hp["tflops_gemm_count"], "paper_count": hp["tflops_paper_count"]},
-        "roofline": {"bound": "mfma", "kernel": kernel_name(head, hp["plan"], n, n), "achieved": hp["mfma_tflops"],
-                     "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s", "frac": hp["mfma_frac"],
-                     "traffic": traffic,
-                     "flops_per_launch": MFMA_PASSES[head] * f_gemm,
-                     "note": "achieved = MFMA flops of one block (%d x 24 n_mom V n^3) / mean event-timed duration "
-                             "of the contraction kernel" % MFMA_PASSES[head]},
+        "roofline": hp["roofline"],
         "paths": paths,
     }
     if not args.no_cpu_baseline:

@@ -110,7 +110,12 @@ typedef struct {
                                up to 16 momenta). */
 } bblock_plan;
 
-/* Create a handle bound to the current HIP device.
+/* Create a handle bound to the current HIP device (paper, Sec. 2 after
+ * eq. (3): the block kernel is called many times, for different noise and
+ * spin combinations, with one momentum set; Sec. 3: the phases are
+ * precomputed once and reused.  The handle holds what those calls share:
+ * the phase roots, the tables of the last momentum set and batch, the
+ * workspace and the launch plans).
  *   L               lattice extent, 1 <= L <= 256 (V = L^3 sites per timeslice)
  *   prec            bblock_prec
  *   in_dtype        bblock_dtype of the quark fields
@@ -122,7 +127,9 @@ typedef struct {
 bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_dtype,
                             int32_t max_ndil, size_t workspace_cap, void *hip_stream);
 
-/* Compute the blocks of timeslices [t_begin, t_end) of Q1, Q2, Q3
+/* Baryon blocks of eq. (3) (paper, Sec. 2), one per timeslice (each
+ * timeslice is an independent block, Sec. 2 after eq. (1)).
+ * Compute the blocks of timeslices [t_begin, t_end) of Q1, Q2, Q3
  * ([T][V][3][n_i] device buffers) into B ([t_end - t_begin][n_mom][n1][n2][n3]
  * complex128 device buffer).  All timeslices go through one grouped launch.
  * Buffers must be 16-byte aligned.  n_i in 1..max_ndil, 1 <= n_mom <= 128,
@@ -132,7 +139,11 @@ bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const v
                              const int32_t *mom, int32_t n_mom,
                              int32_t t_begin, int32_t t_end, void *B);
 
-/* Grouped launch over n_desc independent blocks (uneven dilution sizes
+/* Many eq. (3) blocks in one grouped launch (paper, Sec. 2 after eq. (3):
+ * the kernel is evaluated for many noise and spin combinations per
+ * timeslice with the same momentum set; Sec. 3: independent blocks run in
+ * parallel).
+ * Grouped launch over n_desc independent blocks (uneven dilution sizes
  * allowed), one momentum set.  The tile schedule of a batch structure is
  * captured into a hipGraph on first use and replayed when the same structure
  * (count, shapes, momentum count) comes back; only the descriptor table is
@@ -218,16 +229,24 @@ bblock_status bblock_mode_contract_batch(bblock_t h, const void *T, int32_t n_ev
  * launches).  Other values: BBLOCK_EINVAL. */
 bblock_status bblock_set_graph(bblock_t h, int32_t enable);
 
-/* Autotune the launch plan for one block shape: times the candidate plans
- * (column fragments per wave, split count, persistent or not) on synthetic
- * data with HIP events, checks each candidate's result against the first
- * candidate's, keeps the fastest, and appends it to the file named by the
+/* Autotune the launch plan for one block shape (paper, Sec. 4: the block
+ * sizes of the CPU kernel are tuned experimentally per machine; here the
+ * GPU kernel family, tile width, split count and scheduling mode).  Times
+ * the candidate plans (column fragments per wave, split count, persistent
+ * or not) on synthetic data with HIP events, checks each candidate's result
+ * against the default plan's (relative to the block's largest entry: 1e-11
+ * for FP64, 2e-5 for FP32 and BF16X3), keeps the fastest, and appends it to the file named by the
  * BBLOCK_TUNE_CACHE environment variable when that is set; with
  * BBLOCK_TUNE_VERBOSE set it prints each candidate's time (or rejection) to
  * stderr.  Synchronous. */
 bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom);
 
-/* Force (or, with plan == NULL, forget) the plan used for one block shape. */
+/* Force (or, with plan == NULL, forget) the plan used for one block shape
+ * (paper, Sec. 4: tuned block sizes).  For FP32 and BF16X3 a split holds at
+ * most 4096 sites (the FP32 accumulation depth the 1e-5 error contract
+ * assumes): an explicit split count below ceil(L^3 / 4096) returns
+ * BBLOCK_EINVAL, and splits = 0 takes the planner's wave-filling count,
+ * raised to that floor in whole multiples of itself. */
 bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom,
                               const bblock_plan *plan);
 
@@ -253,7 +272,10 @@ bblock_status bblock_profile_read(bblock_t h, double *gemm_ms, double *reduce_ms
 /* Block until the handle's stream has drained; reports device-side errors. */
 bblock_status bblock_sync(bblock_t h);
 
-/* Release the handle (synchronises its stream first).  NULL is accepted. */
+/* Release the handle (synchronises its stream first, then frees the
+ * workspace, tables, graphs and events bblock_create and the calls on the
+ * handle allocated; the paper's Sec. 2 sequence of calls with one momentum
+ * set ends here).  NULL is accepted. */
 bblock_status bblock_destroy(bblock_t h);
 
 /* Message of the last failure on h; with h == NULL, of the calling thread's

@@ -1300,10 +1300,16 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
     if (geometry(h, plan->kernel, plan->nb, n1, n2, n3, n_mom).lds <= 0)
         return fail(h, BBLOCK_EINVAL, "kernel %d with nb=%d is not available for this precision and shape", plan->kernel,
                     plan->nb);
+    // FP32-accumulating paths hold at most ACCURACY_MAX_SITES sites per split:
+    // an explicit count below that floor is refused, and the planner's own
+    // count (splits = 0) is raised to it in whole multiples of the
+    // wave-filling count, as for an unforced single block.
+    const int s_min = min_splits(h);
+    if (plan->splits > 0 && plan->splits < s_min)
+        return fail(h, BBLOCK_EINVAL, "splits=%d is below the accuracy floor of %d splits (at most %d sites per "
+                    "split in FP32 accumulation)", plan->splits, s_min, ACCURACY_MAX_SITES);
     Plan p{plan->kernel, plan->nb, plan->splits, plan->persistent, plan->grid};
-    if (p.splits == 0) {
-        p.splits = fill_splits(h, geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom));
-    }
+    if (p.splits == 0) p.splits = single_splits(fill_splits(h, geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom)), s_min);
     h->forced[k] = p;
     return BBLOCK_OK;
 }
@@ -1409,9 +1415,26 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
             }
         }
     }
-    const double tol = h->prec == FP64 ? 1e-11 : 1e-4;
+    // Reference: the default plan (the tested one).  A candidate must agree
+    // with it to within the error contract of the precision (FP64 1e-10 of
+    // the block's largest entry, the FP32-accumulating paths 1e-5) with
+    // room for the spread between two correct plans: 1e-11 and 2e-5.
+    const double tol = h->prec == FP64 ? 1e-11 : 2e-5;
     const bool verbose = std::getenv("BBLOCK_TUNE_VERBOSE") != nullptr;
-    bool have_ref = false;
+    {
+        h->forced.erase(key);
+        ++h->plan_gen;
+        const bblock_desc d{q[0], q[1], q[2], n1, n2, n3, 0, out};
+        st = run_batch(h, &d, 1, mom.data(), n_mom);
+        if (st == BBLOCK_OK && hipStreamSynchronize(h->stream) != hipSuccess)
+            st = fail(h, BBLOCK_EHIP, "tune reference failed");
+        if (st == BBLOCK_OK && hipMemcpy(href.data(), out, out_elems * 16, hipMemcpyDeviceToHost) != hipSuccess)
+            st = fail(h, BBLOCK_EHIP, "tune reference copy failed");
+        if (st != BBLOCK_OK) {
+            cleanup();
+            return st;
+        }
+    }
     for (const Plan &cand : cands) {
         h->forced[key] = cand;
         ++h->plan_gen;  // else run_batch would replay the previous candidate's cached schedule
@@ -1426,9 +1449,12 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
             st = fail(h, BBLOCK_EHIP, "tune candidate failed");
             break;
         }
-        // Consistency against the first candidate's result.
-        (void)hipMemcpy(have_ref ? hout.data() : href.data(), out, out_elems * 16, hipMemcpyDeviceToHost);
-        if (have_ref) {
+        // Consistency against the default plan's result.
+        if (hipMemcpy(hout.data(), out, out_elems * 16, hipMemcpyDeviceToHost) != hipSuccess) {
+            st = fail(h, BBLOCK_EHIP, "tune candidate copy failed");
+            break;
+        }
+        {
             double dmax = 0, rmax = 0;
             for (size_t i = 0; i < hout.size(); ++i) {
                 dmax = std::max(dmax, std::fabs(hout[i] - href[i]));
@@ -1442,7 +1468,6 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
                 continue;
             }
         }
-        have_ref = true;
         float best_of = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             (void)hipEventRecord(e0, h->stream);

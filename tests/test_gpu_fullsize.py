@@ -1,0 +1,228 @@
+"""GPU parity at the full sizes of the benchmark workloads, through the C ABI,
+with the plans the library picks by default (the plans bench.py times).
+
+* headline: 32^3 sites, N_dil 32, 7 momenta, complex128 -- every entry of the
+  block against the oracle, in all three precisions;
+* large: 64^3 sites, N_dil 64, 33 momenta (the paper's test problem, Sec. 4)
+  -- two entries in every group of 8 consecutive (d1, d2) pairs, one in each
+  half of the d3 range, every momentum: every row tile of every kernel's
+  tiling (64-row linear tiles, 4 x 32 rectangles, 8-pair tiles) and every
+  column tile is compared, in all three precisions;
+* batched: one timeslice of the 48^3, N_dil 32, 27-momentum workload (its 4
+  spin triples (s, s, s), complex64) in one grouped launch;
+* uneven: one timeslice of the 32^3 uneven workload -- 8 noise triples with
+  N_dil (16, 32, 64)[k mod 3] x the first 20 spin triples of {0..3}^3 = 160
+  blocks in one grouped launch, complex64 -- one whole (d1, d2) row of every
+  block.
+
+Error metric per block: max|B - R| / max|R| over the compared entries; FP64
+1e-10, FP32 and BF16x3 1e-5.  Oracle values are computed once per workload
+and shared by the three precisions.
+"""
+from __future__ import annotations
+
+import itertools
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_16278_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
+PRECS = ("fp64", "fp32", "bf16x3")
+_cache = {}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not os.path.exists(binding.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return torch, torch.device("cuda:0")
+
+
+def err_max(got, ref):
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def cover_entries(n1, n2, n3):
+    """Two (d1, d2, d3) entries per group of 8 consecutive pairs m = d1 n2 + d2,
+    one with d3 in each half of [0, n3)."""
+    out = []
+    M = n1 * n2
+    for g in range((M + 7) // 8):
+        m = min(M - 1, 8 * g + (5 * g) % 8)
+        d1, d2 = divmod(m, n2)
+        h = max(1, n3 // 2)
+        out.append((d1, d2, (7 * g) % h))
+        out.append((d1, d2, min(n3 - 1, h + (11 * g) % max(1, n3 - h))))
+    return np.array(out, dtype=np.int32)
+
+
+def pick(got, ents):
+    """got [n_mom][n1][n2][n3] -> [n_mom][n_entries]."""
+    return got[:, ents[:, 0], ents[:, 1], ents[:, 2]]
+
+
+# ------------------------------------------------------------- headline
+def _headline():
+    if "headline" not in _cache:
+        L, n = 32, 32
+        qs = synth.gaussian_fields(L, (n, n, n), workload=2)
+        mom = synth.momenta("axis")
+        say("  oracle: whole 32^3 block ...")
+        _cache["headline"] = (L, qs, mom, oracle.bblock(L, *qs, mom))
+    return _cache["headline"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_headline_32_full_block(torch_dev, prec):
+    torch, dev = torch_dev
+    say("case headline-32 full block", prec)
+    L, qs, mom, ref = _headline()
+    tq = [torch.from_numpy(q).to(dev) for q in qs]
+    with binding.BaryonBlocks(L, prec=prec, in_dtype="c128", max_ndil=32) as bb:
+        say("  plan", bb.get_plan(32, 32, 32, len(mom)))
+        out = bb.compute(*tq, mom)
+        bb.sync()
+    e = err_max(out[0].cpu().numpy(), ref)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+# ---------------------------------------------------------------- large
+def _large():
+    if "large" not in _cache:
+        L, n = 64, 64
+        say("  generating 64^3 fields ...")
+        qs = synth.gaussian_fields(L, (n, n, n), workload=5)
+        mom = synth.momenta("shell4")
+        ents = cover_entries(n, n, n)
+        say("  oracle: %d entries x %d momenta ..." % (len(ents), len(mom)))
+        _cache["large"] = (L, qs, mom, ents, oracle.bblock_entries(L, *qs, mom, ents))
+    return _cache["large"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_large_64_every_tile(torch_dev, prec):
+    torch, dev = torch_dev
+    say("case large-64 entries over every tile", prec)
+    L, qs, mom, ents, ref = _large()
+    tq = [torch.from_numpy(q).to(dev) for q in qs]
+    with binding.BaryonBlocks(L, prec=prec, in_dtype="c128", max_ndil=64) as bb:
+        say("  plan", bb.get_plan(64, 64, 64, len(mom)))
+        out = bb.compute(*tq, mom)
+        bb.sync()
+    idx = torch.from_numpy(ents.astype(np.int64)).to(dev)
+    got = out[0][:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    del tq, out
+    e = err_max(got, ref)
+    say("  err_max %.3e" % e)
+    assert e < TOL[prec]
+
+
+# ----------------------------------------------------- grouped workloads
+def _device_fields(torch, dev, shapes, seed):
+    """Seeded complex64 fields drawn on the device (the grouped workloads hold
+    GBs of inputs); the oracle gets the same bits copied back."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(16278 * 1000 + seed)
+    out = []
+    for shp in shapes:
+        t = torch.empty((*shp, 2), dtype=torch.float32, device=dev)
+        t.normal_(0.0, 0.5 ** 0.5, generator=g)
+        out.append(torch.view_as_complex(t))
+    return out
+
+
+def _batch_run(torch, dev, prec, L, blocks, mom, max_n):
+    outs = [torch.empty((len(mom), q1.shape[-1], q2.shape[-1], q3.shape[-1]), dtype=torch.complex128, device=dev)
+            for q1, q2, q3 in blocks]
+    with binding.BaryonBlocks(L, prec=prec, in_dtype="c64", max_ndil=max_n) as bb:
+        bb.compute_batch([(*b, o) for b, o in zip(blocks, outs)], mom)
+        bb.sync()
+    return outs
+
+
+def _batched_blocks(torch, dev):
+    L, n = 48, 32
+    V = L ** 3
+    lines = [_device_fields(torch, dev, [(V, 3, n)] * 4, seed=4800 + ln) for ln in range(3)]
+    return L, [(lines[0][s], lines[1][s], lines[2][s]) for s in range(4)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batched_48_timeslice(torch_dev, prec):
+    """48^3, N_dil 32, 27 momenta, complex64: the 4 spin triples (s, s, s) of one
+    timeslice in one grouped launch; 256 entries of every block."""
+    torch, dev = torch_dev
+    say("case batched-48 timeslice", prec)
+    L, blocks = _batched_blocks(torch, dev)
+    mom = synth.momenta("cube")
+    if "batched" not in _cache:
+        ents = cover_entries(32, 32, 32)
+        say("  oracle: 4 blocks x %d entries ..." % len(ents))
+        host = [[q.cpu().numpy().astype(np.complex128) for q in b] for b in blocks]
+        _cache["batched"] = (ents, [oracle.bblock_entries(L, *h, mom, ents) for h in host])
+    ents, refs = _cache["batched"]
+    outs = _batch_run(torch, dev, prec, L, blocks, mom, 32)
+    worst = max(err_max(pick(o.cpu().numpy(), ents), r) for o, r in zip(outs, refs))
+    say("  err_max %.3e" % worst)
+    assert worst < TOL[prec]
+
+
+def _uneven_blocks(torch, dev):
+    L = 32
+    V = L ** 3
+    triples = list(itertools.product(range(4), repeat=3))[:20]
+    blocks, fields = [], []
+    for k in range(8):
+        n = (16, 32, 64)[k % 3]
+        lines = [_device_fields(torch, dev, [(V, 3, n)] * 4, seed=3200 + 10 * k + ln) for ln in range(3)]
+        fields.append(lines)
+        for a, b, c in triples:
+            blocks.append((lines[0][a], lines[1][b], lines[2][c]))
+    return L, blocks, fields, triples
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_uneven_32_timeslice(torch_dev, prec):
+    """32^3, 7 momenta, complex64: 160 blocks (8 noise triples with N_dil 16, 32
+    or 64 x 20 spin triples) of one timeslice in one grouped launch; one whole
+    (d1, d2) row of every block against the oracle."""
+    torch, dev = torch_dev
+    say("case uneven-32 timeslice (160 blocks)", prec)
+    L, blocks, fields, triples = _uneven_blocks(torch, dev)
+    mom = synth.momenta("axis")
+    if "uneven" not in _cache:
+        say("  oracle: one row of each of 160 blocks ...")
+        host = [[[q.cpu().numpy().astype(np.complex128) for q in line] for line in lines] for lines in fields]
+        refs, ents_all = [], []
+        for k in range(8):
+            n = (16, 32, 64)[k % 3]
+            for j, (a, b, c) in enumerate(triples):
+                i = 20 * k + j
+                d1, d2 = (7 * i) % n, (3 * i + 1) % n
+                ents = np.array([(d1, d2, d3) for d3 in range(n)], dtype=np.int32)
+                ents_all.append(ents)
+                refs.append(oracle.bblock_entries(L, host[k][0][a], host[k][1][b], host[k][2][c], mom, ents))
+        _cache["uneven"] = (ents_all, refs)
+    ents_all, refs = _cache["uneven"]
+    outs = _batch_run(torch, dev, prec, L, blocks, mom, 64)
+    worst = 0.0
+    for o, ents, r in zip(outs, ents_all, refs):
+        d1, d2 = int(ents[0, 0]), int(ents[0, 1])
+        worst = max(worst, err_max(o[:, d1, d2, :].cpu().numpy(), r))
+    say("  err_max %.3e over 160 blocks" % worst)
+    assert worst < TOL[prec]

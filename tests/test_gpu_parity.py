@@ -531,37 +531,59 @@ def test_tune_times_each_candidate(torch_dev):
     assert t_tuned < 1.3 * t_default, (plan, t_default, t_tuned)
 
 
-# ---------------------------------------------------- full-size sampled
-def _sampled(torch_dev, prec, L, n, mset, dtype, rows, workload):
-    qs = synth.gaussian_fields(L, (n, n, n), workload=workload,
-                               dtype=np.complex64 if dtype == "c64" else np.complex128)
-    mom = synth.momenta(mset)
-    got = gpu_block(torch_dev, prec, L, qs, mom, dtype=dtype)
-    ref = oracle.bblock_rows(L, *qs, mom, rows)
-    sub = np.stack([got[:, d1, d2, :] for d1, d2 in rows], axis=1)
-    return err_max(sub, ref)
+# ------------------------------------------- split counts and the accuracy floor
+def test_forced_plan_respects_accuracy_floor(torch_dev):
+    """At 32^3 a split of the FP32-accumulating paths holds at most 4096 sites,
+    so at least 8 splits.  Forcing the paper-order kernel with splits = 0 at
+    N_dil 64 (1024 tiles, a wave-filling count of one split) resolves to at
+    least 8 splits; an explicit count below 8 is refused; the forced plan's
+    block matches the oracle on sampled entries."""
+    torch, dev = torch_dev
+    L, n = 32, 64
+    mom = synth.momenta("shell4")
+    say("case forced plan, accuracy floor")
+    qs = synth.gaussian_fields(L, (n, n, n), workload=130)
+    with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=64) as bb:
+        bb.set_plan(n, n, n, len(mom), dict(kernel=3, nb=2, splits=0, persistent=0))
+        plan = bb.get_plan(n, n, n, len(mom))
+        say("  plan", plan)
+        assert plan["kernel"] == 3 and plan["splits"] >= 8
+        for bad in (1, 7):
+            with pytest.raises(binding.BBlockError) as ei:
+                bb.set_plan(n, n, n, len(mom), dict(kernel=3, nb=2, splits=bad, persistent=0))
+            assert ei.value.status == 1
+        out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
+        bb.sync()
+    g = np.random.default_rng(5)
+    ents = np.stack([g.integers(0, n, 48) for _ in range(3)], axis=1).astype(np.int32)
+    ref = oracle.bblock_entries(L, *qs, mom, ents)
+    got = out[0].cpu().numpy()[:, ents[:, 0], ents[:, 1], ents[:, 2]]
+    assert err_max(got, ref) < TOL["bf16x3"]
 
 
-ROWS32 = np.array([[0, 0], [0, 31], [31, 0], [31, 31], [7, 19], [16, 16], [3, 28], [25, 9]], dtype=np.int32)
-
-
-@pytest.mark.parametrize("prec", PRECS)
-def test_headline_32_sampled(torch_dev, prec):
-    """32^3 sites, N_dil = 32, 7 momenta, c128: the benchmarked workload and plan."""
-    say("case headline-32 sampled", prec)
-    e = _sampled(torch_dev, prec, 32, 32, "axis", "c128", ROWS32, workload=2)
-    say("  err_max %.3e" % e)
-    assert e < TOL[prec]
-
-
-@pytest.mark.parametrize("prec", ("fp64", "bf16x3"))
-def test_large_64_sampled(torch_dev, prec):
-    """64^3 sites, N_dil = 64, 33 momenta, c128 (one timeslice), sampled rows."""
-    rows = np.array([[0, 0], [63, 63], [12, 50], [40, 7]], dtype=np.int32)
-    say("case large-64 sampled", prec)
-    e = _sampled(torch_dev, prec, 64, 64, "shell4", "c128", rows, workload=5)
-    say("  err_max %.3e" % e)
-    assert e < TOL[prec]
+def test_single_block_splits_in_whole_waves(torch_dev):
+    """32^3, N_dil 48, 7 momenta, BF16X3: the default plan's split count is
+    raised to the accuracy floor (8) in whole multiples of the wave-filling
+    count (kernel 4 at N_dil 48: d2 blocks of 16, d3 blocks of 24, 6 column
+    fragments -> 18 x 2 = 36 tiles per split, floor(256 / 36) = 7 -> 14
+    splits); sampled entries against the oracle."""
+    torch, dev = torch_dev
+    L, n = 32, 48
+    mom = synth.momenta("axis")
+    say("case single-block split rounding")
+    qs = synth.gaussian_fields(L, (n, n, n), workload=131)
+    with binding.BaryonBlocks(L, prec="bf16x3", in_dtype="c128", max_ndil=64) as bb:
+        plan = bb.get_plan(n, n, n, len(mom))
+        say("  plan", plan)
+        assert plan["kernel"] == 4 and plan["nb"] == 6
+        assert plan["splits"] >= 8 and plan["splits"] % 7 == 0
+        out = bb.compute(*[torch.from_numpy(q).to(dev) for q in qs], mom)
+        bb.sync()
+    g = np.random.default_rng(6)
+    ents = np.stack([g.integers(0, n, 64) for _ in range(3)], axis=1).astype(np.int32)
+    ref = oracle.bblock_entries(L, *qs, mom, ents)
+    got = out[0].cpu().numpy()[:, ents[:, 0], ents[:, 1], ents[:, 2]]
+    assert err_max(got, ref) < TOL["bf16x3"]
 
 
 # --------------------------------------------------------- error paths
@@ -594,54 +616,3 @@ def test_error_paths_enqueue_nothing(torch_dev):
         assert torch.all(out == 7.0).item()
     finally:
         binding.bblock_destroy(h)
-
-
-# ------------------------------------------- grouped workloads at full block size
-def _sampled_batch_check(torch_dev, prec, L, dtype, blocks, mom, rows_per_block=2, seed=7):
-    """blocks: list of (q1, q2, q3) numpy fields; one grouped launch, sampled rows vs oracle."""
-    torch, dev = torch_dev
-    g = np.random.default_rng(seed)
-    tq = [[torch.from_numpy(q).to(dev) for q in trip] for trip in blocks]
-    outs = [torch.empty((len(mom), *(q.shape[-1] for q in trip)), dtype=torch.complex128, device=dev)
-            for trip in blocks]
-    max_n = max(max(q.shape[-1] for q in trip) for trip in blocks)
-    with binding.BaryonBlocks(L, prec=prec, in_dtype=dtype, max_ndil=max_n) as bb:
-        bb.compute_batch([(*t, o) for t, o in zip(tq, outs)], mom)
-        bb.sync()
-    worst = 0.0
-    for trip, o in zip(blocks, outs):
-        n1, n2 = trip[0].shape[-1], trip[1].shape[-1]
-        rows = np.stack([g.integers(0, n1, rows_per_block), g.integers(0, n2, rows_per_block)], axis=1)
-        got = o.cpu().numpy()
-        sub = np.stack([got[:, d1, d2, :] for d1, d2 in rows], axis=1)
-        worst = max(worst, err_max(sub, oracle.bblock_rows(L, *trip, mom, rows.astype(np.int32))))
-    return worst
-
-
-@pytest.mark.parametrize("prec", ("bf16x3", "fp32"))
-def test_batched_48_sampled(torch_dev, prec):
-    """48^3 sites, N_dil = 32, 27 momenta, complex64: 4 spin triples of one
-    timeslice in one grouped launch (the batched workload's block shape)."""
-    L, n = 48, 32
-    lines = [[synth.gaussian_field(L, n, workload=3, role=ln, spin=s, dtype=np.complex64) for s in range(2)]
-             for ln in range(3)]
-    blocks = [(lines[0][a], lines[1][b], lines[2][c]) for (a, b, c) in ((0, 0, 0), (1, 1, 1), (0, 1, 0))]
-    say("case batched-48 sampled", prec)
-    e = _sampled_batch_check(torch_dev, prec, L, "c64", blocks, synth.momenta("cube"))
-    say("  err_max %.3e" % e)
-    assert e < TOL[prec]
-
-
-@pytest.mark.parametrize("prec", ("bf16x3", "fp64"))
-def test_uneven_32_sampled(torch_dev, prec):
-    """32^3 sites, 7 momenta, complex64: noise triples with N_dil 16, 32 and 64
-    mixed in one grouped launch (the uneven workload's block shapes)."""
-    L = 32
-    blocks = []
-    for k, n in enumerate((16, 32, 64)):
-        trip = [synth.gaussian_field(L, n, workload=4, t=k, role=ln, dtype=np.complex64) for ln in range(3)]
-        blocks.append(tuple(trip))
-    say("case uneven-32 sampled", prec)
-    e = _sampled_batch_check(torch_dev, prec, L, "c64", blocks, synth.momenta("axis"))
-    say("  err_max %.3e" % e)
-    assert e < TOL[prec]
