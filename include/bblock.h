@@ -139,6 +139,27 @@ bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const v
                              const int32_t *mom, int32_t n_mom,
                              int32_t t_begin, int32_t t_end, void *B);
 
+/* bblock_compute for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and plans as bblock_compute, but the call
+ * allocates nothing: its tables, phase-index table and split-K workspace
+ * live in a static device array of BBLOCK_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends (1 MiB of
+ * tables, then n_mom * L^3 bytes of phase indices, then the workspace), and
+ * the tables go up through a pinned buffer allocated by bblock_create.  The
+ * planner fits the plan into what remains of the array (fewer splits, or the
+ * kernel that builds W in LDS instead of workspace images); a batch that
+ * still does not fit returns BBLOCK_ENOMEM with the sizes in the message.
+ * Launches are eager (no graph), nothing is cached between calls, and the
+ * array is shared by every call and handle on the device: calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by
+ * the caller. */
+#define BBLOCK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+bblock_status bblock_compute_noalloc(bblock_t h, const void *Q1, const void *Q2, const void *Q3,
+                                     int32_t n1, int32_t n2, int32_t n3,
+                                     const int32_t *mom, int32_t n_mom,
+                                     int32_t t_begin, int32_t t_end, void *B);
+
 /* Many eq. (3) blocks in one grouped launch (paper, Sec. 2 after eq. (3):
  * the kernel is evaluated for many noise and spin combinations per
  * timeslice with the same momentum set; Sec. 3: independent blocks run in

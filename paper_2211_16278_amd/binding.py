@@ -24,7 +24,7 @@ STATUS = {0: "BBLOCK_OK", 1: "BBLOCK_EINVAL", 2: "BBLOCK_ENOMEM", 3: "BBLOCK_EHI
           5: "BBLOCK_EUNSUPPORTED"}
 
 # Every symbol include/bblock.h declares.
-EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_batch", "bblock_compute_projected",
+EXPORTS = ("bblock_create", "bblock_compute", "bblock_compute_noalloc", "bblock_compute_batch", "bblock_compute_projected",
            "bblock_reconstruct", "bblock_mode_triplets", "bblock_mode_contract", "bblock_mode_contract_batch",
            "bblock_set_graph", "bblock_tune",
            "bblock_set_plan", "bblock_get_plan", "bblock_profile", "bblock_profile_read", "bblock_sync",
@@ -66,6 +66,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "bblock_create": ([ctypes.POINTER(h), i32, i32, i32, i32, ctypes.c_size_t, vp], ctypes.c_int),
         "bblock_compute": ([h, vp, vp, vp, i32, i32, i32, ip, i32, i32, i32, vp], ctypes.c_int),
+        "bblock_compute_noalloc": ([h, vp, vp, vp, i32, i32, i32, ip, i32, i32, i32, vp], ctypes.c_int),
         "bblock_compute_batch": ([h, ctypes.POINTER(bblock_desc), i32, ip, i32], ctypes.c_int),
         "bblock_compute_projected": ([h, ctypes.POINTER(bblock_desc), ctypes.POINTER(ctypes.c_double), i32, ip, i32],
                                      ctypes.c_int),
@@ -119,6 +120,12 @@ def bblock_compute(h, Q1, Q2, Q3, n1, n2, n3, mom, t_begin, t_end, B):
     m, mp = _momenta(mom)
     _check(h, load().bblock_compute(h, _ptr(Q1), _ptr(Q2), _ptr(Q3), n1, n2, n3, mp, m.shape[0], t_begin, t_end,
                                     _ptr(B)))
+
+
+def bblock_compute_noalloc(h, Q1, Q2, Q3, n1, n2, n3, mom, t_begin, t_end, B):
+    m, mp = _momenta(mom)
+    _check(h, load().bblock_compute_noalloc(h, _ptr(Q1), _ptr(Q2), _ptr(Q3), n1, n2, n3, mp, m.shape[0], t_begin,
+                                            t_end, _ptr(B)))
 
 
 def _descs(descs):
@@ -243,6 +250,14 @@ class BaryonBlocks:
         if out is None:
             out = torch.empty(shape, dtype=torch.complex128, device=q1.device)
         bblock_compute(self.h, q1, q2, q3, q1.shape[-1], q2.shape[-1], q3.shape[-1], m, t_begin, t_end, out)
+        return out
+
+    def compute_noalloc(self, q1, q2, q3, mom, out, t_begin: int = 0, t_end: int | None = None):
+        """compute() through the allocation-free entry point; out must be given."""
+        q1, q2, q3 = (q if q.dim() == 4 else q.unsqueeze(0) for q in (q1, q2, q3))
+        t_end = q1.shape[0] if t_end is None else t_end
+        m = np.asarray(mom, dtype=np.int32).reshape(-1, 3)
+        bblock_compute_noalloc(self.h, q1, q2, q3, q1.shape[-1], q2.shape[-1], q3.shape[-1], m, t_begin, t_end, out)
         return out
 
     def compute_batch(self, descs, mom):

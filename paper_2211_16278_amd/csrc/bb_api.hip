@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,11 @@
 #include "bb_internal.h"
 
 using namespace bb;
+
+// Size of the static device scratch array of the allocation-free entry point.
+constexpr size_t SCRATCH_BYTES = BBLOCK_NOALLOC_SCRATCH_BYTES;
+static_assert(SCRATCH_BYTES % 4096 == 0, "scratch regions are 4 KiB aligned");
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
 namespace {
 
@@ -68,6 +74,43 @@ struct SubBatch {
 // Device table regions of a batch.
 enum TableRegion { T_BLOCKS, T_TILES, T_LIST, T_MOM, T_WENT, T_CMEM, T_CCOEF, T_CGS, T_CACC, T_COUNT };
 
+// Device scratch of the allocation-free entry point (bblock_compute_noalloc):
+// tables, phase-index table and split-K workspace of one call, laid out
+//   [0, SCRATCH_TABLE)                      descriptor, tile and reduce tables
+//   [SCRATCH_TABLE, + kidx bytes)           phase-index table (4 KiB aligned)
+//   [then, SCRATCH_BYTES)                   split partials and W images
+// Host code never uses the array's name as an address: each device's copy
+// is found with hipGetSymbolAddress once, at create, with that device
+// current.
+constexpr size_t SCRATCH_TABLE = (size_t)1 << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_addr[SCRATCH_MAX_DEVICES] = {};
+
+// Address of the scratch array on device dev (current), looked up once.
+hipError_t scratch_address(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+// Device memory one batch runs in: the handle's allocations, or regions of
+// the static scratch array.
+struct Mem {
+    unsigned char *table;
+    void *ws;
+    unsigned char *kidx;
+};
+
 }  // namespace
 
 struct bblock_s {
@@ -75,6 +118,7 @@ struct bblock_s {
     int L = 0, V = 0;
     int prec = 0, in_dtype = 0, max_ndil = 0;
     size_t ws_cap = 0;
+    size_t ws_eff = 0;                // workspace cap of the batch being planned
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     int num_cu = 256;
@@ -92,6 +136,12 @@ struct bblock_s {
     unsigned char *d_kidx = nullptr;  // [n_mom][V] phase index of the cached momentum set
     size_t kidx_cap = 0;
     std::vector<int> kidx_mom;        // momentum set (reduced mod L) the table holds
+    // Allocation-free entry point: this device's static scratch array (its
+    // device address, looked up at create) and a pinned staging buffer for
+    // its tables, allocated at create.
+    unsigned char *scratch = nullptr;
+    unsigned char *h_static = nullptr;
+    hipEvent_t static_free = nullptr;
 
     int graph_mode = 2;               // 0: eager, 1: capture and replay, 2: replay schedules of 4+ launches
     bool profiling = false;
@@ -360,7 +410,7 @@ void set_splits(bblock_t h, BlockPlan &bp, int S)
         // of as many splits as fit (at least one; 0 = does not fit).
         const size_t per_split = (size_t)bp.g.n_nt * bp.d.cps * w3_image_bytes(bp.plan.nb);
         const size_t part = align_up(bp.part_bytes, 4096);
-        const size_t room = h->ws_cap > part ? h->ws_cap - part : 0;
+        const size_t room = h->ws_eff > part ? h->ws_eff - part : 0;
         bp.spr = (int)std::min<size_t>(bp.d.S, room / per_split);
         bp.rounds = bp.spr > 0 ? (bp.d.S + bp.spr - 1) / bp.spr : 1;
         bp.ws_bytes = part + (size_t)std::max(bp.spr, 1) * per_split;
@@ -457,30 +507,31 @@ hipEvent_t take_event(bblock_t h)
 }
 
 // Launch the kernels of all sub-batches on stream st; tables already uploaded.
-bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_t *offs, int n_mom, hipStream_t st)
+bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &subs, const size_t *offs, int n_mom,
+                      hipStream_t st)
 {
     const size_t off_blocks = offs[T_BLOCKS], off_tiles = offs[T_TILES], off_list = offs[T_LIST];
     const size_t off_mom = offs[T_MOM], off_went = offs[T_WENT];
     for (const SubBatch &sb : subs) {
         GemmArgs ga;
-        ga.blocks = reinterpret_cast<const BlockDesc *>(h->d_table + off_blocks);
-        ga.tiles = reinterpret_cast<const int4 *>(h->d_table + off_tiles) + sb.tile_off;
+        ga.blocks = reinterpret_cast<const BlockDesc *>(mem.table + off_blocks);
+        ga.tiles = reinterpret_cast<const int4 *>(mem.table + off_tiles) + sb.tile_off;
         ga.n_tiles = sb.n_tiles;
         ga.counter = sb.persistent ? h->d_counter : nullptr;
-        ga.mom = reinterpret_cast<const int *>(h->d_table + off_mom);
+        ga.mom = reinterpret_cast<const int *>(mem.table + off_mom);
         ga.n_mom = n_mom;
         ga.L = h->L;
         ga.V = h->V;
         ga.in_c64 = h->in_dtype == BBLOCK_C64;
         ga.roots = h->d_roots;
-        ga.kidx = h->d_kidx;
+        ga.kidx = mem.kidx;
         ga.kstride = kstride_of(h);
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
         if (is_w3(sb.kernel)) {
             WImageArgs wa;
             wa.blocks = ga.blocks;
-            wa.entries = reinterpret_cast<const int4 *>(h->d_table + off_went) + sb.went_off;
+            wa.entries = reinterpret_cast<const int4 *>(mem.table + off_went) + sb.went_off;
             wa.n_entries = sb.n_went;
             wa.mom = ga.mom;
             wa.n_mom = n_mom;
@@ -517,10 +568,10 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
         if (sb.n_cg > 0) {
             CombineArgs ca;
             ca.blocks = ga.blocks;
-            ca.list = reinterpret_cast<const int *>(h->d_table + offs[T_CMEM]);
-            ca.coef = reinterpret_cast<const double *>(h->d_table + offs[T_CCOEF]);
-            ca.gstart = reinterpret_cast<const int *>(h->d_table + offs[T_CGS]) + sb.cgs_off;
-            ca.accumulate = reinterpret_cast<const int *>(h->d_table + offs[T_CACC]) + sb.cg_off;
+            ca.list = reinterpret_cast<const int *>(mem.table + offs[T_CMEM]);
+            ca.coef = reinterpret_cast<const double *>(mem.table + offs[T_CCOEF]);
+            ca.gstart = reinterpret_cast<const int *>(mem.table + offs[T_CGS]) + sb.cgs_off;
+            ca.accumulate = reinterpret_cast<const int *>(mem.table + offs[T_CACC]) + sb.cg_off;
             ca.n_groups = sb.n_cg;
             if (h->profiling) {
                 ev = {take_event(h), take_event(h)};
@@ -537,7 +588,7 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
         if (sb.n_list > 0) {
             ReduceArgs ra;
             ra.blocks = ga.blocks;
-            ra.list = reinterpret_cast<const int *>(h->d_table + off_list) + sb.list_off;
+            ra.list = reinterpret_cast<const int *>(mem.table + off_list) + sb.list_off;
             ra.n_list = sb.n_list;
             if (h->profiling) {
                 ev = {take_event(h), take_event(h)};
@@ -557,9 +608,10 @@ bblock_status enqueue(bblock_t h, const std::vector<SubBatch> &subs, const size_
 
 // Launch a planned batch whose tables are on the device: eagerly, or by
 // replaying (capturing on first use) the graph of this batch structure.
-bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, const size_t *offs, int n_mom)
+bblock_status launch_planned(bblock_t h, const Mem &mem, const std::vector<SubBatch> &subs, const size_t *offs,
+                             int n_mom, bool eager)
 {
-    if (h->graph_mode == 0 || h->profiling) return enqueue(h, subs, offs, n_mom, h->stream);
+    if (eager || h->graph_mode == 0 || h->profiling) return enqueue(h, mem, subs, offs, n_mom, h->stream);
     if (h->graph_mode == 2) {
         // A replayed graph separates its kernels by more idle time than eager
         // launches on one stream (≈1 % of a single-block call); it pays only
@@ -567,7 +619,7 @@ bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, cons
         int launches = 0;
         for (const SubBatch &sb : subs)
             launches += 1 + is_w3(sb.kernel) + (sb.n_cg > 0) + (sb.n_list > 0);
-        if (launches < 4) return enqueue(h, subs, offs, n_mom, h->stream);
+        if (launches < 4) return enqueue(h, mem, subs, offs, n_mom, h->stream);
     }
     // Graph signature: everything baked into kernel arguments.
     std::vector<long long> sig;
@@ -583,7 +635,7 @@ bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, cons
     auto it = h->graphs.find(sig);
     if (it == h->graphs.end()) {
         HIP_OR_FAIL(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        bblock_status st = enqueue(h, subs, offs, n_mom, h->cap_stream);
+        bblock_status st = enqueue(h, mem, subs, offs, n_mom, h->cap_stream);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
         if (st != BBLOCK_OK) {
@@ -605,8 +657,15 @@ bblock_status launch_planned(bblock_t h, const std::vector<SubBatch> &subs, cons
 // coef == nullptr: every descriptor's block is written to its out.  Else
 // (spin projection) descriptors sharing an out pointer form one output group
 // and out = sum of coef_i * B_i over the group.
+//
+// noalloc: the allocation-free form.  Tables, phase-index table and
+// workspace live in the device's static scratch array instead of the
+// handle's allocations, the tables go up through the pinned buffer
+// allocated at create, launches are eager (a graph instantiation
+// allocates), and nothing is cached across calls (the scratch array is
+// shared by every call on the device).
 bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const int32_t *mom, int n_mom,
-                        const double *coef = nullptr)
+                        const double *coef = nullptr, bool noalloc = false)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
     if (!desc || n_desc < 1) return fail(h, BBLOCK_EINVAL, "empty batch");
@@ -654,9 +713,23 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         const int tail[4] = {h->plan_gen, n_mom, n_desc, coef ? 1 : 0};
         std::memcpy(kp, tail, sizeof tail);
     }
-    if (key == h->last_key && !h->last_subs.empty())
-        return launch_planned(h, h->last_subs, h->last_offs, n_mom);
-    h->last_key.clear();
+    // The allocation-free form: the phase-index table after the tables, the
+    // workspace in the rest of the scratch array.
+    size_t s_kidx_off = 0, s_ws_off = 0;
+    if (noalloc) {
+        if (!h->scratch || !h->h_static) return fail(h, BBLOCK_EHIP, "no static scratch on this device");
+        s_kidx_off = SCRATCH_TABLE;
+        s_ws_off = align_up(s_kidx_off + (size_t)n_mom * kstride_of(h), 4096);
+        if (s_ws_off >= SCRATCH_BYTES)
+            return fail(h, BBLOCK_ENOMEM, "the phase-index table of %d momenta at L=%d (%zu bytes) exceeds the static "
+                        "scratch of %zu bytes", n_mom, h->L, (size_t)n_mom * kstride_of(h), SCRATCH_BYTES);
+        h->ws_eff = std::min(h->ws_cap, SCRATCH_BYTES - s_ws_off);
+    } else {
+        if (key == h->last_key && !h->last_subs.empty())
+            return launch_planned(h, Mem{h->d_table, h->d_ws, h->d_kidx}, h->last_subs, h->last_offs, n_mom, false);
+        h->last_key.clear();
+        h->ws_eff = h->ws_cap;
+    }
 
     // Plans, geometry and split counts per block.
     const int s_min = min_splits(h);
@@ -698,14 +771,14 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             S = std::max<int>(s_min, (int)std::max<long>(1, 2L * h->num_cu / std::max(1L, total_tiles_s1)));
         bp.need_part = coef != nullptr;
         set_splits(h, bp, S);
-        if (!fixed && bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
-        if (is_w3(bp.plan.kernel) && (bp.ws_bytes > h->ws_cap || !w3_offsets_fit(h, bp))) {
+        if (!fixed && bp.ws_bytes > h->ws_eff) set_splits(h, bp, s_min);
+        if (is_w3(bp.plan.kernel) && (bp.ws_bytes > h->ws_eff || !w3_offsets_fit(h, bp))) {
             // Not even one split's W images fit beside the partials (or the
             // split is too long for 32-bit offsets): the pipelined kernel
             // builds W in LDS instead.
             if (h->forced.count(k))
                 return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the precomputed-W plan needs %zu workspace bytes "
-                            "(cap %zu) and splits of at most 2 GiB of q1/q2", i, bp.ws_bytes, h->ws_cap);
+                            "(cap %zu) and splits of at most 2 GiB of q1/q2", i, bp.ws_bytes, h->ws_eff);
             // Its column fragments: 7 or 4, whichever pads fewer columns.
             bp.plan.kernel = K_PIPELINED;
             bp.g = Geometry{};
@@ -717,7 +790,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             if (bp.g.lds < 0) return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
             take_geometry(bp);
             set_splits(h, bp, S);
-            if (bp.ws_bytes > h->ws_cap) set_splits(h, bp, s_min);
+            if (bp.ws_bytes > h->ws_eff) set_splits(h, bp, s_min);
         }
         if (bp.plan.kernel == K_PORD && !w3_offsets_fit(h, bp)) {
             if (h->forced.count(k))
@@ -730,8 +803,9 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             take_geometry(bp);
             set_splits(h, bp, S);
         }
-        if (bp.ws_bytes > h->ws_cap)
-            return fail(h, BBLOCK_ENOMEM, "block %d needs %zu workspace bytes, cap is %zu", i, bp.ws_bytes, h->ws_cap);
+        if (bp.ws_bytes > h->ws_eff)
+            return fail(h, BBLOCK_ENOMEM, "block %d needs %zu workspace bytes, cap is %zu%s", i, bp.ws_bytes, h->ws_eff,
+                        noalloc ? " (what the static scratch of the allocation-free entry point leaves for it)" : "");
     }
 
     // Work units: (block, round).  Every block is one unit, except a
@@ -789,7 +863,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         while (u < units.size()) {
             const BlockPlan &bp = bps[units[u].b];
             if (u > u0 && (bp.rounds > 1 || b0.rounds > 1)) break;
-            if (!same_kernel(bp, sb) || used + bp.ws_bytes > h->ws_cap) break;
+            if (!same_kernel(bp, sb) || used + bp.ws_bytes > h->ws_eff) break;
             if (is_w3(sb.kernel)) {  // image entries form the y dimension of one launch
                 const long e = (long)bp.g.n_nt * bp.spr;
                 if (u > u0 && n_went + e > 65535) break;
@@ -885,14 +959,15 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         }
         subs.push_back(sb);
     }
-    {
+    if (!noalloc) {
         bblock_status st = ensure_ws(h, ws_need);
         if (st != BBLOCK_OK) return st;
     }
+    void *ws_base = noalloc ? static_cast<void *>(h->scratch + s_ws_off) : h->d_ws;
     for (const Unit &un : units) {
         BlockPlan &bp = bps[un.b];
         BlockDesc d = bp.d;
-        unsigned char *base = static_cast<unsigned char *>(h->d_ws) + ws_off[un.d];
+        unsigned char *base = static_cast<unsigned char *>(ws_base) + ws_off[un.d];
         d.ws = bp.part_bytes ? base : nullptr;
         d.wimg = is_w3(bp.plan.kernel) ? base + align_up(bp.part_bytes, 4096) : nullptr;
         d.img_s0 = un.r * bp.spr;
@@ -912,12 +987,18 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     const size_t off_cgs = align_up(off_ccoef + sizeof(double) * std::max<size_t>(2, ccoef.size()), 256);
     const size_t off_cacc = align_up(off_cgs + sizeof(int) * std::max<size_t>(1, cgs.size()), 256);
     const size_t bytes = align_up(off_cacc + sizeof(int) * std::max<size_t>(1, cacc.size()), 256);
-    {
+    if (noalloc) {
+        if (bytes > SCRATCH_TABLE)
+            return fail(h, BBLOCK_ENOMEM, "the batch's tables (%zu bytes) exceed the %zu bytes the static scratch holds "
+                        "for them", bytes, SCRATCH_TABLE);
+    } else {
         bblock_status st = ensure_table(h, bytes);
         if (st != BBLOCK_OK) return st;
     }
-    HIP_OR_FAIL(h, hipEventSynchronize(h->staging_free));  // previous upload has left the staging buffer
-    unsigned char *hs = h->h_staging;
+    const Mem mem = noalloc ? Mem{h->scratch, ws_base, h->scratch + s_kidx_off} : Mem{h->d_table, h->d_ws, nullptr};
+    hipEvent_t upload_done = noalloc ? h->static_free : h->staging_free;
+    HIP_OR_FAIL(h, hipEventSynchronize(upload_done));  // previous upload has left the staging buffer
+    unsigned char *hs = noalloc ? h->h_static : h->h_staging;
     std::memcpy(hs + off_blocks, descs.data(), sizeof(BlockDesc) * descs.size());
     if (!tiles.empty()) std::memcpy(hs + off_tiles, tiles.data(), sizeof(int4) * tiles.size());
     if (!list.empty()) std::memcpy(hs + off_list, list.data(), sizeof(int) * list.size());
@@ -927,8 +1008,18 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     if (!ccoef.empty()) std::memcpy(hs + off_ccoef, ccoef.data(), sizeof(double) * ccoef.size());
     if (!cgs.empty()) std::memcpy(hs + off_cgs, cgs.data(), sizeof(int) * cgs.size());
     if (!cacc.empty()) std::memcpy(hs + off_cacc, cacc.data(), sizeof(int) * cacc.size());
-    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_table, hs, bytes, hipMemcpyHostToDevice, h->stream));
-    HIP_OR_FAIL(h, hipEventRecord(h->staging_free, h->stream));
+    HIP_OR_FAIL(h, hipMemcpyAsync(mem.table, hs, bytes, hipMemcpyHostToDevice, h->stream));
+    HIP_OR_FAIL(h, hipEventRecord(upload_done, h->stream));
+    if (noalloc) {
+        // Rebuilt on every call: another call may have overwritten it.
+        if (any_pipelined) {
+            const hipError_t e = launch_phase_index(reinterpret_cast<const int *>(mem.table + off_mom), n_mom, h->L,
+                                                    kstride_of(h), mem.kidx, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "launch of the phase-index kernel");
+        }
+        size_t offs[T_COUNT] = {off_blocks, off_tiles, off_list, off_mom, off_went, off_cmem, off_ccoef, off_cgs, off_cacc};
+        return launch_planned(h, mem, subs, offs, n_mom, true);
+    }
     if (any_pipelined) {
         bblock_status st = ensure_kidx(h, mom_red, reinterpret_cast<const int *>(h->d_table + off_mom));
         if (st != BBLOCK_OK) return st;
@@ -945,7 +1036,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     h->last_offs[T_CCOEF] = off_ccoef;
     h->last_offs[T_CGS] = off_cgs;
     h->last_offs[T_CACC] = off_cacc;
-    return launch_planned(h, subs, h->last_offs, n_mom);
+    return launch_planned(h, Mem{h->d_table, h->d_ws, h->d_kidx}, subs, h->last_offs, n_mom, false);
 }
 
 // ---------------------------------------------------------------- tuner ---
@@ -1035,6 +1126,14 @@ bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_d
         return bail(BBLOCK_EHIP, "roots upload");
     if (hipMalloc(&h->d_counter, 2 * sizeof(int)) != hipSuccess) return bail(BBLOCK_ENOMEM, "counter allocation");
     if (hipMemset(h->d_counter, 0, 2 * sizeof(int)) != hipSuccess) return bail(BBLOCK_EHIP, "counter reset");
+    // The allocation-free entry point: this device's scratch array (looked up
+    // once per device, with the device current) and the pinned buffer its
+    // tables go up through.
+    if (scratch_address(dev, &h->scratch) != hipSuccess) return bail(BBLOCK_EHIP, "static scratch lookup");
+    if (hipHostMalloc(&h->h_static, SCRATCH_TABLE, hipHostMallocDefault) != hipSuccess)
+        return bail(BBLOCK_ENOMEM, "pinned staging allocation");
+    if (hipEventCreateWithFlags(&h->static_free, hipEventDisableTiming) != hipSuccess)
+        return bail(BBLOCK_EHIP, "event creation failed");
 
     // Tuned plans persisted by earlier runs.
     if (const char *path = std::getenv("BBLOCK_TUNE_CACHE")) {
@@ -1053,8 +1152,13 @@ bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_d
     return BBLOCK_OK;
 }
 
-bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const void *Q3, int32_t n1, int32_t n2,
-                             int32_t n3, const int32_t *mom, int32_t n_mom, int32_t t_begin, int32_t t_end, void *B)
+}  // extern "C"
+
+namespace {
+
+bblock_status compute_range(bblock_t h, const void *Q1, const void *Q2, const void *Q3, int32_t n1, int32_t n2,
+                            int32_t n3, const int32_t *mom, int32_t n_mom, int32_t t_begin, int32_t t_end, void *B,
+                            bool noalloc)
 {
     if (!h) return fail(h, BBLOCK_EINVAL, "null handle");
     if (t_begin < 0 || t_end <= t_begin) return fail(h, BBLOCK_EINVAL, "empty or negative timeslice range [%d,%d)", t_begin, t_end);
@@ -1076,7 +1180,24 @@ bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const v
         d[i].reserved = 0;
         d[i].out = static_cast<unsigned char *>(B) + (size_t)i * n_mom * n1 * n2 * n3 * 16;
     }
-    return run_batch(h, d.data(), nt, mom, n_mom);
+    return run_batch(h, d.data(), nt, mom, n_mom, nullptr, noalloc);
+}
+
+}  // namespace
+
+extern "C" {
+
+bblock_status bblock_compute(bblock_t h, const void *Q1, const void *Q2, const void *Q3, int32_t n1, int32_t n2,
+                             int32_t n3, const int32_t *mom, int32_t n_mom, int32_t t_begin, int32_t t_end, void *B)
+{
+    return compute_range(h, Q1, Q2, Q3, n1, n2, n3, mom, n_mom, t_begin, t_end, B, false);
+}
+
+bblock_status bblock_compute_noalloc(bblock_t h, const void *Q1, const void *Q2, const void *Q3, int32_t n1,
+                                     int32_t n2, int32_t n3, const int32_t *mom, int32_t n_mom, int32_t t_begin,
+                                     int32_t t_end, void *B)
+{
+    return compute_range(h, Q1, Q2, Q3, n1, n2, n3, mom, n_mom, t_begin, t_end, B, true);
 }
 
 bblock_status bblock_compute_batch(bblock_t h, const bblock_desc *desc, int32_t n_desc, const int32_t *mom, int32_t n_mom)
@@ -1548,7 +1669,7 @@ bblock_status bblock_sync(bblock_t h)
 bblock_status bblock_destroy(bblock_t h)
 {
     if (!h) return BBLOCK_OK;
-    if (h->d_table || h->d_roots) (void)hipStreamSynchronize(h->stream);
+    if (h->d_table || h->d_roots || h->h_static) (void)hipStreamSynchronize(h->stream);
     clear_graphs(h);
     if (h->d_ws) (void)hipFree(h->d_ws);
     if (h->d_table) (void)hipFree(h->d_table);
@@ -1557,6 +1678,8 @@ bblock_status bblock_destroy(bblock_t h)
     if (h->d_roots) (void)hipFree(h->d_roots);
     if (h->d_counter) (void)hipFree(h->d_counter);
     if (h->staging_free) (void)hipEventDestroy(h->staging_free);
+    if (h->h_static) (void)hipHostFree(h->h_static);
+    if (h->static_free) (void)hipEventDestroy(h->static_free);
     for (auto &ev : h->ev_gemm) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
     for (auto &ev : h->ev_reduce) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
     for (auto &ev : h->ev_prep) h->ev_pool.insert(h->ev_pool.end(), ev.begin(), ev.end());
