@@ -39,6 +39,8 @@ PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 def kernel_name(path, plan, n2, n3):
     """Name of the contraction kernel a plan launches (as rocprofv3 lists it)."""
+    if plan["kernel"] == 5:
+        return "bb::f64::contract<%d, false>" % plan["nb"]
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
         return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)
@@ -67,6 +69,7 @@ KERNEL_SOURCES = {
     "bb::fast::": ("bb_fast.h", "bb_fast_fp32.hip", "bb_fast_bf16.hip", "bb_internal.h"),
     "bb::pord::": ("bb_pord.hip", "bb_fast.h", "bb_internal.h"),
     "bb::bb_gemm": ("bb_kernels.hip", "bb_internal.h"),
+    "bb::f64::": ("bb_f64.hip", "bb_internal.h"),
 }
 
 
@@ -80,11 +83,17 @@ def sources_of(kname: str):
 def mfma_flops_executed(path, plan, f_gemm):
     """Matrix-core flops one headline launch executes: the fused complex GEMM
     (F_gemm = 24 n_mom V n^3, 8 real flops per complex multiply-add), three
-    times over for the three BF16 products of BF16x3."""
+    times over for the three BF16 products of BF16x3; the FP64 kernel 5 forms
+    each complex product from three real products (6 real flops per complex
+    multiply-add), 3/4 of F_gemm."""
+    if plan["kernel"] == 5:
+        return 0.75 * f_gemm
     return MFMA_PASSES[path] * f_gemm
 
 
 def flops_note(path, plan):
+    if plan["kernel"] == 5:
+        return "18 n_mom V n^3: three real products per complex multiply-add"
     return "%d x 24 n_mom V n^3" % MFMA_PASSES[path]
 
 
@@ -147,7 +156,7 @@ def mfma_flops(plan, V, n1, n2, n3, n_mom):
     fused GEMM (kernels 0-2, 24 n_mom V n1 n2 n3) or, for the paper-order
     kernel 3, only the momentum projection (8 n_mom V n1 n2 n3; its singlet
     runs on the vector unit)."""
-    per = 8.0 if plan["kernel"] == 3 else 24.0
+    per = 8.0 if plan["kernel"] == 3 else (18.0 if plan["kernel"] == 5 else 24.0)
     return per * n_mom * V * n1 * n2 * n3
 
 

@@ -36,7 +36,7 @@ thread_local std::string g_create_error;
 
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
-constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4;
+constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, K_F64 = 5;
 // Kernel 2 and its eight-wave form 4 share geometry, images and workspace.
 inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 
@@ -248,6 +248,17 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_mt = cdiv(n1, g.b1) * g.n_mt2;
         g.n_nt = cdiv(n_mom, g.bp) * g.n_nt3;
         g.lds = is_w3(kernel) ? w3_lds_bytes(nb, g.b2) : fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
+    } else if (kernel == K_F64) {
+        // Linear row tiles of 64 (d1,d2) pairs, linear column tiles of 16 nb
+        // (p,d3) pairs; FP64 only.
+        if (h->prec != FP64) return g;
+        const int lds = f64_lds_bytes(nb);
+        if (lds <= 0) return g;
+        g.m_tile = 64;
+        g.n_tile = 16 * nb;
+        g.n_mt = cdiv(n1 * n2, g.m_tile);
+        g.n_nt = cdiv(n3 * n_mom, g.n_tile);
+        g.lds = lds;
     } else if (kernel == K_PORD) {
         // Rows (d1,d2,d3): a block of consecutive (d1,d2) pairs x a d3 block;
         // columns: 32 nb momenta.
@@ -313,6 +324,21 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
             p.kernel = K_PORD;
             p.nb = g.nb;
             p.splits = fill_splits(h, g);
+            return p;
+        }
+    }
+    if (h->prec == FP64) {
+        // The producer/consumer FP64 kernel: the column width that pads
+        // fewest columns (the wider on a tie).
+        for (int nb : {7, 4, 2}) {
+            const Geometry g = geometry(h, K_F64, nb, n1, n2, n3, n_mom);
+            if (g.lds < 0) continue;
+            if (best.lds < 0 || (long)g.n_nt * g.n_tile < (long)best.n_nt * best.n_tile) best = g;
+        }
+        if (best.lds >= 0) {
+            p.kernel = best.kernel;
+            p.nb = best.nb;
+            p.splits = fill_splits(h, best);
             return p;
         }
     }
@@ -559,6 +585,7 @@ bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &s
                        : is_w3(sb.kernel)       ? launch_w3(sb.nb, sb.b2, sb.kernel == K_W3W8 ? 8 : 4, ga.in_c64, ga,
                                                             grid, st)
                        : sb.kernel == K_PORD    ? launch_pord(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
+                       : sb.kernel == K_F64     ? launch_f64(sb.nb, ga.in_c64, ga, grid, st)
                                                 : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
         if (h->profiling) {
@@ -856,7 +883,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         sb.b3 = b0.g.b3;
         sb.persistent = b0.plan.persistent;
         sb.grid = b0.plan.grid > 0 ? b0.plan.grid : h->num_cu;
-        any_pipelined |= sb.kernel == K_PIPELINED || sb.kernel == K_PORD;
+        any_pipelined |= sb.kernel == K_PIPELINED || sb.kernel == K_PORD || sb.kernel == K_F64;
         size_t used = 0;
         long n_went = 0;
         const size_t u0 = u;
@@ -1414,7 +1441,8 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         h->forced.erase(k);
         return BBLOCK_OK;
     }
-    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && !is_w3(plan->kernel) && plan->kernel != K_PORD)
+    if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && !is_w3(plan->kernel) && plan->kernel != K_PORD &&
+        plan->kernel != K_F64)
         return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
@@ -1517,6 +1545,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         for (int nb : {7, 6, 5, 4}) kn.push_back({K_W3W8, nb});
         for (int nb : {7, 6, 5, 4}) kn.push_back({K_W3, nb});
         for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
+        for (int nb : {7, 4, 2}) kn.push_back({K_F64, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
         const int N = n3 * n_mom;
         for (auto [kernel, nb] : kn) {

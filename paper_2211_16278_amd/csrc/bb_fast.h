@@ -71,6 +71,25 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
     return __builtin_bit_cast(uint32_t, v);
 }
 
+// Residual of the BF16 split of (a, b) given hi = pack_bf16(a, b).  The low
+// half is widened with a byte permute so that the compiler keeps using hi.
+__device__ __forceinline__ uint32_t split_lo(float a, float b, uint32_t hi)
+{
+    const float ha = __uint_as_float(__builtin_amdgcn_perm(hi, hi, 0x01000c0cu));
+    const float hb = __uint_as_float(hi & 0xffff0000u);
+    return pack_bf16(a - ha, b - hb);
+}
+
+// Keeps a computed value at this point of the instruction stream: the empty
+// asm statement reads and rewrites it, so the arithmetic that produces it
+// cannot sink past the scheduling barrier that follows (work spread one step
+// per MFMA slot would otherwise gather next to its first use).
+template <class T>
+__device__ __forceinline__ void pin(T &x)
+{
+    asm volatile("" : "+v"(x));
+}
+
 // Complex product with a fixed rounding sequence (one rounded product, then
 // one fused multiply-add per part), so that every kernel that forms the same
 // product gets the same bits whatever the compiler's contraction choices.

@@ -19,6 +19,22 @@ constexpr int MAX_MOM = 128;
 constexpr int MAX_MODES = 4096;  // eigenvectors or coefficient rows of the LapH-subspace entry points
 constexpr int MAX_L = 256;
 
+// A value every lane of the wave holds alike, moved to scalar registers
+// (loads of the tile tables are vector loads; the compiler cannot tell on its
+// own), so that buffer resources built from it need no waterfall loop.
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized fields only");
+    struct Words {
+        uint32_t w[sizeof(T) / 4];
+    };
+    Words x = __builtin_bit_cast(Words, v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) x.w[i] = __builtin_amdgcn_readfirstlane(x.w[i]);
+    return __builtin_bit_cast(T, x);
+}
+
 // One baryon block as the kernels see it (device resident table).
 struct BlockDesc {
     const void *q1, *q2, *q3;  // [V][3][n_i] complex (c128 or c64)
@@ -124,6 +140,12 @@ hipError_t launch_w3(int nb, int b2, int waves, int c64, const GemmArgs &a, int 
 // BlockDesc.n_mt2 for the number of d3 blocks.
 int pord_pairs(int nb, int b3);
 hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
+// FP64 kernel (plan kernel 5): eight waves per workgroup, four running the
+// three-product complex GEMM on the matrix cores, four building the D and W
+// tiles; 64 complex rows x 16 cf columns per tile (cf 2, 4 or 7).  Static
+// LDS bytes (-1 when no instantiation), launch.
+int f64_lds_bytes(int cf);
+hipError_t launch_f64(int cf, int c64, const GemmArgs &a, int grid, hipStream_t st);
 // Offset of batch entry b of one GEMM operand, in complex elements: two
 // terms ((b / d) % m) * s, so that an operand can run with the whole batch
 // index, with an outer part of it only, or stay fixed (s = 0).

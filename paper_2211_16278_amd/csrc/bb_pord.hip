@@ -29,39 +29,14 @@ using fast::bf8_t;
 using fast::cmulf;
 using fast::f16_t;
 using fast::pack_bf16;
+using fast::pin;
+using fast::split_lo;
 using fast::static_for;
 
 typedef const void __attribute__((address_space(1))) *gvoid;
 
-__device__ __forceinline__ uint32_t split_lo(float a, float b, uint32_t hi)
-{
-    const float ha = __uint_as_float(__builtin_amdgcn_perm(hi, hi, 0x01000c0cu));
-    const float hb = __uint_as_float(hi & 0xffff0000u);
-    return pack_bf16(a - ha, b - hb);
-}
-
-template <class T>
-__device__ __forceinline__ T wave_uniform(const T &v)
-{
-    static_assert(sizeof(T) % 4 == 0, "word-sized fields only");
-    struct Words {
-        uint32_t w[sizeof(T) / 4];
-    };
-    Words x = __builtin_bit_cast(Words, v);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) x.w[i] = __builtin_amdgcn_readfirstlane(x.w[i]);
-    return __builtin_bit_cast(T, x);
-}
-
 typedef float f2v_t __attribute__((ext_vector_type(2)));
 typedef float f4v_t __attribute__((ext_vector_type(4)));
-
-// Keeps a computed value at this point of the instruction stream (the empty
-// asm statement reads and rewrites it), so that the singlet steps spread over
-// the MFMA slots stay where they are placed instead of gathering at their
-// first use.
-__device__ __forceinline__ void pin(float &x) { asm volatile("" : "+v"(x)); }
-__device__ __forceinline__ void pin(uint32_t &x) { asm volatile("" : "+v"(x)); }
 
 // Tile shape: NB column fragments of 32 momenta; F row fragments of 32 rows
 // per wave (rows = PPF pairs x B3 d3 values); 4 waves.

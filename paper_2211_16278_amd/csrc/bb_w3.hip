@@ -31,6 +31,8 @@ using fast::MT;
 using fast::pack_bf16;
 using fast::drow;
 using fast::wrow;
+using fast::pin;
+using fast::split_lo;
 using fast::static_for;
 
 // One W image: the hi and lo planes of an n-tile of NT columns over one chunk
@@ -58,15 +60,6 @@ struct CLayout {
     }
 };
 
-// Residual of the BF16 split of (a, b) given hi = pack_bf16(a, b).  The low
-// half is widened with a byte permute so that the compiler keeps using hi.
-__device__ __forceinline__ uint32_t split_lo(float a, float b, uint32_t hi)
-{
-    const float ha = __uint_as_float(__builtin_amdgcn_perm(hi, hi, 0x01000c0cu));
-    const float hb = __uint_as_float(hi & 0xffff0000u);
-    return pack_bf16(a - ha, b - hb);
-}
-
 // (Im, -Re) of four packed (Re, Im) BF16 pairs: the Im-row operand.
 __device__ __forceinline__ bf8_t im_rows(uint4 v)
 {
@@ -74,32 +67,6 @@ __device__ __forceinline__ bf8_t im_rows(uint4 v)
                                                 __builtin_amdgcn_perm(v.y, v.y, 0x01000302u) ^ 0x80000000u,
                                                 __builtin_amdgcn_perm(v.z, v.z, 0x01000302u) ^ 0x80000000u,
                                                 __builtin_amdgcn_perm(v.w, v.w, 0x01000302u) ^ 0x80000000u));
-}
-
-// Keeps a computed value at this point of the instruction stream: the empty
-// asm statement reads and rewrites it, so the arithmetic that produces it
-// cannot sink past the scheduling barrier that follows (the diquark work is
-// spread one step per MFMA slot, and without this the compiler gathers the
-// steps of a colour next to their first use).
-template <class T>
-__device__ __forceinline__ void pin(T &x)
-{
-    asm volatile("" : "+v"(x));
-}
-
-// A value every lane of the wave holds alike, moved to scalar registers (loads
-// of the tile tables are vector loads, the compiler cannot tell on its own).
-template <class T>
-__device__ __forceinline__ T wave_uniform(const T &v)
-{
-    static_assert(sizeof(T) % 4 == 0, "word-sized fields only");
-    struct Words {
-        uint32_t w[sizeof(T) / 4];
-    };
-    Words x = __builtin_bit_cast(Words, v);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) x.w[i] = __builtin_amdgcn_readfirstlane(x.w[i]);
-    return __builtin_bit_cast(T, x);
 }
 
 // Staged complex values move as one 8-byte LDS access (a float2 struct would

@@ -145,6 +145,8 @@ def _plans(prec):
     """Every (kernel, nb, splits, persistent) the planner or autotuner may pick."""
     out = []
     kernels = [(0, nb) for nb in ((1, 2, 4, 7, 14) if prec == "fp64" else (1, 2, 4, 7))]
+    if prec == "fp64":
+        kernels += [(5, 2), (5, 4), (5, 7)]
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
     if prec == "bf16x3":
@@ -181,8 +183,8 @@ def test_determinism_graph_persistent(torch_dev, prec):
     say("case determinism", prec)
     a = gpu_block(torch_dev, prec, L, qs, mom, graph=False)
     b = gpu_block(torch_dev, prec, L, qs, mom, graph=True)
-    kernel = 0 if prec == "fp64" else 1
-    nb = 14 if prec == "fp64" else 7
+    kernel = 5 if prec == "fp64" else 1
+    nb = 7
     c = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(kernel=kernel, nb=nb, splits=0, persistent=1))
     d = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(kernel=kernel, nb=nb, splits=0, persistent=0))
     assert np.array_equal(a, b)
@@ -385,7 +387,10 @@ def test_plan_validation_and_defaults(torch_dev):
             for kernel in (2, 4):
                 with pytest.raises(binding.BBlockError):
                     bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=7, splits=0, persistent=0, grid=0))
-            assert bb.get_plan(n, n, n, 7)["kernel"] in (0, 1)
+            assert bb.get_plan(n, n, n, 7)["kernel"] == (5 if prec == "fp64" else 1)
+            if prec == "fp32":
+                with pytest.raises(binding.BBlockError):  # kernel 5 is FP64 only
+                    bb.set_plan(n, n, n, 7, dict(kernel=5, nb=7, splits=0, persistent=0, grid=0))
 
 
 def test_projected_argument_errors(torch_dev):
