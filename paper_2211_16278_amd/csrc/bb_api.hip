@@ -249,12 +249,12 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_nt = cdiv(n_mom, g.bp) * g.n_nt3;
         g.lds = is_w3(kernel) ? w3_lds_bytes(nb, g.b2) : fast_lds_bytes(h->prec, nb, g.b2, g.b3, h->L);
     } else if (kernel == K_F64) {
-        // Linear row tiles of 64 (d1,d2) pairs, linear column tiles of 16 nb
+        // Linear row tiles of 128 (d1,d2) pairs, linear column tiles of 16 nb
         // (p,d3) pairs; FP64 only.
         if (h->prec != FP64) return g;
         const int lds = f64_lds_bytes(nb);
         if (lds <= 0) return g;
-        g.m_tile = 64;
+        g.m_tile = 128;
         g.n_tile = 16 * nb;
         g.n_mt = cdiv(n1 * n2, g.m_tile);
         g.n_nt = cdiv(n3 * n_mom, g.n_tile);

@@ -46,10 +46,11 @@ namespace f64 {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 512;        // eight waves
-constexpr int MT = 64;         // complex rows per tile (16 per matrix wave)
+constexpr int MT = 128;        // complex rows per tile (16 per wave)
 constexpr int SITES = 4;       // sites per chunk (divides CHUNK_SITES, the split granularity)
 constexpr int KC = 3 * SITES;  // kappa per chunk
 constexpr int DS = MT + 16;    // kappa stride of the D planes (doubles)
+static_assert(DS % 32 == 16 && MT * SITES == WG, "D stride off the banks; one D item per thread");
 constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past any range: loads return zero
 
 template <int CF>
@@ -58,10 +59,9 @@ struct Shape {
     static constexpr int WS = (NT % 32 == 0) ? NT + 16 : NT;   // kappa stride of the W planes
     static constexpr int DPL = KC * DS, WPL = KC * WS;          // doubles per plane
     static constexpr int BUF = 2 * DPL + 3 * WPL;               // D: Re, Im; W: Re, Im, Re + Im
-    static constexpr int WI = (NT * SITES + 255) / 256;         // W items per generation thread
     static constexpr size_t lds = (size_t)2 * BUF * 8 + (size_t)MAX_L * 16;
     static_assert(WS % 32 == 16, "k-groups must fall on disjoint banks");
-    static_assert((NT * SITES) % 64 == 0, "W item slots end on a wave boundary");
+    static_assert((NT * SITES) % 64 == 0 && NT * SITES <= WG, "W items end on a wave boundary, one per thread");
 };
 
 template <bool C64>
@@ -101,16 +101,15 @@ template <int CF, bool C64>
 __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 {
     using Sh = Shape<CF>;
-    constexpr int NT = Sh::NT, WS = Sh::WS, DPL = Sh::DPL, WPL = Sh::WPL, BUF = Sh::BUF, WI = Sh::WI;
+    constexpr int NT = Sh::NT, WS = Sh::WS, DPL = Sh::DPL, WPL = Sh::WPL, BUF = Sh::BUF;
     constexpr int ESZ = In<C64>::ESZ;
+    constexpr int NW = NT * SITES;  // W items per chunk (one per thread, waves past it have none)
     __shared__ __align__(16) double lds[2 * BUF];
     __shared__ double2 roots[MAX_L];
     __shared__ int s_tile;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const bool gen = wave >= 4;
-    const int gt = tid - 256;  // generation thread index (gen waves only)
     for (int k = tid; k < a.L; k += WG) roots[k] = make_double2(a.roots[2 * k], a.roots[2 * k + 1]);
 
     auto next_tile = [&](int current) -> int {
@@ -130,168 +129,141 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         const int xe = min(a.V, xs + bd.sps);
         const int n_chunks = (xe - xs + SITES - 1) / SITES;
 
-        if (gen) {
-            // ---------------------------------------------- generation waves
-            // D item: row r = gt % 64 at site s = gt / 64 of each chunk.
-            const int r = gt & 63, s = gt >> 6;
-            const int m = m0 + r;
-            const bool mok = m < bd.M;
-            const int d1 = mok ? m / bd.n2 : 0, d2 = mok ? m - (m / bd.n2) * bd.n2 : 0;
-            uint32_t o1[3], o2[3];
+        // ---- generation items of this thread (tile invariant) ----
+        // D item: row r = tid % 128 at site s = tid / 128 of each chunk.
+        const int r = tid & (MT - 1), s = tid >> 7;
+        const int m = m0 + r;
+        const bool mok = m < bd.M;
+        const int d1 = mok ? m / bd.n2 : 0, d2 = mok ? m - (m / bd.n2) * bd.n2 : 0;
+        uint32_t o1[3], o2[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o1[c] = mok ? (uint32_t)(((s * 3 + c) * bd.n1 + d1) * ESZ) : OOB;
+            o2[c] = mok ? (uint32_t)(((s * 3 + c) * bd.n2 + d2) * ESZ) : OOB;
+        }
+        // W item: column j = tid % NT at site tid / NT (threads past NW: none).
+        const bool has_w = wave * 64 < NW;  // wave-uniform: NW is a multiple of 64
+        const int wj = tid % NT, wsite = tid / NT;
+        const int nu = nu0 + wj;
+        const bool wok = tid < NW && nu < bd.N;
+        const int p = wok ? nu / bd.n3 : 0, d3 = wok ? nu - (nu / bd.n3) * bd.n3 : 0;
+        uint32_t o3[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o3[c] = wok ? (uint32_t)(((wsite * 3 + c) * bd.n3 + d3) * ESZ) : OOB;
+        const uint32_t ok = (uint32_t)(p * a.kstride + wsite);
+        const int krec = a.n_mom * a.kstride;
+
+        double2 u[3], v[3], w[3];
+        uint32_t kk = 0;
+        auto issue = [&](int ci) {
+            const int x0 = xs + ci * SITES;
+            const __amdgpu_buffer_rsrc_t rs1 = chunk_rsrc<C64>(bd.q1, bd.n1, x0, xe);
+            const __amdgpu_buffer_rsrc_t rs2 = chunk_rsrc<C64>(bd.q2, bd.n2, x0, xe);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                o1[c] = mok ? (uint32_t)(((s * 3 + c) * bd.n1 + d1) * ESZ) : OOB;
-                o2[c] = mok ? (uint32_t)(((s * 3 + c) * bd.n2 + d2) * ESZ) : OOB;
+                u[c] = ldq<C64>(rs1, o1[c]);
+                v[c] = ldq<C64>(rs2, o2[c]);
             }
-            // W items: e = gt + 256 i -> column j = e % NT at site e / NT.
-            int wj[WI], wsite[WI];
-            uint32_t o3[WI][3], ok_[WI];
-#pragma unroll
-            for (int i = 0; i < WI; ++i) {
-                const int e = gt + 256 * i;
-                wj[i] = e % NT;
-                wsite[i] = e / NT;
-                const int nu = nu0 + wj[i];
-                const bool ok = e < NT * SITES && nu < bd.N;
-                const int p = ok ? nu / bd.n3 : 0, d3 = ok ? nu - (nu / bd.n3) * bd.n3 : 0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) o3[i][c] = ok ? (uint32_t)(((wsite[i] * 3 + c) * bd.n3 + d3) * ESZ) : OOB;
-                ok_[i] = (uint32_t)(p * a.kstride + wsite[i]);
-            }
-            const int krec = a.n_mom * a.kstride;
-
-            struct Regs {
-                double2 u[3], v[3], w[WI][3];
-                uint32_t k[WI];
-            };
-            Regs ra, rb;
-            auto issue = [&](Regs &R, int ci) {
-                const int x0 = xs + ci * SITES;
-                const __amdgpu_buffer_rsrc_t rs1 = chunk_rsrc<C64>(bd.q1, bd.n1, x0, xe);
-                const __amdgpu_buffer_rsrc_t rs2 = chunk_rsrc<C64>(bd.q2, bd.n2, x0, xe);
+            if (has_w) {
                 const __amdgpu_buffer_rsrc_t rs3 = chunk_rsrc<C64>(bd.q3, bd.n3, x0, xe);
                 const __amdgpu_buffer_rsrc_t rsk = __builtin_amdgcn_make_buffer_rsrc(
                     (void *)(a.kidx + min(x0, krec)), (short)0, max(krec - x0, 0), 0x00020000);
 #pragma unroll
+                for (int c = 0; c < 3; ++c) w[c] = ldq<C64>(rs3, o3[c]);
+                kk = __builtin_amdgcn_raw_buffer_load_b8(rsk, ok, 0, 0);
+            }
+        };
+        // Diquark u_a v_b - u_b v_a (eps_{a b c} = +1) and W_c = q3_c
+        // exp(-i p.x) of the loaded chunk into buffer b.
+        auto build = [&](int b) {
+            // The buffer offset stays a register value: folded into every
+            // store it would exceed the 16-bit LDS offset field and cost one
+            // address register per store.
+            asm volatile("" : "+s"(b));
+            double *Dr = lds + b * BUF, *Di = Dr + DPL, *Wr = Di + DPL, *Wi = Wr + WPL, *Wsum = Wi + WPL;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double2 ua = u[(c + 1) % 3], ub = u[(c + 2) % 3];
+                const double2 va = v[(c + 1) % 3], vb = v[(c + 2) % 3];
+                const double re = __builtin_fma(ua.x, vb.x, __builtin_fma(-ua.y, vb.y, __builtin_fma(-ub.x, va.x, ub.y * va.y)));
+                const double im = __builtin_fma(ua.x, vb.y, __builtin_fma(ua.y, vb.x, __builtin_fma(-ub.x, va.y, -(ub.y * va.x))));
+                Dr[(c * SITES + s) * DS + r] = re;
+                Di[(c * SITES + s) * DS + r] = im;
+            }
+            if (has_w) {
+                const double2 e = roots[kk];
+#pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    R.u[c] = ldq<C64>(rs1, o1[c]);
-                    R.v[c] = ldq<C64>(rs2, o2[c]);
-                }
-#pragma unroll
-                for (int i = 0; i < WI; ++i) {
-                    if (gt + 256 * i >= NT * SITES) break;  // wave-uniform
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) R.w[i][c] = ldq<C64>(rs3, o3[i][c]);
-                    R.k[i] = __builtin_amdgcn_raw_buffer_load_b8(rsk, ok_[i], 0, 0);
-                }
-            };
-            // Diquark u_a v_b - u_b v_a (eps_{a b c} = +1) and W_c = q3_c
-            // exp(-i p.x) of the loaded chunk into buffer B.
-            auto build = [&](const Regs &R, int b) {
-                // The buffer offset stays a register value: folded into
-                // every store it would exceed the 16-bit LDS offset field
-                // and cost one address register per store.
-                asm volatile("" : "+s"(b));
-                double *Dr = lds + b * BUF, *Di = Dr + DPL, *Wr = Di + DPL, *Wi = Wr + WPL, *Wsum = Wi + WPL;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double2 ua = R.u[(c + 1) % 3], ub = R.u[(c + 2) % 3];
-                    const double2 va = R.v[(c + 1) % 3], vb = R.v[(c + 2) % 3];
-                    const double re = __builtin_fma(ua.x, vb.x, __builtin_fma(-ua.y, vb.y, __builtin_fma(-ub.x, va.x, ub.y * va.y)));
-                    const double im = __builtin_fma(ua.x, vb.y, __builtin_fma(ua.y, vb.x, __builtin_fma(-ub.x, va.y, -(ub.y * va.x))));
-                    Dr[(c * SITES + s) * DS + r] = re;
-                    Di[(c * SITES + s) * DS + r] = im;
-                }
-#pragma unroll
-                for (int i = 0; i < WI; ++i) {
-                    if (gt + 256 * i >= NT * SITES) break;  // wave-uniform
-                    const double2 e = roots[R.k[i]];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double2 q = R.w[i][c];
-                        const double wr = __builtin_fma(q.x, e.x, -(q.y * e.y));
-                        const double wi = __builtin_fma(q.x, e.y, q.y * e.x);
-                        const int o = (c * SITES + wsite[i]) * WS + wj[i];
-                        Wr[o] = wr;
-                        Wi[o] = wi;
-                        Wsum[o] = wr + wi;
-                    }
-                }
-            };
-            // Register set ra holds even chunks, rb odd ones; each is loaded
-            // about two chunks before it is built.
-            issue(ra, 0);
-            issue(rb, 1);
-            build(ra, 0);
-            issue(ra, 2);
-            __syncthreads();
-            for (int i = 0; i < n_chunks; i += 2) {
-                if (i + 1 < n_chunks) {
-                    build(rb, 1);
-                    issue(rb, i + 3);
-                }
-                __syncthreads();
-                if (i + 1 < n_chunks) {
-                    if (i + 2 < n_chunks) {
-                        build(ra, 0);
-                        issue(ra, i + 4);
-                    }
-                    __syncthreads();
+                    const double wr = __builtin_fma(w[c].x, e.x, -(w[c].y * e.y));
+                    const double wi = __builtin_fma(w[c].x, e.y, w[c].y * e.x);
+                    const int o = (c * SITES + wsite) * WS + wj;
+                    Wr[o] = wr;
+                    Wi[o] = wi;
+                    Wsum[o] = wr + wi;
                 }
             }
-        } else {
-            // -------------------------------------------------- matrix waves
-            d4_t acc[3][CF];
+        };
+
+        d4_t acc[3][CF];
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 3; ++q)
 #pragma unroll
-                for (int n = 0; n < CF; ++n) acc[q][n] = d4_t{0.0, 0.0, 0.0, 0.0};
-            // A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k.
-            const int li = lane & 15, kg = lane >> 4;
-            const int arow = wave * 16 + li;
-            auto mma = [&](int b) {
-                asm volatile("" : "+s"(b));  // one base register per chunk, immediate offsets from it
-                const double *Dr = lds + b * BUF, *Di = Dr + DPL, *Wr = Di + DPL, *Wi = Wr + WPL, *Wsum = Wi + WPL;
+            for (int n = 0; n < CF; ++n) acc[q][n] = d4_t{0.0, 0.0, 0.0, 0.0};
+        // A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k.
+        const int li = lane & 15, kg = lane >> 4;
+        const int arow = wave * 16 + li;
+        auto mma = [&](int b) {
+            asm volatile("" : "+s"(b));  // one base register per chunk, immediate offsets from it
+            const double *Dr = lds + b * BUF, *Di = Dr + DPL, *Wr = Di + DPL, *Wi = Wr + WPL, *Wsum = Wi + WPL;
 #pragma unroll
-                for (int ks = 0; ks < KC / 4; ++ks) {
-                    const int kap = 4 * ks + kg;
-                    const double ar = Dr[kap * DS + arow], ai = Di[kap * DS + arow];
-                    const double as = ar + ai;
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                const int kap = 4 * ks + kg;
+                const double ar = Dr[kap * DS + arow], ai = Di[kap * DS + arow];
+                const double as = ar + ai;
 #pragma unroll
-                    for (int n = 0; n < CF; ++n) {
-                        const int o = kap * WS + n * 16 + li;
-                        const double br = Wr[o], bi = Wi[o], bs = Wsum[o];
-                        acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bs, acc[0][n], 0, 0, 0);
-                        acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, acc[1][n], 0, 0, 0);
-                        acc[2][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, acc[2][n], 0, 0, 0);
-                    }
+                for (int n = 0; n < CF; ++n) {
+                    const int o = kap * WS + n * 16 + li;
+                    const double br = Wr[o], bi = Wi[o], bs = Wsum[o];
+                    acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bs, acc[0][n], 0, 0, 0);
+                    acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, acc[1][n], 0, 0, 0);
+                    acc[2][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, acc[2][n], 0, 0, 0);
                 }
-            };
-            __syncthreads();
-            for (int i = 0; i < n_chunks; ++i) {
-                mma(i & 1);
-                __syncthreads();
             }
-            // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  Accumulator register
-            // e of a 16x16 f64 fragment holds row 4 e + lane / 16, column lane % 16.
+        };
+
+        // Prologue: chunk 0 into buffer 0, chunk 1 in registers.
+        issue(0);
+        build(0);
+        issue(1);
+        __syncthreads();
+        for (int i = 0; i < n_chunks; ++i) {
+            mma(i & 1);
+            if (i + 1 < n_chunks) {
+                build((i + 1) & 1);
+                issue(i + 2);  // past the split: out of range, zeros
+            }
+            __syncthreads();
+        }
+
+        // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  Accumulator register
+        // e of a 16x16 f64 fragment holds row 4 e + lane / 16, column lane % 16.
 #pragma unroll
-            for (int n = 0; n < CF; ++n) {
-                const int nu = nu0 + n * 16 + li;
-                if (nu >= bd.N) continue;
-                const int p = nu / bd.n3, d3 = nu - (nu / bd.n3) * bd.n3;
+        for (int n = 0; n < CF; ++n) {
+            const int nuo = nu0 + n * 16 + li;
+            if (nuo >= bd.N) continue;
+            const int po = nuo / bd.n3, d3o = nuo - (nuo / bd.n3) * bd.n3;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int m = m0 + wave * 16 + 4 * e + kg;
-                    if (m >= bd.M) continue;
-                    const double p1 = acc[0][n][e], p2 = acc[1][n][e], p3 = acc[2][n][e];
-                    const double re = p2 - p3, im = (p1 - p2) - p3;
-                    if (bd.direct) {
-                        reinterpret_cast<double2 *>(bd.out)[((size_t)p * bd.M + m) * bd.n3 + d3] = make_double2(re, im);
-                    } else {
-                        double *ws = reinterpret_cast<double *>(bd.ws);
-                        ws[((size_t)tl.w * 2 * bd.M + m) * bd.N + nu] = re;
-                        ws[(((size_t)tl.w * 2 + 1) * bd.M + m) * bd.N + nu] = im;
-                    }
+            for (int e = 0; e < 4; ++e) {
+                const int mo = m0 + wave * 16 + 4 * e + kg;
+                if (mo >= bd.M) continue;
+                const double p1 = acc[0][n][e], p2 = acc[1][n][e], p3 = acc[2][n][e];
+                const double re = p2 - p3, im = (p1 - p2) - p3;
+                if (bd.direct) {
+                    reinterpret_cast<double2 *>(bd.out)[((size_t)po * bd.M + mo) * bd.n3 + d3o] = make_double2(re, im);
+                } else {
+                    double *wsp = reinterpret_cast<double *>(bd.ws);
+                    wsp[((size_t)tl.w * 2 * bd.M + mo) * bd.N + nuo] = re;
+                    wsp[(((size_t)tl.w * 2 + 1) * bd.M + mo) * bd.N + nuo] = im;
                 }
             }
         }

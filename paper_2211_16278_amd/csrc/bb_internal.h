@@ -140,10 +140,11 @@ hipError_t launch_w3(int nb, int b2, int waves, int c64, const GemmArgs &a, int 
 // BlockDesc.n_mt2 for the number of d3 blocks.
 int pord_pairs(int nb, int b3);
 hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
-// FP64 kernel (plan kernel 5): eight waves per workgroup, four running the
-// three-product complex GEMM on the matrix cores, four building the D and W
-// tiles; 64 complex rows x 16 cf columns per tile (cf 2, 4 or 7).  Static
-// LDS bytes (-1 when no instantiation), launch.
+// FP64 kernel (plan kernel 5): eight waves per workgroup, each running the
+// three-product complex GEMM of 16 rows on the matrix cores and building its
+// share of the next chunk's D and W tiles; 128 complex rows x 16 cf columns
+// per tile (cf 2, 4 or 7).  Static LDS bytes (-1 when no instantiation),
+// launch.
 int f64_lds_bytes(int cf);
 hipError_t launch_f64(int cf, int c64, const GemmArgs &a, int grid, hipStream_t st);
 // Offset of batch entry b of one GEMM operand, in complex elements: two
