@@ -38,6 +38,7 @@
 // disjoint LDS banks.
 #include <algorithm>
 
+#include "bb_fast.h"
 #include "bb_internal.h"
 
 namespace bb {
@@ -212,23 +213,93 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         // A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k.
         const int li = lane & 15, kg = lane >> 4;
         const int arow = wave * 16 + li;
-        auto mma = [&](int b) {
-            asm volatile("" : "+s"(b));  // one base register per chunk, immediate offsets from it
+
+        // One chunk: the MFMAs of the chunk in buffer b, in 3 CF groups of
+        // one column fragment's three products, each group followed (in
+        // program order, fenced) by a slice of the next chunk's generation
+        // into buffer b ^ 1 and, once the registers are consumed, the loads
+        // of the chunk after it.  A vector instruction cannot issue while an
+        // FP64 MFMA occupies the SIMD, so the slices cost their issue time,
+        // but their latencies and the LDS and memory latencies run under
+        // the MFMAs.  Operands of fragment f + 1 are read during fragment f.
+        auto chunk = [&](int b, int ci_next) {
+            asm volatile("" : "+s"(b));  // one base register per buffer, immediate offsets from it
             const double *Dr = lds + b * BUF, *Di = Dr + DPL, *Wr = Di + DPL, *Wi = Wr + WPL, *Wsum = Wi + WPL;
-#pragma unroll
-            for (int ks = 0; ks < KC / 4; ++ks) {
-                const int kap = 4 * ks + kg;
-                const double ar = Dr[kap * DS + arow], ai = Di[kap * DS + arow];
-                const double as = ar + ai;
-#pragma unroll
-                for (int n = 0; n < CF; ++n) {
-                    const int o = kap * WS + n * 16 + li;
-                    const double br = Wr[o], bi = Wi[o], bs = Wsum[o];
-                    acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, bs, acc[0][n], 0, 0, 0);
-                    acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, acc[1][n], 0, 0, 0);
-                    acc[2][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, acc[2][n], 0, 0, 0);
+            double *nDr = lds + (b ^ 1) * BUF, *nDi = nDr + DPL, *nWr = nDi + DPL, *nWi = nWr + WPL;
+            double *nWs = nWi + WPL;
+            constexpr int NG = 3 * CF;  // groups per chunk
+            double a_r = Dr[kg * DS + arow], a_i = Di[kg * DS + arow];
+            double n_r = 0.0, n_i = 0.0;
+            double b_r[2], b_i[2], b_s[2];
+            b_r[0] = Wr[kg * WS + li];
+            b_i[0] = Wi[kg * WS + li];
+            b_s[0] = Wsum[kg * WS + li];
+            double a_s = a_r + a_i;
+            double dre[3], dim[3];
+            double2 e = make_double2(0.0, 0.0);
+            auto step = [&](auto ss) {
+                constexpr int st = ss;
+                if constexpr (st < 6) {
+                    // Diquark colour c = st / 2 of this thread's (row, site).
+                    constexpr int c = st / 2;
+                    const double2 ua = u[(c + 1) % 3], ub = u[(c + 2) % 3];
+                    const double2 va = v[(c + 1) % 3], vb = v[(c + 2) % 3];
+                    if constexpr (st % 2 == 0) {
+                        dre[c] = __builtin_fma(ua.x, vb.x, __builtin_fma(-ua.y, vb.y, __builtin_fma(-ub.x, va.x, ub.y * va.y)));
+                        fast::pin(dre[c]);
+                    } else {
+                        dim[c] = __builtin_fma(ua.x, vb.y, __builtin_fma(ua.y, vb.x, __builtin_fma(-ub.x, va.y, -(ub.y * va.x))));
+                        nDr[(c * SITES + s) * DS + r] = dre[c];
+                        nDi[(c * SITES + s) * DS + r] = dim[c];
+                    }
+                } else if constexpr (st == 6) {
+                    if (has_w) e = roots[kk];
+                } else if constexpr (st < 10) {
+                    // Phase-weighted q3, colour c.
+                    constexpr int c = st - 7;
+                    if (has_w) {
+                        const double wr = __builtin_fma(w[c].x, e.x, -(w[c].y * e.y));
+                        const double wi = __builtin_fma(w[c].x, e.y, w[c].y * e.x);
+                        const int o = (c * SITES + wsite) * WS + wj;
+                        nWr[o] = wr;
+                        nWi[o] = wi;
+                        nWs[o] = wr + wi;
+                    }
+                } else if constexpr (st == 10) {
+                    issue(ci_next);  // the registers of this chunk are consumed
                 }
-            }
+            };
+            fast::static_for<0, NG>([&](auto gg) {
+                constexpr int g = gg, ks = g / CF, n = g % CF, f = g;
+                // Operands of the next fragment (and of the next k-step's rows).
+                if constexpr (n + 1 < CF) {
+                    const int o = (4 * ks + kg) * WS + (n + 1) * 16 + li;
+                    b_r[(f + 1) & 1] = Wr[o];
+                    b_i[(f + 1) & 1] = Wi[o];
+                    b_s[(f + 1) & 1] = Wsum[o];
+                } else if constexpr (ks + 1 < KC / 4) {
+                    const int kap = 4 * (ks + 1) + kg;
+                    n_r = Dr[kap * DS + arow];
+                    n_i = Di[kap * DS + arow];
+                    b_r[(f + 1) & 1] = Wr[kap * WS + li];
+                    b_i[(f + 1) & 1] = Wi[kap * WS + li];
+                    b_s[(f + 1) & 1] = Wsum[kap * WS + li];
+                }
+                acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_s, b_s[f & 1], acc[0][n], 0, 0, 0);
+                acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r, b_r[f & 1], acc[1][n], 0, 0, 0);
+                acc[2][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i, b_i[f & 1], acc[2][n], 0, 0, 0);
+                // The generation slices run in the last groups of the chunk,
+                // so the loads they end with have a whole chunk to land
+                // before the next chunk's slices read them.
+                constexpr int G0 = NG > 11 ? NG - 11 : 0;
+                if constexpr (g >= G0) fast::slot_steps<g - G0, NG - G0, 11>(step);
+                if constexpr (n + 1 == CF && ks + 1 < KC / 4) {
+                    a_r = n_r;
+                    a_i = n_i;
+                    a_s = a_r + a_i;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            });
         };
 
         // Prologue: chunk 0 into buffer 0, chunk 1 in registers.
@@ -237,11 +308,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         issue(1);
         __syncthreads();
         for (int i = 0; i < n_chunks; ++i) {
-            mma(i & 1);
-            if (i + 1 < n_chunks) {
-                build((i + 1) & 1);
-                issue(i + 2);  // past the split: out of range, zeros
-            }
+            chunk(i & 1, i + 2);  // past the split the loads are out of range (zeros)
             __syncthreads();
         }
 
