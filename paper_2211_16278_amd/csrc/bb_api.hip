@@ -144,6 +144,7 @@ struct bblock_s {
     hipEvent_t static_free = nullptr;
 
     int graph_mode = 2;               // 0: eager, 1: capture and replay, 2: replay schedules of 4+ launches
+    int walk_mode = 2;                // walking tiles: 0 never, 1 every unprojected batch, 2 batches that fill the device
     bool profiling = false;
     int plan_gen = 0;                 // bumped whenever forced or tuned plans change
     // The last batch: when a call repeats it (same descriptors, momenta and
@@ -404,6 +405,7 @@ struct BlockPlan {
     int rounds = 1;     // precomputed-W kernel: rounds of spr splits each
     int spr = 0;
     bool need_part = false;  // partials even for one split (spin projection)
+    bool walk = false;       // the tile's workgroup runs all splits in order (no partials)
 };
 
 // Sites per split for S splits: a multiple of CHUNK_SITES; the split count
@@ -426,8 +428,10 @@ void set_splits(bblock_t h, BlockPlan &bp, int S)
     bp.d.S = (h->V + sps - 1) / sps;
     bp.d.cps = sps / CHUNK_SITES;
     bp.d.n_nt = bp.g.n_nt;
-    bp.part_bytes = bp.d.S > 1 || bp.need_part ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
-    bp.d.direct = bp.part_bytes == 0;
+    const bool parts = (bp.d.S > 1 || bp.need_part) && !bp.walk;
+    bp.part_bytes = parts ? (size_t)bp.d.S * 2 * bp.d.M * bp.d.N * part_bytes(h->prec) : 0;
+    bp.d.direct = !parts && bp.d.S == 1;
+    bp.d.walk = !parts && bp.d.S > 1;
     bp.ws_bytes = bp.part_bytes;
     bp.rounds = 1;
     bp.spr = bp.d.S;
@@ -783,6 +787,15 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         take_geometry(bp);
         total_tiles_s1 += (long)bp.g.n_mt * bp.g.n_nt;
     }
+    // Walking tiles (the sum over sites of Algorithm 1 kept in one
+    // workgroup): a batch whose tiles fill the device without splitting the
+    // sites gives each (block, m-tile, n-tile) to one workgroup, which runs
+    // the block's splits (as few as the FP32 accumulation bound allows) in
+    // order and sums them into the output in FP64.  No partials, no
+    // reduction launch, no workspace beyond W images, so a whole batch of
+    // one kernel instantiation is one launch.  Spin projection keeps the
+    // partials: the combination reads them.
+    const bool walk = !coef && (h->walk_mode == 1 || (h->walk_mode == 2 && total_tiles_s1 >= 2L * h->num_cu));
     // Split count: a forced plan fixes it; a single block uses its plan's
     // count; batches fill the device; never below the accuracy bound.
     for (int i = 0; i < n_desc; ++i) {
@@ -792,12 +805,20 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         int S;
         if (fixed)
             S = bp.plan.splits;
+        else if (walk)
+            S = s_min;
         else if (n_desc == 1 && bp.plan.splits > 0)
             S = single_splits(bp.plan.splits, s_min);
         else
             S = std::max<int>(s_min, (int)std::max<long>(1, 2L * h->num_cu / std::max(1L, total_tiles_s1)));
         bp.need_part = coef != nullptr;
+        bp.walk = walk;
         set_splits(h, bp, S);
+        if (bp.walk && is_w3(bp.plan.kernel) && bp.rounds > 1) {
+            // A walking tile needs the images of all its splits at once.
+            bp.walk = false;
+            set_splits(h, bp, S);
+        }
         if (!fixed && bp.ws_bytes > h->ws_eff) set_splits(h, bp, s_min);
         if (is_w3(bp.plan.kernel) && (bp.ws_bytes > h->ws_eff || !w3_offsets_fit(h, bp))) {
             // Not even one split's W images fit beside the partials (or the
@@ -843,7 +864,19 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     };
     std::vector<Unit> units;
     std::vector<BlockDesc> descs(n_desc);
-    for (int b = 0; b < n_desc; ++b) {
+    // Blocks in order of kernel instantiation (stable), so that each
+    // instantiation forms one sub-batch however the caller interleaves the
+    // shapes; spin projection keeps descriptor order (its sums run in it).
+    std::vector<int> order(n_desc);
+    for (int b = 0; b < n_desc; ++b) order[b] = b;
+    if (!coef) {
+        auto inst = [&](int b) {
+            const BlockPlan &x = bps[b];
+            return std::array<int, 5>{x.plan.kernel, x.plan.nb, x.g.b2, x.g.b3, x.plan.persistent};
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return inst(x) < inst(y); });
+    }
+    for (int b : order) {
         for (int r = 0; r < bps[b].rounds; ++r) {
             int d = b;
             if (r > 0) {
@@ -867,6 +900,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
     std::vector<double> ccoef;
     std::vector<char> group_started(n_groups, 0);
     std::vector<size_t> ws_off(descs.size(), 0);
+    std::vector<size_t> img_off(descs.size(), 0);  // workspace offset of each unit's W images
     size_t ws_need = 0;
     bool any_pipelined = false;
     auto same_kernel = [&](const BlockPlan &x, const SubBatch &sb) {
@@ -887,17 +921,35 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         size_t used = 0;
         long n_went = 0;
         const size_t u0 = u;
+        // W images depend on q3, its d3/momentum blocking and the split
+        // structure only: blocks of the sub-batch that share them (the spin
+        // triples of one noise triple use each q3 several times) share one
+        // set, produced once.
+        std::map<std::array<long long, 8>, size_t> img_of;
+        std::vector<char> makes_img(units.size(), 0);
         while (u < units.size()) {
             const BlockPlan &bp = bps[units[u].b];
             if (u > u0 && (bp.rounds > 1 || b0.rounds > 1)) break;
-            if (!same_kernel(bp, sb) || used + bp.ws_bytes > h->ws_eff) break;
-            if (is_w3(sb.kernel)) {  // image entries form the y dimension of one launch
+            if (!same_kernel(bp, sb)) break;
+            const std::array<long long, 8> ikey{(long long)(uintptr_t)bp.d.q3, bp.d.n3, bp.plan.nb, bp.g.b3, bp.g.bp,
+                                                bp.g.n_nt, bp.d.S, bp.d.sps};
+            const bool shared = is_w3(sb.kernel) && bp.rounds == 1 && img_of.count(ikey);
+            const size_t need = shared ? align_up(bp.part_bytes, 4096) : bp.ws_bytes;
+            if (used + need > h->ws_eff) break;
+            if (is_w3(sb.kernel) && !shared) {  // image entries form the y dimension of one launch
                 const long e = (long)bp.g.n_nt * bp.spr;
                 if (u > u0 && n_went + e > 65535) break;
                 n_went += e;
             }
             ws_off[units[u].d] = used;
-            used += align_up(bp.ws_bytes, 256);
+            if (shared) {
+                img_off[units[u].d] = img_of[ikey];
+            } else {
+                img_off[units[u].d] = used + align_up(bp.part_bytes, 4096);
+                makes_img[u] = 1;
+                if (is_w3(sb.kernel) && bp.rounds == 1) img_of[ikey] = img_off[units[u].d];
+            }
+            used += align_up(need, 256);
             ++u;
         }
         sb.count = (int)(u - u0);
@@ -906,6 +958,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         // (block, split, n-tile, m-tile) order so neighbours share inputs.
         struct Item {
             long cost;
+            size_t group;  // workspace offset of the W images the tile reads (tiles sharing them stay together)
             int4 t;
         };
         std::vector<Item> items;
@@ -915,18 +968,20 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             const Unit &un = units[v];
             const BlockPlan &bp = bps[un.b];
             const int s_lo = un.r * bp.spr, s_hi = std::min(bp.d.S, s_lo + bp.spr);
-            for (int s = s_lo; s < s_hi; ++s) {
-                const long sites = std::min(bp.d.sps, h->V - s * bp.d.sps);
+            // A walking tile is one entry (split 0) that runs all splits.
+            for (int s = s_lo; s < (bp.d.walk ? s_lo + 1 : s_hi); ++s) {
+                const long sites = bp.d.walk ? h->V : std::min(bp.d.sps, h->V - s * bp.d.sps);
                 const long cost = (long)bp.g.m_tile * bp.g.n_tile * sites;
                 for (int nt = 0; nt < bp.g.n_nt; ++nt)
-                    for (int mt = 0; mt < bp.g.n_mt; ++mt) items.push_back({cost, make_int4(un.d, mt, nt, s)});
+                    for (int mt = 0; mt < bp.g.n_mt; ++mt)
+                        items.push_back({cost, img_off[un.d] + (size_t)nt, make_int4(un.d, mt, nt, s)});
             }
-            if (is_w3(sb.kernel)) {
+            if (is_w3(sb.kernel) && makes_img[v]) {
                 sb.cps_max = std::max(sb.cps_max, bp.d.cps);
                 for (int s = s_lo; s < s_hi; ++s)
                     for (int nt = 0; nt < bp.g.n_nt; ++nt) went.push_back(make_int4(un.d, nt, s, 0));
             }
-            if (!coef && bp.d.S > 1 && un.r == bp.rounds - 1) {
+            if (!coef && bp.d.S > 1 && !bp.d.walk && un.r == bp.rounds - 1) {
                 list.push_back(un.d);
                 sb.max_mn = std::max(sb.max_mn, bp.d.M * bp.d.N);
             }
@@ -961,7 +1016,10 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         if (went.size() - sb.went_off > 65535)
             return fail(h, BBLOCK_EUNSUPPORTED, "block %d has more than 65535 (n-tile, split) pairs", units[u0].b);
         sb.n_went = (int)went.size() - sb.went_off;
-        std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+        std::stable_sort(items.begin(), items.end(), [&](const Item &x, const Item &y) {
+            if (x.cost != y.cost) return x.cost > y.cost;
+            return is_w3(sb.kernel) && x.group < y.group;  // tiles reading one image set side by side
+        });
         sb.tile_off = (int)tiles.size();
         sb.n_tiles = (int)items.size();
         // XCD-aware order.  The dispatcher hands workgroup g to XCD g mod
@@ -973,7 +1031,13 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         // order only sets the cost ordering.
         {
             const int n_xcd = sb.persistent ? 1 : h->n_xcd;
-            const int k = (int)std::min<long>(std::max<long>(1, (long)b0.g.n_mt * b0.g.n_nt), h->cu_per_xcd);
+            long per = (long)b0.g.n_mt * b0.g.n_nt;  // tiles per split, or per shared image set
+            if (is_w3(sb.kernel) && !items.empty()) {
+                long same = 0;
+                while (same < (long)items.size() && items[same].group == items[0].group) ++same;
+                per = std::max(per, same);
+            }
+            const int k = (int)std::min<long>(std::max<long>(1, per), h->cu_per_xcd);
             const int n = (int)items.size();
             for (int base = 0; base < n; base += n_xcd * k) {
                 const int m = std::min(n_xcd * k, n - base);
@@ -996,7 +1060,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         BlockDesc d = bp.d;
         unsigned char *base = static_cast<unsigned char *>(ws_base) + ws_off[un.d];
         d.ws = bp.part_bytes ? base : nullptr;
-        d.wimg = is_w3(bp.plan.kernel) ? base + align_up(bp.part_bytes, 4096) : nullptr;
+        d.wimg = is_w3(bp.plan.kernel) ? static_cast<unsigned char *>(ws_base) + img_off[un.d] : nullptr;
         d.img_s0 = un.r * bp.spr;
         descs[un.d] = d;
     }
@@ -1162,6 +1226,9 @@ bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_d
     if (hipEventCreateWithFlags(&h->static_free, hipEventDisableTiming) != hipSuccess)
         return bail(BBLOCK_EHIP, "event creation failed");
 
+    // Walking tiles: BBLOCK_SPLIT_WALK=0 never, 1 in every unprojected batch
+    // (tests force it on small batches), unset: batches that fill the device.
+    if (const char *w = std::getenv("BBLOCK_SPLIT_WALK")) h->walk_mode = std::atoi(w) == 0 ? 0 : (std::atoi(w) == 1 ? 1 : 2);
     // Tuned plans persisted by earlier runs.
     if (const char *path = std::getenv("BBLOCK_TUNE_CACHE")) {
         if (FILE *f = std::fopen(path, "r")) {

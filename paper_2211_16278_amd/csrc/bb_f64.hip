@@ -123,8 +123,12 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
     __syncthreads();
 
     for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
-        const int4 tl = wave_uniform(a.tiles[t]);
-        const BlockDesc bd = wave_uniform(a.blocks[tl.x]);
+        const int4 tl0 = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
+        // A walking tile runs every split of its block in order.
+        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
+        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
         const int m0 = tl.y * MT, nu0 = tl.z * NT;
         const int xs = tl.w * bd.sps;
         const int xe = min(a.V, xs + bd.sps);
@@ -325,15 +329,11 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                 if (mo >= bd.M) continue;
                 const double p1 = acc[0][n][e], p2 = acc[1][n][e], p3 = acc[2][n][e];
                 const double re = p2 - p3, im = (p1 - p2) - p3;
-                if (bd.direct) {
-                    reinterpret_cast<double2 *>(bd.out)[((size_t)po * bd.M + mo) * bd.n3 + d3o] = make_double2(re, im);
-                } else {
-                    double *wsp = reinterpret_cast<double *>(bd.ws);
-                    wsp[((size_t)tl.w * 2 * bd.M + mo) * bd.N + nuo] = re;
-                    wsp[(((size_t)tl.w * 2 + 1) * bd.M + mo) * bd.N + nuo] = im;
-                }
+                put_result<double>(bd, tl.w, mo, nuo, po, d3o, 0, re);
+                put_result<double>(bd, tl.w, mo, nuo, po, d3o, 1, im);
             }
         }
+        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {

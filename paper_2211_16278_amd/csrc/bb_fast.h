@@ -357,8 +357,12 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
     };
 
     for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
-        const int4 tl = a.tiles[t];
-        const BlockDesc bd = a.blocks[tl.x];
+        const int4 tl0 = a.tiles[t];
+        const BlockDesc bd = a.blocks[tl0.x];
+        // A walking tile runs every split of its block in order.
+        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
+        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
         const int d1_0 = (tl.y / bd.n_mt2) * Lt::B1, d2_0 = (tl.y % bd.n_mt2) * B2;
         const int p0 = (tl.z / bd.n_nt3) * bd.bp, d3_0 = (tl.z % bd.n_nt3) * B3;
         const int xs = tl.w * bd.sps;
@@ -712,12 +716,10 @@ __global__ void __launch_bounds__(THREADS, 1) bb_fast(GemmArgs a)
                     const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
                     if (d1 >= bd.n1 || d2 >= bd.n2) continue;
                     const int m = d1 * bd.n2 + d2;
-                    if (bd.direct)
-                        bd.out[(((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + s] = (double)acc[f][n][e];
-                    else
-                        reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + s) * bd.M + m) * bd.N + nu] = acc[f][n][e];
+                    put_result<float>(bd, tl.w, m, nu, p, d3, s, (double)acc[f][n][e]);
                 }
         }
+        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {

@@ -59,7 +59,36 @@ struct BlockDesc {
     int n_nt;                  // n-tiles
     int img_s0;
     int direct;                // 1: one split, the kernel writes out itself; 0: partials in ws
+    int walk;                  // 1: the workgroup of a tile runs all S splits in order and sums them into out
 };
+
+// One element of a tile's result: part 0 (real) or 1 (imaginary) of
+// B[p][m][d3] (m = d1 n2 + d2, column nu = p n3 + d3) from site split s.
+//   direct (one split): written to out;
+//   walk (the tile's workgroup runs every split in order): the first split
+//     writes out and each later one adds to it, in FP64 -- the same sums in
+//     the same order as the split-K reduction of partials (Algorithm 1 sums
+//     the site blocks into tmpBuf the same way), so the block is bitwise
+//     the one the reduction would give;
+//   otherwise: stored as split s's partial for the reduction kernel.
+// A walking tile adds its later splits with a returnless FP64 atomic add:
+// each element has one writer (one lane of one workgroup, splits in program
+// order with a barrier between them), so the adds apply in split order with
+// IEEE round-to-nearest, exactly as a load, add and store would -- but
+// without a load whose latency would serialise the epilogue.
+template <class PartT>
+__device__ __forceinline__ void put_result(const BlockDesc &bd, int s, int m, int nu, int p, int d3, int part, double v)
+{
+    if (bd.direct || bd.walk) {
+        double *o = bd.out + (((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + part;
+        if (bd.walk && s > 0)
+            (void)unsafeAtomicAdd(o, v);
+        else
+            *o = v;
+    } else {
+        reinterpret_cast<PartT *>(bd.ws)[(((size_t)s * 2 + part) * bd.M + m) * bd.N + nu] = (PartT)v;
+    }
+}
 
 // Arguments of one grouped GEMM launch.
 struct GemmArgs {

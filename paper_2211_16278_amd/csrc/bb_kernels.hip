@@ -318,8 +318,12 @@ __global__ void __launch_bounds__(THREADS, 1) bb_gemm(GemmArgs a)
     };
 
     for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
-        const int4 tl = a.tiles[t];
-        const BlockDesc bd = a.blocks[tl.x];
+        const int4 tl0 = a.tiles[t];
+        const BlockDesc bd = a.blocks[tl0.x];
+        // A walking tile runs every split of its block in order.
+        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
+        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
         const int m0 = tl.y * MT, nu0 = tl.z * NT;
         const int xs = tl.w * bd.sps;
         const int xe = min(a.V, xs + bd.sps);
@@ -415,14 +419,10 @@ __global__ void __launch_bounds__(THREADS, 1) bb_gemm(GemmArgs a)
                     const int m = m0 + wave * WR + f * HALF + (row % HALF);
                     const int s = row / HALF;
                     if (m >= bd.M) continue;
-                    if (bd.direct) {
-                        bd.out[(((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + s] = (double)acc[f][n][e];
-                    } else {
-                        typename T::Part *ws = reinterpret_cast<typename T::Part *>(bd.ws);
-                        ws[(((size_t)tl.w * 2 + s) * bd.M + m) * bd.N + nu] = acc[f][n][e];
-                    }
+                    put_result<typename T::Part>(bd, tl.w, m, nu, p, d3, s, (double)acc[f][n][e]);
                 }
         }
+        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {

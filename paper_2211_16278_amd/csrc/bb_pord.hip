@@ -91,8 +91,12 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
     };
 
     for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
-        const int4 tl = wave_uniform(a.tiles[t]);
-        const BlockDesc bd = wave_uniform(a.blocks[tl.x]);
+        const int4 tl0 = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
+        // A walking tile runs every split of its block in order.
+        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
+        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
         // m-tile = (pair block, d3 block); n_mt2 holds the number of d3 blocks.
         const int pb = tl.y / bd.n_mt2, d3_0 = (tl.y % bd.n_mt2) * B3;
         const int m12_0 = pb * NPAIR, M12 = bd.n1 * bd.n2;
@@ -352,13 +356,10 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                         const int pi = (wave * F + f) * PPF + row / B3;
                         const int m = m12_0 + pi, d3 = d3_0 + row % B3;
                         if (m >= M12 || d3 >= bd.n3) continue;
-                        if (bd.direct)
-                            bd.out[(((size_t)p * M12 + m) * bd.n3 + d3) * 2 + s] = (double)acc[f][n][s][e];
-                        else
-                            reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + s) * M12 + m) * bd.N + p * bd.n3 + d3] =
-                                acc[f][n][s][e];
+                        put_result<float>(bd, tl.w, m, p * bd.n3 + d3, p, d3, s, (double)acc[f][n][s][e]);
                     }
             }
+        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {

@@ -178,8 +178,12 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
     };
 
     for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
-        const int4 tl = wave_uniform(a.tiles[t]);
-        const BlockDesc bd = wave_uniform(a.blocks[tl.x]);
+        const int4 tl0 = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
+        // A walking tile runs every split of its block in order.
+        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
+        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
         const int d1_0 = (tl.y / bd.n_mt2) * B1, d2_0 = (tl.y % bd.n_mt2) * B2;
         const int p0 = (tl.z / bd.n_nt3) * bd.bp, d3_0 = (tl.z % bd.n_nt3) * bd.b3;
         const int xs = tl.w * bd.sps;
@@ -471,12 +475,10 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
                     const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
                     if (d1 >= bd.n1 || d2 >= bd.n2) continue;
                     const int m = d1 * bd.n2 + d2;
-                    if (bd.direct)
-                        bd.out[(((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + f] = (double)acc[f][n][e];
-                    else
-                        reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + f) * bd.M + m) * bd.N + nu] = acc[f][n][e];
+                    put_result<float>(bd, tl.w, m, nu, p, d3, f, (double)acc[f][n][e]);
                 }
         }
+        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {
@@ -531,8 +533,12 @@ __global__ void __launch_bounds__(THREADS8, 1) contract8(GemmArgs a)
     };
 
     for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
-        const int4 tl = wave_uniform(a.tiles[t]);
-        const BlockDesc bd = wave_uniform(a.blocks[tl.x]);
+        const int4 tl0 = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
+        // A walking tile runs every split of its block in order.
+        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
+        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
         const int d1_0 = (tl.y / bd.n_mt2) * B1, d2_0 = (tl.y % bd.n_mt2) * B2;
         const int p0 = (tl.z / bd.n_nt3) * bd.bp, d3_0 = (tl.z % bd.n_nt3) * bd.b3;
         const int xs = tl.w * bd.sps;
@@ -790,10 +796,7 @@ __global__ void __launch_bounds__(THREADS8, 1) contract8(GemmArgs a)
                         const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
                         if (d1 >= bd.n1 || d2 >= bd.n2) continue;
                         const int m = d1 * bd.n2 + d2;
-                        if (bd.direct)
-                            bd.out[(((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + f] = (double)acc[f][n][e];
-                        else
-                            reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + f) * bd.M + m) * bd.N + nu] = acc[f][n][e];
+                        put_result<float>(bd, tl.w, m, nu, p, d3, f, (double)acc[f][n][e]);
                     }
             }
         };
@@ -801,6 +804,7 @@ __global__ void __launch_bounds__(THREADS8, 1) contract8(GemmArgs a)
             body(std::integral_constant<int, NBA>{}, std::integral_constant<int, 0>{});
         else
             body(std::integral_constant<int, NB - NBA>{}, std::integral_constant<int, NBA>{});
+        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {
