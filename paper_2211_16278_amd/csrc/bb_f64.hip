@@ -122,13 +122,12 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
     };
     __syncthreads();
 
-    for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
+    // A walking tile runs every split of its block in order: the loop
+    // stays on tile t and steps its split (wsp) up to the block's last.
+    for (int t = next_tile(-1), wsp = 0; t < a.n_tiles;) {
         const int4 tl0 = wave_uniform(a.tiles[t]);
         const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
-        // A walking tile runs every split of its block in order.
-        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
-        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
-        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, tl0.w + wsp);
         const int m0 = tl.y * MT, nu0 = tl.z * NT;
         const int xs = tl.w * bd.sps;
         const int xe = min(a.V, xs + bd.sps);
@@ -318,22 +317,30 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 
         // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  Accumulator register
         // e of a 16x16 f64 fragment holds row 4 e + lane / 16, column lane % 16.
+        with_put_mode(bd, tl.w, [&](auto mode) {
 #pragma unroll
-        for (int n = 0; n < CF; ++n) {
-            const int nuo = nu0 + n * 16 + li;
-            if (nuo >= bd.N) continue;
-            const int po = nuo / bd.n3, d3o = nuo - (nuo / bd.n3) * bd.n3;
+            for (int n = 0; n < CF; ++n) {
+                const int nuo = nu0 + n * 16 + li;
+                if (nuo >= bd.N) continue;
+                const int po = nuo / bd.n3, d3o = nuo - (nuo / bd.n3) * bd.n3;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int mo = m0 + wave * 16 + 4 * e + kg;
-                if (mo >= bd.M) continue;
-                const double p1 = acc[0][n][e], p2 = acc[1][n][e], p3 = acc[2][n][e];
-                const double re = p2 - p3, im = (p1 - p2) - p3;
-                put_result<double>(bd, tl.w, mo, nuo, po, d3o, 0, re);
-                put_result<double>(bd, tl.w, mo, nuo, po, d3o, 1, im);
+                for (int e = 0; e < 4; ++e) {
+                    const int mo = m0 + wave * 16 + 4 * e + kg;
+                    if (mo >= bd.M) continue;
+                    const double p1 = acc[0][n][e], p2 = acc[1][n][e], p3 = acc[2][n][e];
+                    const double re = p2 - p3, im = (p1 - p2) - p3;
+                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nuo, po, d3o, 0, re);
+                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nuo, po, d3o, 1, im);
+                }
             }
+        });
+        if (bd.walk && tl.w + 1 < bd.S) {
+            ++wsp;
+            __syncthreads();  // the split's last LDS reads come before the next split's writes
+        } else {
+            wsp = 0;
+            t = next_tile(t);
         }
-        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {

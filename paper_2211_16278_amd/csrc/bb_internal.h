@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace bb {
 
 enum Prec : int { FP64 = 0, FP32 = 1, BF16X3 = 2 };
@@ -64,30 +66,49 @@ struct BlockDesc {
 
 // One element of a tile's result: part 0 (real) or 1 (imaginary) of
 // B[p][m][d3] (m = d1 n2 + d2, column nu = p n3 + d3) from site split s.
-//   direct (one split): written to out;
-//   walk (the tile's workgroup runs every split in order): the first split
-//     writes out and each later one adds to it, in FP64 -- the same sums in
-//     the same order as the split-K reduction of partials (Algorithm 1 sums
-//     the site blocks into tmpBuf the same way), so the block is bitwise
-//     the one the reduction would give;
-//   otherwise: stored as split s's partial for the reduction kernel.
-// A walking tile adds its later splits with a returnless FP64 atomic add:
-// each element has one writer (one lane of one workgroup, splits in program
-// order with a barrier between them), so the adds apply in split order with
-// IEEE round-to-nearest, exactly as a load, add and store would -- but
-// without a load whose latency would serialise the epilogue.
-template <class PartT>
+//   PUT_STORE (one split, or the first split of a walking tile): written to
+//     out;
+//   PUT_ADD (a later split of a walking tile, whose workgroup runs every
+//     split in order): added to out in FP64 -- the same sums in the same
+//     order as the split-K reduction of partials (Algorithm 1 sums the site
+//     blocks into tmpBuf the same way), so the block is bitwise the one the
+//     reduction would give;
+//   PUT_PARTIAL: stored as split s's partial for the reduction kernel.
+// The add is a returnless FP64 atomic: each element has one writer (one lane
+// of one workgroup, splits in program order with a barrier between them), so
+// the adds apply in split order with IEEE round-to-nearest, exactly as a
+// load, add and store would -- but without a load whose latency would
+// serialise the epilogue.
+enum PutMode : int { PUT_PARTIAL = 0, PUT_STORE = 1, PUT_ADD = 2 };
+
+template <int MODE, class PartT>
 __device__ __forceinline__ void put_result(const BlockDesc &bd, int s, int m, int nu, int p, int d3, int part, double v)
 {
-    if (bd.direct || bd.walk) {
+    if constexpr (MODE == PUT_PARTIAL) {
+        reinterpret_cast<PartT *>(bd.ws)[(((size_t)s * 2 + part) * bd.M + m) * bd.N + nu] = (PartT)v;
+    } else {
         double *o = bd.out + (((size_t)p * bd.M + m) * bd.n3 + d3) * 2 + part;
-        if (bd.walk && s > 0)
+        if constexpr (MODE == PUT_ADD)
             (void)unsafeAtomicAdd(o, v);
         else
             *o = v;
-    } else {
-        reinterpret_cast<PartT *>(bd.ws)[(((size_t)s * 2 + part) * bd.M + m) * bd.N + nu] = (PartT)v;
     }
+}
+
+// Runs the epilogue f with the tile's write mode as a compile-time constant
+// (f(std::integral_constant<int, mode>)): one copy of the epilogue per mode,
+// chosen by a wave-uniform branch, instead of a three-way branch per element
+// inside divergent code, which keeps values of all three paths live and
+// pushes the accumulators out of the register file.
+template <class F>
+__device__ __forceinline__ void with_put_mode(const BlockDesc &bd, int s, F &&f)
+{
+    if (bd.walk && s > 0)
+        f(std::integral_constant<int, PUT_ADD>{});
+    else if (bd.direct || bd.walk)
+        f(std::integral_constant<int, PUT_STORE>{});
+    else
+        f(std::integral_constant<int, PUT_PARTIAL>{});
 }
 
 // Arguments of one grouped GEMM launch.

@@ -317,13 +317,12 @@ __global__ void __launch_bounds__(THREADS, 1) bb_gemm(GemmArgs a)
         }
     };
 
-    for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
-        const int4 tl0 = a.tiles[t];
-        const BlockDesc bd = a.blocks[tl0.x];
-        // A walking tile runs every split of its block in order.
-        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
-        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
-        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
+    // A walking tile runs every split of its block in order: the loop
+    // stays on tile t and steps its split (wsp) up to the block's last.
+    for (int t = next_tile(-1), wsp = 0; t < a.n_tiles;) {
+        const int4 tl0 = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, tl0.w + wsp);
         const int m0 = tl.y * MT, nu0 = tl.z * NT;
         const int xs = tl.w * bd.sps;
         const int xe = min(a.V, xs + bd.sps);
@@ -403,26 +402,34 @@ __global__ void __launch_bounds__(THREADS, 1) bb_gemm(GemmArgs a)
         }
 
         // Epilogue: Re-rows and Im-rows of complex row m, column nu = p*n3 + d3.
-        constexpr int REGS = sizeof(typename T::Acc) / sizeof(acc[0][0][0]);
-        constexpr int HALF = T::FRAG / 2;
-        constexpr int WR = 2 * HALF;  // complex rows per wave
+        with_put_mode(bd, tl.w, [&](auto mode) {
+            constexpr int REGS = sizeof(typename T::Acc) / sizeof(acc[0][0][0]);
+            constexpr int HALF = T::FRAG / 2;
+            constexpr int WR = 2 * HALF;  // complex rows per wave
 #pragma unroll
-        for (int n = 0; n < NB; ++n) {
-            const int nu = nu0 + n * T::FRAG + (lane % T::FRAG);
-            if (nu >= bd.N) continue;
-            const int p = nu / bd.n3, d3 = nu - (nu / bd.n3) * bd.n3;
+            for (int n = 0; n < NB; ++n) {
+                const int nu = nu0 + n * T::FRAG + (lane % T::FRAG);
+                if (nu >= bd.N) continue;
+                const int p = nu / bd.n3, d3 = nu - (nu / bd.n3) * bd.n3;
 #pragma unroll
-            for (int f = 0; f < 2; ++f)
+                for (int f = 0; f < 2; ++f)
 #pragma unroll
-                for (int e = 0; e < REGS; ++e) {
-                    const int row = acc_row<P>(lane, e);
-                    const int m = m0 + wave * WR + f * HALF + (row % HALF);
-                    const int s = row / HALF;
-                    if (m >= bd.M) continue;
-                    put_result<typename T::Part>(bd, tl.w, m, nu, p, d3, s, (double)acc[f][n][e]);
-                }
+                    for (int e = 0; e < REGS; ++e) {
+                        const int row = acc_row<P>(lane, e);
+                        const int m = m0 + wave * WR + f * HALF + (row % HALF);
+                        const int s = row / HALF;
+                        if (m >= bd.M) continue;
+                        put_result<decltype(mode)::value, typename T::Part>(bd, tl.w, m, nu, p, d3, s, (double)acc[f][n][e]);
+                    }
+            }
+        });
+        if (bd.walk && tl.w + 1 < bd.S) {
+            ++wsp;
+            __syncthreads();  // the split's last LDS reads come before the next split's writes
+        } else {
+            wsp = 0;
+            t = next_tile(t);
         }
-        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {

@@ -90,13 +90,12 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
         return __builtin_amdgcn_readfirstlane(s_tile);
     };
 
-    for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
+    // A walking tile runs every split of its block in order: the loop
+    // stays on tile t and steps its split (wsp) up to the block's last.
+    for (int t = next_tile(-1), wsp = 0; t < a.n_tiles;) {
         const int4 tl0 = wave_uniform(a.tiles[t]);
         const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
-        // A walking tile runs every split of its block in order.
-        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
-        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
-        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, tl0.w + wsp);
         // m-tile = (pair block, d3 block); n_mt2 holds the number of d3 blocks.
         const int pb = tl.y / bd.n_mt2, d3_0 = (tl.y % bd.n_mt2) * B3;
         const int m12_0 = pb * NPAIR, M12 = bd.n1 * bd.n2;
@@ -342,24 +341,32 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
         }
 
         // Epilogue: row (pair, d3), column p; Re/Im fragment s.
+        with_put_mode(bd, tl.w, [&](auto mode) {
 #pragma unroll
-        for (int f = 0; f < F; ++f)
+            for (int f = 0; f < F; ++f)
 #pragma unroll
-            for (int n = 0; n < NB; ++n) {
-                const int p = pcol + 32 * n;
-                if (p >= a.n_mom) continue;
+                for (int n = 0; n < NB; ++n) {
+                    const int p = pcol + 32 * n;
+                    if (p >= a.n_mom) continue;
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
+                    for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int row = 8 * (e >> 2) + 4 * g + (e & 3);
-                        const int pi = (wave * F + f) * PPF + row / B3;
-                        const int m = m12_0 + pi, d3 = d3_0 + row % B3;
-                        if (m >= M12 || d3 >= bd.n3) continue;
-                        put_result<float>(bd, tl.w, m, p * bd.n3 + d3, p, d3, s, (double)acc[f][n][s][e]);
-                    }
-            }
-        }  // splits of a walking tile
+                        for (int e = 0; e < 16; ++e) {
+                            const int row = 8 * (e >> 2) + 4 * g + (e & 3);
+                            const int pi = (wave * F + f) * PPF + row / B3;
+                            const int m = m12_0 + pi, d3 = d3_0 + row % B3;
+                            if (m >= M12 || d3 >= bd.n3) continue;
+                            put_result<decltype(mode)::value, float>(bd, tl.w, m, p * bd.n3 + d3, p, d3, s, (double)acc[f][n][s][e]);
+                        }
+                }
+        });
+        if (bd.walk && tl.w + 1 < bd.S) {
+            ++wsp;
+            __syncthreads();  // the split's last LDS reads come before the next split's writes
+        } else {
+            wsp = 0;
+            t = next_tile(t);
+        }
     }
 
     if (a.counter != nullptr && tid == 0) {

@@ -177,13 +177,12 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
         return __builtin_amdgcn_readfirstlane(s_tile);  // uniform: tile data go to scalar registers
     };
 
-    for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
+    // A walking tile runs every split of its block in order: the loop
+    // stays on tile t and steps its split (wsp) up to the block's last.
+    for (int t = next_tile(-1), wsp = 0; t < a.n_tiles;) {
         const int4 tl0 = wave_uniform(a.tiles[t]);
         const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
-        // A walking tile runs every split of its block in order.
-        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
-        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
-        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, tl0.w + wsp);
         const int d1_0 = (tl.y / bd.n_mt2) * B1, d2_0 = (tl.y % bd.n_mt2) * B2;
         const int p0 = (tl.z / bd.n_nt3) * bd.bp, d3_0 = (tl.z % bd.n_nt3) * bd.b3;
         const int xs = tl.w * bd.sps;
@@ -459,26 +458,34 @@ __global__ void __launch_bounds__(THREADS, 1) contract(GemmArgs a)
 
         // Epilogue: fragment f = Re (0) / Im (1) part of complex row
         // 32 wave + row; column -> (p, d3).
-        const int B3 = bd.b3;
+        with_put_mode(bd, tl.w, [&](auto mode) {
+            const int B3 = bd.b3;
 #pragma unroll
-        for (int n = 0; n < NB; ++n) {
-            const int nl = n * 32 + r;
-            const int ip = nl / B3, d3 = d3_0 + nl % B3, p = p0 + ip;
-            if (ip >= bd.bp || p >= a.n_mom || d3 >= bd.n3) continue;
-            const int nu = p * bd.n3 + d3;
+            for (int n = 0; n < NB; ++n) {
+                const int nl = n * 32 + r;
+                const int ip = nl / B3, d3 = d3_0 + nl % B3, p = p0 + ip;
+                if (ip >= bd.bp || p >= a.n_mom || d3 >= bd.n3) continue;
+                const int nu = p * bd.n3 + d3;
 #pragma unroll
-            for (int f = 0; f < 2; ++f)
+                for (int f = 0; f < 2; ++f)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int row = 8 * (e >> 2) + 4 * g + (e & 3);
-                    const int ml = wave * 32 + row;
-                    const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
-                    if (d1 >= bd.n1 || d2 >= bd.n2) continue;
-                    const int m = d1 * bd.n2 + d2;
-                    put_result<float>(bd, tl.w, m, nu, p, d3, f, (double)acc[f][n][e]);
-                }
+                    for (int e = 0; e < 16; ++e) {
+                        const int row = 8 * (e >> 2) + 4 * g + (e & 3);
+                        const int ml = wave * 32 + row;
+                        const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
+                        if (d1 >= bd.n1 || d2 >= bd.n2) continue;
+                        const int m = d1 * bd.n2 + d2;
+                        put_result<decltype(mode)::value, float>(bd, tl.w, m, nu, p, d3, f, (double)acc[f][n][e]);
+                    }
+            }
+        });
+        if (bd.walk && tl.w + 1 < bd.S) {
+            ++wsp;
+            __syncthreads();  // the split's last LDS reads come before the next split's writes
+        } else {
+            wsp = 0;
+            t = next_tile(t);
         }
-        }  // splits of a walking tile
     }
 
     if (a.counter != nullptr && tid == 0) {
@@ -532,13 +539,12 @@ __global__ void __launch_bounds__(THREADS8, 1) contract8(GemmArgs a)
         return __builtin_amdgcn_readfirstlane(s_tile);
     };
 
-    for (int t = next_tile(-1); t < a.n_tiles; t = next_tile(t)) {
+    // A walking tile runs every split of its block in order: the loop
+    // stays on tile t and steps its split (wsp) up to the block's last.
+    for (int t = next_tile(-1), wsp = 0; t < a.n_tiles;) {
         const int4 tl0 = wave_uniform(a.tiles[t]);
         const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
-        // A walking tile runs every split of its block in order.
-        for (int sp = tl0.w; sp < (bd.walk ? bd.S : tl0.w + 1); ++sp) {
-        if (sp > tl0.w) __syncthreads();  // the previous split's last LDS reads come first
-        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, sp);
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, tl0.w + wsp);
         const int d1_0 = (tl.y / bd.n_mt2) * B1, d2_0 = (tl.y % bd.n_mt2) * B2;
         const int p0 = (tl.z / bd.n_nt3) * bd.bp, d3_0 = (tl.z % bd.n_nt3) * bd.b3;
         const int xs = tl.w * bd.sps;
@@ -780,31 +786,39 @@ __global__ void __launch_bounds__(THREADS8, 1) contract8(GemmArgs a)
 
             // Epilogue: fragment f = Re (0) / Im (1) part of complex row
             // 32 wr + row; column -> (p, d3).
-            const int B3 = bd.b3;
+            with_put_mode(bd, tl.w, [&](auto mode) {
+                const int B3 = bd.b3;
 #pragma unroll
-            for (int n = 0; n < NBW; ++n) {
-                const int nl = (N0 + n) * 32 + r;
-                const int ip = nl / B3, d3 = d3_0 + nl % B3, p = p0 + ip;
-                if (ip >= bd.bp || p >= a.n_mom || d3 >= bd.n3) continue;
-                const int nu = p * bd.n3 + d3;
+                for (int n = 0; n < NBW; ++n) {
+                    const int nl = (N0 + n) * 32 + r;
+                    const int ip = nl / B3, d3 = d3_0 + nl % B3, p = p0 + ip;
+                    if (ip >= bd.bp || p >= a.n_mom || d3 >= bd.n3) continue;
+                    const int nu = p * bd.n3 + d3;
 #pragma unroll
-                for (int f = 0; f < 2; ++f)
+                    for (int f = 0; f < 2; ++f)
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int row = 8 * (e >> 2) + 4 * g + (e & 3);
-                        const int ml = wr * 32 + row;
-                        const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
-                        if (d1 >= bd.n1 || d2 >= bd.n2) continue;
-                        const int m = d1 * bd.n2 + d2;
-                        put_result<float>(bd, tl.w, m, nu, p, d3, f, (double)acc[f][n][e]);
-                    }
-            }
+                        for (int e = 0; e < 16; ++e) {
+                            const int row = 8 * (e >> 2) + 4 * g + (e & 3);
+                            const int ml = wr * 32 + row;
+                            const int d1 = d1_0 + ml / B2, d2 = d2_0 + ml % B2;
+                            if (d1 >= bd.n1 || d2 >= bd.n2) continue;
+                            const int m = d1 * bd.n2 + d2;
+                            put_result<decltype(mode)::value, float>(bd, tl.w, m, nu, p, d3, f, (double)acc[f][n][e]);
+                        }
+                }
+            });
         };
         if (swave < 4)
             body(std::integral_constant<int, NBA>{}, std::integral_constant<int, 0>{});
         else
             body(std::integral_constant<int, NB - NBA>{}, std::integral_constant<int, NBA>{});
-        }  // splits of a walking tile
+        if (bd.walk && tl.w + 1 < bd.S) {
+            ++wsp;
+            __syncthreads();  // the split's last LDS reads come before the next split's writes
+        } else {
+            wsp = 0;
+            t = next_tile(t);
+        }
     }
 
     if (a.counter != nullptr && tid == 0) {
