@@ -220,7 +220,7 @@ def batch_workload(torch, dev, name):
 def workspace_gib(args, name):
     if args.workspace_gib is not None:
         return args.workspace_gib
-    return 128 if name == "uneven-32" else 16
+    return {"uneven-32": 128, "batched-48": 40, "large-64": 40}.get(name, 16)
 
 
 def run_batch_workload(args, name):
@@ -602,7 +602,8 @@ def main() -> int:
                          "block against volume and dilution size)")
     ap.add_argument("--workspace-gib", type=int, default=None,
                     help="library workspace cap (default: 128 for uneven-32, whose W images of one step's 512 distinct "
-                         "third fields, 105 GB, then stay resident; 16 otherwise)")
+                         "third fields, 105 GB, then stay resident; 40 for batched-48 and large-64, whose split partials "
+                         "(34 and 16.5 GiB in BF16X3 and FP32) then fit one launch; 16 otherwise)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()

@@ -107,7 +107,12 @@ typedef struct {
                                per SIMD, which split the column fragments
                                (same shapes, images and workspace as 2, and
                                bitwise the same results; the BF16X3 default
-                               up to 16 momenta). */
+                               up to 16 momenta).
+                            5: complex double on the FP64 matrix cores with
+                               three real products per complex product
+                               (FP64 only, any shape; nb 2, 4 or 7 column
+                               fragments of 16; 128-row tiles, D and W built
+                               in LDS; the FP64 default). */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device (paper, Sec. 2 after
@@ -165,9 +170,18 @@ bblock_status bblock_compute_noalloc(bblock_t h, const void *Q1, const void *Q2,
  * timeslice with the same momentum set; Sec. 3: independent blocks run in
  * parallel).
  * Grouped launch over n_desc independent blocks (uneven dilution sizes
- * allowed), one momentum set.  The tile schedule of a batch structure is
- * captured into a hipGraph on first use and replayed when the same structure
- * (count, shapes, momentum count) comes back; only the descriptor table is
+ * allowed), one momentum set: one contraction launch per kernel
+ * instantiation the batch needs (blocks are grouped by it), plus the W-image
+ * launches of kernels 2 and 4, whose blocks with the same third field share
+ * one set of images.  When the batch's tiles fill the device without
+ * splitting the sites and its split partials would not fit the workspace,
+ * each tile's workgroup runs all its site splits in order and adds each
+ * split's result into B in FP64 (walking tiles: no partials, no reduction
+ * launch, no sub-batches; bitwise the result of the split-K reduction; not
+ * for kernel 3, which runs faster in sub-batches); the environment variable
+ * BBLOCK_SPLIT_WALK=0 turns this off, =1 forces it for every block.  The tile schedule of a batch structure is captured into a
+ * hipGraph on first use and replayed when the same structure (count,
+ * shapes, momentum count) comes back; only the descriptor table is
  * re-uploaded.  desc is host memory, read before the call returns. */
 bblock_status bblock_compute_batch(bblock_t h, const bblock_desc *desc, int32_t n_desc,
                                    const int32_t *mom, int32_t n_mom);

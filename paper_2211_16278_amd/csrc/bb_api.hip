@@ -144,7 +144,7 @@ struct bblock_s {
     hipEvent_t static_free = nullptr;
 
     int graph_mode = 2;               // 0: eager, 1: capture and replay, 2: replay schedules of 4+ launches
-    int walk_mode = 2;                // walking tiles: 0 never, 1 every unprojected batch, 2 batches that fill the device
+    int walk_mode = 2;                // walking tiles: 0 never, 1 every unprojected batch, 2 when the partials do not fit
     bool profiling = false;
     int plan_gen = 0;                 // bumped whenever forced or tuned plans change
     // The last batch: when a call repeats it (same descriptors, momenta and
@@ -788,72 +788,108 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         total_tiles_s1 += (long)bp.g.n_mt * bp.g.n_nt;
     }
     // Walking tiles (the sum over sites of Algorithm 1 kept in one
-    // workgroup): a batch whose tiles fill the device without splitting the
-    // sites gives each (block, m-tile, n-tile) to one workgroup, which runs
-    // the block's splits (as few as the FP32 accumulation bound allows) in
-    // order and sums them into the output in FP64.  No partials, no
-    // reduction launch, no workspace beyond W images, so a whole batch of
-    // one kernel instantiation is one launch.  Spin projection keeps the
-    // partials: the combination reads them.
-    const bool walk = !coef && (h->walk_mode == 1 || (h->walk_mode == 2 && total_tiles_s1 >= 2L * h->num_cu));
+    // workgroup): the workgroup of a (block, m-tile, n-tile) runs the block's
+    // splits (as few as the FP32 accumulation bound allows) in order and sums
+    // them into the output in FP64.  No partials, no reduction launch, no
+    // workspace beyond W images, so a batch of one kernel instantiation is
+    // one launch however many blocks it holds.  They need tiles that fill
+    // the device without splitting the sites, and they cost time where the
+    // split schedule keeps the concurrent workgroups on one site range (the
+    // paper-order kernel: 9-15 % on 48^3 and 64^3 batches), so by default a
+    // batch walks only when its split partials would not fit the workspace
+    // (the sub-batches that would take) and the paper-order kernel never
+    // does.  Spin projection keeps the partials: the combination reads them.
+    const bool walk_fill = !coef && h->walk_mode != 0 && (h->walk_mode == 1 || total_tiles_s1 >= 2L * h->num_cu);
+    bool walk = false;
+    auto walk_of = [&](const BlockPlan &bp) { return walk && (h->walk_mode == 1 || bp.plan.kernel != K_PORD); };
     // Split count: a forced plan fixes it; a single block uses its plan's
     // count; batches fill the device; never below the accuracy bound.
-    for (int i = 0; i < n_desc; ++i) {
-        BlockPlan &bp = bps[i];
-        const ShapeKey k{bp.d.n1, bp.d.n2, bp.d.n3, n_mom};
-        const bool fixed = h->forced.count(k) && bp.plan.splits > 0;
-        int S;
-        if (fixed)
-            S = bp.plan.splits;
-        else if (walk)
-            S = s_min;
-        else if (n_desc == 1 && bp.plan.splits > 0)
-            S = single_splits(bp.plan.splits, s_min);
-        else
-            S = std::max<int>(s_min, (int)std::max<long>(1, 2L * h->num_cu / std::max(1L, total_tiles_s1)));
-        bp.need_part = coef != nullptr;
-        bp.walk = walk;
-        set_splits(h, bp, S);
-        if (bp.walk && is_w3(bp.plan.kernel) && bp.rounds > 1) {
-            // A walking tile needs the images of all its splits at once.
-            bp.walk = false;
+    // trial: plan without failing (the walk decision looks at the result).
+    auto split_pass = [&](bool trial) -> bblock_status {
+        for (int i = 0; i < n_desc; ++i) {
+            BlockPlan &bp = bps[i];
+            const ShapeKey k{bp.d.n1, bp.d.n2, bp.d.n3, n_mom};
+            const bool fixed = h->forced.count(k) && bp.plan.splits > 0;
+            int S;
+            if (fixed)
+                S = bp.plan.splits;
+            else if (walk_of(bp))
+                S = s_min;
+            else if (n_desc == 1 && bp.plan.splits > 0)
+                S = single_splits(bp.plan.splits, s_min);
+            else
+                S = std::max<int>(s_min, (int)std::max<long>(1, 2L * h->num_cu / std::max(1L, total_tiles_s1)));
+            bp.need_part = coef != nullptr;
+            bp.walk = walk_of(bp);
             set_splits(h, bp, S);
-        }
-        if (!fixed && bp.ws_bytes > h->ws_eff) set_splits(h, bp, s_min);
-        if (is_w3(bp.plan.kernel) && (bp.ws_bytes > h->ws_eff || !w3_offsets_fit(h, bp))) {
-            // Not even one split's W images fit beside the partials (or the
-            // split is too long for 32-bit offsets): the pipelined kernel
-            // builds W in LDS instead.
-            if (h->forced.count(k))
-                return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the precomputed-W plan needs %zu workspace bytes "
-                            "(cap %zu) and splits of at most 2 GiB of q1/q2", i, bp.ws_bytes, h->ws_eff);
-            // Its column fragments: 7 or 4, whichever pads fewer columns.
-            bp.plan.kernel = K_PIPELINED;
-            bp.g = Geometry{};
-            for (int nb : {7, 4}) {
-                const Geometry g = geometry(h, K_PIPELINED, nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
-                if (g.lds >= 0 && (bp.g.lds < 0 || (long)g.n_nt * g.n_tile < (long)bp.g.n_nt * bp.g.n_tile)) bp.g = g;
+            if (bp.walk && is_w3(bp.plan.kernel) && bp.rounds > 1) {
+                // A walking tile needs the images of all its splits at once.
+                bp.walk = false;
+                set_splits(h, bp, S);
             }
-            bp.plan.nb = bp.g.nb;
-            if (bp.g.lds < 0) return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
-            take_geometry(bp);
-            set_splits(h, bp, S);
-            if (bp.ws_bytes > h->ws_eff) set_splits(h, bp, s_min);
+            if (!fixed && bp.ws_bytes > h->ws_eff) set_splits(h, bp, s_min);
+            if (is_w3(bp.plan.kernel) && (bp.ws_bytes > h->ws_eff || !w3_offsets_fit(h, bp))) {
+                // Not even one split's W images fit beside the partials (or the
+                // split is too long for 32-bit offsets): the pipelined kernel
+                // builds W in LDS instead.
+                if (h->forced.count(k)) {
+                    if (trial) return BBLOCK_EUNSUPPORTED;
+                    return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the precomputed-W plan needs %zu workspace bytes "
+                                "(cap %zu) and splits of at most 2 GiB of q1/q2", i, bp.ws_bytes, h->ws_eff);
+                }
+                // Its column fragments: 7 or 4, whichever pads fewer columns.
+                bp.plan.kernel = K_PIPELINED;
+                bp.g = Geometry{};
+                for (int nb : {7, 4}) {
+                    const Geometry g = geometry(h, K_PIPELINED, nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
+                    if (g.lds >= 0 && (bp.g.lds < 0 || (long)g.n_nt * g.n_tile < (long)bp.g.n_nt * bp.g.n_tile)) bp.g = g;
+                }
+                bp.plan.nb = bp.g.nb;
+                if (bp.g.lds < 0) {
+                    if (trial) return BBLOCK_EUNSUPPORTED;
+                    return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
+                }
+                take_geometry(bp);
+                set_splits(h, bp, S);
+                if (bp.ws_bytes > h->ws_eff) set_splits(h, bp, s_min);
+            }
+            if (bp.plan.kernel == K_PORD && !w3_offsets_fit(h, bp)) {
+                if (h->forced.count(k)) {
+                    if (trial) return BBLOCK_EUNSUPPORTED;
+                    return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the paper-order plan needs splits of at most 2 GiB of "
+                                "q1/q2/q3", i);
+                }
+                bp.plan.kernel = K_GENERIC;
+                bp.plan.nb = 4;
+                bp.g = geometry(h, K_GENERIC, bp.plan.nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
+                if (bp.g.lds < 0) {
+                    if (trial) return BBLOCK_EUNSUPPORTED;
+                    return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
+                }
+                take_geometry(bp);
+                set_splits(h, bp, S);
+            }
+            if (bp.ws_bytes > h->ws_eff) {
+                if (trial) return BBLOCK_ENOMEM;
+                return fail(h, BBLOCK_ENOMEM, "block %d needs %zu workspace bytes, cap is %zu%s", i, bp.ws_bytes, h->ws_eff,
+                            noalloc ? " (what the static scratch of the allocation-free entry point leaves for it)" : "");
+            }
         }
-        if (bp.plan.kernel == K_PORD && !w3_offsets_fit(h, bp)) {
-            if (h->forced.count(k))
-                return fail(h, BBLOCK_EUNSUPPORTED, "block %d: the paper-order plan needs splits of at most 2 GiB of "
-                            "q1/q2/q3", i);
-            bp.plan.kernel = K_GENERIC;
-            bp.plan.nb = 4;
-            bp.g = geometry(h, K_GENERIC, bp.plan.nb, bp.d.n1, bp.d.n2, bp.d.n3, n_mom);
-            if (bp.g.lds < 0) return fail(h, BBLOCK_EUNSUPPORTED, "block %d: no kernel for its shape", i);
-            take_geometry(bp);
-            set_splits(h, bp, S);
-        }
-        if (bp.ws_bytes > h->ws_eff)
-            return fail(h, BBLOCK_ENOMEM, "block %d needs %zu workspace bytes, cap is %zu%s", i, bp.ws_bytes, h->ws_eff,
-                        noalloc ? " (what the static scratch of the allocation-free entry point leaves for it)" : "");
+        return BBLOCK_OK;
+    };
+    if (walk_fill && h->walk_mode == 2) {
+        const std::vector<BlockPlan> bps0 = bps;
+        size_t need = 0;
+        const bblock_status st = split_pass(true);
+        for (const BlockPlan &bp : bps) need += align_up(bp.ws_bytes, 256);
+        walk = st != BBLOCK_OK || need > h->ws_eff;
+        bps = bps0;
+    } else {
+        walk = walk_fill;
+    }
+    {
+        const bblock_status st = split_pass(false);
+        if (st != BBLOCK_OK) return st;
     }
 
     // Work units: (block, round).  Every block is one unit, except a
@@ -1226,8 +1262,9 @@ bblock_status bblock_create(bblock_t *out, int32_t L, int32_t prec, int32_t in_d
     if (hipEventCreateWithFlags(&h->static_free, hipEventDisableTiming) != hipSuccess)
         return bail(BBLOCK_EHIP, "event creation failed");
 
-    // Walking tiles: BBLOCK_SPLIT_WALK=0 never, 1 in every unprojected batch
-    // (tests force it on small batches), unset: batches that fill the device.
+    // Walking tiles: BBLOCK_SPLIT_WALK=0 never, 1 every block of every
+    // unprojected batch (tests force it on small batches), unset: batches
+    // that fill the device and whose partials exceed the workspace.
     if (const char *w = std::getenv("BBLOCK_SPLIT_WALK")) h->walk_mode = std::atoi(w) == 0 ? 0 : (std::atoi(w) == 1 ? 1 : 2);
     // Tuned plans persisted by earlier runs.
     if (const char *path = std::getenv("BBLOCK_TUNE_CACHE")) {

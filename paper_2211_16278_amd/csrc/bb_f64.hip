@@ -22,20 +22,25 @@
 //     past the split, of rows past M or of columns past N are out of range
 //     and return zero (no masks);
 //   * the diquark and the phase product are written as fused multiply-adds;
-//   * the column sum Wr + Wi is formed once per element by the generation
-//     waves and stored as a third plane, not once per row fragment by the
-//     matrix waves.
+//   * the column sum Wr + Wi is formed once per element when W is built and
+//     stored as a third plane, not once per row fragment before each MFMA.
 //
-// Workgroup: eight wave64, two per SIMD, with two roles.
-//   * Waves 0-3 (matrix waves) own 16 complex rows each of the 64-row tile and
-//     all 16 CF columns: 3 x CF accumulator fragments of 16 x 16 doubles.
-//     Per chunk of 4 sites (12 kappa) they run 3 k-steps x 3 CF MFMAs from
-//     LDS buffer i & 1.
-//   * Waves 4-7 (generation waves) build the D and W tiles of chunk i + 1 into
-//     the other buffer from registers loaded about two chunks earlier.
-// One barrier per chunk.  Tiles are stored k-major ([plane][kappa][row]) with
-// row strides of 16 mod 32 doubles, so the two k-groups of a half-wave read
-// disjoint LDS banks.
+// Workgroup: eight wave64, two per SIMD, all doing the same work (two waves
+// per SIMD reach the full FP64 MFMA rate; one does not).  Tile: 128 complex
+// rows x 16 CF columns x one site split.  Wave w owns rows [16 w, 16 w + 16)
+// and all columns: 3 x CF accumulator fragments of 16 x 16 doubles (one per
+// product P1, P2, P3).  Per chunk of 4 sites (12 kappa) a wave runs 3 k-steps
+// x CF fragments x 3 MFMAs from LDS buffer i & 1, reading the operands of
+// fragment f + 1 during fragment f.  Between its last 11 MFMA groups (fenced
+// by scheduling barriers) it builds its share of chunk i + 1 into the other
+// buffer from registers loaded a chunk earlier: each thread one diquark item
+// (row tid % 128 at site tid / 128, three colours) and, in the waves that
+// hold one, one W item (column tid % NT at site tid / NT); then it issues the
+// loads of chunk i + 2.  The latencies of those loads and of the LDS stores
+// then run under the MFMAs, and only the issue slots of the vector
+// instructions cost matrix time.  One barrier per chunk.  Tiles are stored
+// k-major ([plane][kappa][row]) with row strides of 16 mod 32 doubles, so the
+// two k-groups of a half-wave read disjoint LDS banks.
 #include <algorithm>
 
 #include "bb_fast.h"

@@ -340,8 +340,13 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
             __syncthreads();
         }
 
-        // Epilogue: row (pair, d3), column p; Re/Im fragment s.
-        with_put_mode(bd, tl.w, [&](auto mode) {
+        // Epilogue: row (pair, d3), column p; Re/Im fragment s.  A later
+        // split of a walking tile adds to out (put_result's PUT_ADD);
+        // otherwise the tile stores to out (one split, or a walking tile's
+        // first) or its split partial.  Written out here rather than through
+        // put_result: in this kernel that form, or one copy of the loops per
+        // write mode, makes the compiler spill in the contraction loops.
+        if (bd.walk && tl.w > 0) {
 #pragma unroll
             for (int f = 0; f < F; ++f)
 #pragma unroll
@@ -356,10 +361,33 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                             const int pi = (wave * F + f) * PPF + row / B3;
                             const int m = m12_0 + pi, d3 = d3_0 + row % B3;
                             if (m >= M12 || d3 >= bd.n3) continue;
-                            put_result<decltype(mode)::value, float>(bd, tl.w, m, p * bd.n3 + d3, p, d3, s, (double)acc[f][n][s][e]);
+                            (void)unsafeAtomicAdd(bd.out + (((size_t)p * M12 + m) * bd.n3 + d3) * 2 + s,
+                                                  (double)acc[f][n][s][e]);
                         }
                 }
-        });
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; ++f)
+#pragma unroll
+                for (int n = 0; n < NB; ++n) {
+                    const int p = pcol + 32 * n;
+                    if (p >= a.n_mom) continue;
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) {
+                            const int row = 8 * (e >> 2) + 4 * g + (e & 3);
+                            const int pi = (wave * F + f) * PPF + row / B3;
+                            const int m = m12_0 + pi, d3 = d3_0 + row % B3;
+                            if (m >= M12 || d3 >= bd.n3) continue;
+                            if (bd.direct || bd.walk)
+                                bd.out[(((size_t)p * M12 + m) * bd.n3 + d3) * 2 + s] = (double)acc[f][n][s][e];
+                            else
+                                reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + s) * M12 + m) * bd.N + p * bd.n3 + d3] =
+                                    acc[f][n][s][e];
+                        }
+                }
+        }
         if (bd.walk && tl.w + 1 < bd.S) {
             ++wsp;
             __syncthreads();  // the split's last LDS reads come before the next split's writes
