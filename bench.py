@@ -69,6 +69,7 @@ KERNEL_SOURCES = {
     "bb::fast::": ("bb_fast.h", "bb_fast_fp32.hip", "bb_fast_bf16.hip", "bb_internal.h"),
     "bb::pord::": ("bb_pord.hip", "bb_fast.h", "bb_internal.h"),
     "bb::bb_gemm": ("bb_kernels.hip", "bb_internal.h"),
+    "bb::bb_reduce": ("bb_kernels.hip", "bb_internal.h"),
     "bb::f64::": ("bb_f64.hip", "bb_internal.h"),
 }
 
@@ -124,17 +125,23 @@ def kernel_source_sha(files) -> str:
 
 
 def read_traffic(path_name: str, workload: str, kname: str):
-    """HBM bytes per launch of a path's contraction kernel from the committed
-    counter summary, or None when there is none, it is of another kernel, or
-    the kernel's sources changed since the counters were taken."""
+    """HBM bytes of a path from the committed counter summary: (bytes per
+    launch of the contraction kernel, bytes of the whole step, the minimal
+    bytes of one block).  A figure is None when there is no summary, it is
+    of another kernel, or a kernel's sources changed since the counters were
+    taken."""
     fn = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (path_name, workload))
     if not os.path.exists(fn):
-        return None
+        return None, None, None
     with open(fn) as f:
         rec = json.load(f)
     if rec.get("kernel") != kname or rec.get("kernel_source_sha") != kernel_source_sha(sources_of(kname)):
-        return None
-    return rec.get("hbm_bytes_per_launch")
+        return None, None, rec.get("minimal_block_bytes")
+    step = rec.get("step_kernels")
+    step_bytes = None
+    if step and all(k["kernel_source_sha"] == kernel_source_sha(sources_of(k["kernel"])) for k in step):
+        step_bytes = sum(k["hbm_bytes_per_step"] for k in step)
+    return rec.get("hbm_bytes_per_launch"), step_bytes, rec.get("minimal_block_bytes")
 
 
 def device_fields(torch, dev, shape_list, dtype, seed):
@@ -692,6 +699,9 @@ def main() -> int:
         f_exec = mfma_flops_executed(pname, plan, f_gemm)
         ach = f_exec / (g_avg * 1e-3) / 1e12
         kname = kernel_name(pname, plan, n, n)
+        # HBM bytes from the committed counters; the minimal bytes of a block
+        # are its inputs read once and its output written once.
+        traffic, step_traffic, minimal_bytes = read_traffic(pname, "headline-32", kname)
         paths[pname] = {
             "blocks_per_s": 1e3 / step_ms,
             "ms_per_step": step_ms,
@@ -711,7 +721,9 @@ def main() -> int:
             "roofline": {"bound": "mfma", "kernel": kname, "achieved": ach, "peak": PEAK_TFLOPS[pname],
                          "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[pname],
                          "step_frac": f_exec / (step_ms * 1e-3) / 1e12 / PEAK_TFLOPS[pname],
-                         "traffic": read_traffic(pname, "headline-32", kname),
+                         "traffic": traffic,
+                         "step_traffic": step_traffic,
+                         "minimal_bytes": minimal_bytes,
                          "flops_per_launch": f_exec,
                          "note": "achieved = MFMA flops one launch executes (%s) / mean event-timed duration of the "
                                  "contraction kernel; step_frac uses the whole step" % flops_note(pname, plan)},
