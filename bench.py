@@ -24,6 +24,7 @@ import gc
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -114,13 +115,17 @@ class no_gc:
 
 
 def kernel_source_sha(files) -> str:
-    """Hash of the sources a kernel is compiled from: counter figures taken
-    for another hash no longer describe the kernel that runs."""
+    """Hash of the code a kernel is compiled from (comments and layout
+    removed): counter figures taken for another hash no longer describe the
+    kernel that runs."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2211_16278_amd", "csrc")
     for f in files:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

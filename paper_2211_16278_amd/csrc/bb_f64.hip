@@ -25,22 +25,22 @@
 //   * the column sum Wr + Wi is formed once per element when W is built and
 //     stored as a third plane, not once per row fragment before each MFMA.
 //
-// Workgroup: eight wave64, two per SIMD, all doing the same work (two waves
-// per SIMD reach the full FP64 MFMA rate; one does not).  Tile: 128 complex
-// rows x 16 CF columns x one site split.  Wave w owns rows [16 w, 16 w + 16)
-// and all columns: 3 x CF accumulator fragments of 16 x 16 doubles (one per
-// product P1, P2, P3).  Per chunk of 4 sites (12 kappa) a wave runs 3 k-steps
-// x CF fragments x 3 MFMAs from LDS buffer i & 1, reading the operands of
-// fragment f + 1 during fragment f.  Between its last 11 MFMA groups (fenced
+// Workgroup: eight wave64, two per SIMD, all doing the same work (while one
+// wave of a SIMD waits on LDS or a barrier, the other's MFMAs run).  Tile: 128
+// complex rows x 16 CF columns x one site split.  Wave w owns rows 16 w to
+// 16 w + 15 and all columns: 3 x CF accumulator fragments of 16 x 16 doubles
+// (one per product P1, P2, P3).  Per chunk of 4 sites (12 kappa) a wave runs 3
+// k-steps x CF fragments x 3 MFMAs from LDS buffer i & 1, reading the operands
+// of fragment f + 1 during fragment f.  Between its last 11 MFMA groups (fenced
 // by scheduling barriers) it builds its share of chunk i + 1 into the other
 // buffer from registers loaded a chunk earlier: each thread one diquark item
-// (row tid % 128 at site tid / 128, three colours) and, in the waves that
-// hold one, one W item (column tid % NT at site tid / NT); then it issues the
-// loads of chunk i + 2.  The latencies of those loads and of the LDS stores
-// then run under the MFMAs, and only the issue slots of the vector
-// instructions cost matrix time.  One barrier per chunk.  Tiles are stored
-// k-major ([plane][kappa][row]) with row strides of 16 mod 32 doubles, so the
-// two k-groups of a half-wave read disjoint LDS banks.
+// (row tid % 128 at site tid / 128, three colours) and, in the waves that hold
+// one, one W item (column tid % NT at site tid / NT); then it issues the loads
+// of chunk i + 2.  The latencies of those loads and of the LDS stores then run
+// under the MFMAs, and only the issue slots of the vector instructions cost
+// matrix time.  One barrier per chunk.  Tiles are stored k-major
+// ([plane][kappa][row]) with row strides of 16 mod 32 doubles, so the two
+// k-groups of a half-wave read disjoint LDS banks.
 #include <algorithm>
 
 #include "bb_fast.h"
