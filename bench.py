@@ -42,6 +42,8 @@ def kernel_name(path, plan, n2, n3):
     """Name of the contraction kernel a plan launches (as rocprofv3 lists it)."""
     if plan["kernel"] == 5:
         return "bb::f64::contract<%d, false>" % plan["nb"]
+    if plan["kernel"] == 6:
+        return "bb::f64p::contract<%d, %d, false>" % (plan["nb"], 32 if n3 >= 32 else 16)
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
         return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)
@@ -72,6 +74,7 @@ KERNEL_SOURCES = {
     "bb::bb_gemm": ("bb_kernels.hip", "bb_internal.h"),
     "bb::bb_reduce": ("bb_kernels.hip", "bb_internal.h"),
     "bb::f64::": ("bb_f64.hip", "bb_internal.h"),
+    "bb::f64p::": ("bb_f64p.hip", "bb_fast.h", "bb_internal.h"),
 }
 
 
@@ -87,15 +90,21 @@ def mfma_flops_executed(path, plan, f_gemm):
     (F_gemm = 24 n_mom V n^3, 8 real flops per complex multiply-add), three
     times over for the three BF16 products of BF16x3; the FP64 kernel 5 forms
     each complex product from three real products (6 real flops per complex
-    multiply-add), 3/4 of F_gemm."""
+    multiply-add), 3/4 of F_gemm; the FP64 paper-order kernel 6 only the
+    momentum projection, with three real products (6 n_mom V n^3), 1/4 of
+    F_gemm."""
     if plan["kernel"] == 5:
         return 0.75 * f_gemm
+    if plan["kernel"] == 6:
+        return 0.25 * f_gemm
     return MFMA_PASSES[path] * f_gemm
 
 
 def flops_note(path, plan):
     if plan["kernel"] == 5:
         return "18 n_mom V n^3: three real products per complex multiply-add"
+    if plan["kernel"] == 6:
+        return "6 n_mom V n^3: the momentum projection with three real products"
     return "%d x 24 n_mom V n^3" % MFMA_PASSES[path]
 
 
@@ -164,11 +173,12 @@ def device_fields(torch, dev, shape_list, dtype, seed):
 
 
 def mfma_flops(plan, V, n1, n2, n3, n_mom):
-    """Algorithmic flops of one MFMA pass of the formulation a plan runs: the
-    fused GEMM (kernels 0-2, 24 n_mom V n1 n2 n3) or, for the paper-order
-    kernel 3, only the momentum projection (8 n_mom V n1 n2 n3; its singlet
-    runs on the vector unit)."""
-    per = 8.0 if plan["kernel"] == 3 else (18.0 if plan["kernel"] == 5 else 24.0)
+    """Flops of one MFMA pass of the formulation a plan runs: the fused GEMM
+    (24 n_mom V n1 n2 n3; 18 for FP64 kernel 5's three real products) or, for
+    the paper-order kernels, only the momentum projection (8 n_mom V n1 n2 n3
+    for kernel 3, 6 for FP64 kernel 6; their singlet runs on the vector
+    unit)."""
+    per = {3: 8.0, 5: 18.0, 6: 6.0}.get(plan["kernel"], 24.0)
     return per * n_mom * V * n1 * n2 * n3
 
 

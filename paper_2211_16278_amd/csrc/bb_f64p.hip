@@ -1,0 +1,376 @@
+// FP64 paper-order contraction kernel of libbblock.so (gfx950, plan kernel 6).
+//
+// The block of the paper (Sec. 2, eq. (3)) in the order of Algorithm 1: per
+// site the singlet
+//   S[x; (d1,d2), d3] = sum_c D_c[x; d1,d2] q3_c[x; d3],  D_c = eps_abc q1_a q2_b,
+// then its projection on the momenta, a complex GEMM with rows (d1,d2,d3),
+// columns p and contraction index x:
+//   B[p][(d1,d2)][d3] = sum_x S[x; (d1,d2), d3] exp(-i p.x),
+// in complex double throughout.  Per (site, row) the matrix cores do one
+// complex multiply-add per momentum instead of the fused form's three (one
+// per colour), and the vector unit forms the singlet (12 FMAs); on gfx950
+// FP64 vector and matrix work run at the same rate and do not overlap, so
+// this order is the cheaper one once the momenta outnumber the colours'
+// share of the padding.
+//
+// Complex products with three real products (Gauss), as in kernel 5:
+//   P1 = (Sr + Si)(er + ei),  P2 = Sr er,  P3 = Si ei,
+//   Re = P2 - P3,  Im = P1 - P2 - P3,  e = exp(-i p.x).
+//
+// Workgroup: eight wave64, two per SIMD.  Tile: 128 rows = NPAIR (d1,d2)
+// pairs x a block of B3 d3 values, 16 CF momenta, one site split.  Wave w
+// owns rows 16 w to 16 w + 15 (16 d3 values of one pair) and all momenta:
+// 3 x CF accumulator fragments of v_mfma_f64_16x16x4_f64.  The A operand of
+// a k-step (4 sites) is the singlet itself: lane l forms S of row
+// 16 w + l % 16 at site l / 16 from the diquark and q3 tiles in LDS, in
+// registers, and feeds it to the MFMAs.  Per chunk of 16 sites the
+// workgroup builds the next chunk's tiles (the diquark of its pairs, q3 of
+// its d3 block, the phases of its momenta with their Re + Im plane) into the
+// other LDS buffer from registers loaded a chunk earlier, and issues the
+// loads of the chunk after it.  Quark and phase-index loads go through
+// per-chunk buffer resources: loads past the split, of pairs past M, of d3
+// past n3 or momenta past n_mom return zero (no masks).
+#include <algorithm>
+
+#include "bb_fast.h"
+#include "bb_internal.h"
+
+namespace bb {
+namespace f64p {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int WG = 512;     // eight waves
+constexpr int MT = 128;     // rows (pair, d3) per tile, 16 per wave
+constexpr int SITES = 16;   // sites per chunk
+constexpr int KS = SITES / 4;  // k-steps per chunk
+constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past any range: loads return zero
+
+template <int CF, int B3>
+struct Shape {
+    static constexpr int NPAIR = MT / B3;                     // (d1,d2) pairs per tile
+    static constexpr int NC = 16 * CF;                        // momenta per tile
+    static constexpr int PS = (NC % 32 == 0) ? NC + 16 : NC;  // site stride of the phase planes (doubles)
+    static constexpr int ND = NPAIR * SITES;                  // diquark items per chunk
+    static constexpr int NQ = SITES * 3 * B3;                 // q3 values per chunk
+    static constexpr int NP = SITES * NC;                     // phases per chunk
+    static constexpr int JQ = (NQ + WG - 1) / WG, JP = (NP + WG - 1) / WG;
+    // One buffer: D [3][SITES][NPAIR] and q3 [3][SITES][B3] as (re, im)
+    // pairs, then the phase planes Re, Im, Re + Im [SITES][PS].
+    static constexpr int DOFF = 0, QOFF = 2 * 3 * SITES * NPAIR, POFF = QOFF + 2 * 3 * SITES * B3;
+    static constexpr int BUF = POFF + 3 * SITES * PS;  // doubles
+    static constexpr size_t lds = (size_t)2 * BUF * 8 + (size_t)MAX_L * 16;
+    static_assert(PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
+    static_assert(B3 % 16 == 0 && MT % B3 == 0, "a wave's 16 rows are d3 values of one pair");
+    static_assert(ND % 64 == 0 && ND <= WG, "diquark items end on a wave boundary, one per thread");
+    static_assert(NQ % 256 == 0 && NP % 256 == 0, "q3 and phase items end on a wave boundary");
+};
+
+template <bool C64>
+struct In {
+    static constexpr int ESZ = 16;
+};
+template <>
+struct In<true> {
+    static constexpr int ESZ = 8;
+};
+
+template <bool C64>
+__device__ __forceinline__ double2 ldq(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+{
+    if constexpr (C64) {
+        const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        return make_double2(v.x, v.y);
+    } else {
+        return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    }
+}
+
+// Resource over sites [x0, x0 + SITES) of a field [V][3][n] (bytes in range:
+// the sites below xe only; none when x0 >= xe).
+template <bool C64>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int n, int x0, int xe)
+{
+    constexpr int ESZ = In<C64>::ESZ;
+    const int ns = __builtin_amdgcn_readfirstlane(min(max(xe - x0, 0), SITES));  // wave-uniform: no waterfall
+    const unsigned char *base = static_cast<const unsigned char *>(q) + (size_t)x0 * 3 * n * ESZ;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, ns * 3 * n * ESZ, 0x00020000);
+}
+
+template <int CF, int B3, bool C64>
+__global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
+{
+    using Sh = Shape<CF, B3>;
+    constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF;
+    constexpr int ESZ = In<C64>::ESZ;
+    __shared__ __align__(16) double lds[2 * BUF];
+    __shared__ double2 roots[MAX_L];
+    __shared__ int s_tile;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int k = tid; k < a.L; k += WG) roots[k] = make_double2(a.roots[2 * k], a.roots[2 * k + 1]);
+
+    auto next_tile = [&](int current) -> int {
+        if (a.counter == nullptr) return current < 0 ? (int)blockIdx.x : a.n_tiles;
+        __syncthreads();
+        if (tid == 0) s_tile = atomicAdd(&a.counter[0], 1);
+        __syncthreads();
+        return __builtin_amdgcn_readfirstlane(s_tile);
+    };
+    __syncthreads();
+
+    // A walking tile runs every split of its block in order: the loop
+    // stays on tile t and steps its split (wsp) up to the block's last.
+    for (int t = next_tile(-1), wsp = 0; t < a.n_tiles;) {
+        const int4 tl0 = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, tl0.w + wsp);
+        // m-tile = (pair block, d3 block); n_mt2 holds the number of d3 blocks.
+        const int m12_0 = (tl.y / bd.n_mt2) * NPAIR, d3_0 = (tl.y % bd.n_mt2) * B3;
+        const int p0 = tl.z * NC;
+        const int M12 = bd.M;
+        const int xs = tl.w * bd.sps;
+        const int xe = min(a.V, xs + bd.sps);
+        const int n_chunks = (xe - xs + SITES - 1) / SITES;
+
+        // ---- generation items of this thread (tile invariant) ----
+        // Diquark item: pair tid % NPAIR at site tid / NPAIR (threads past ND: none).
+        const bool has_d = wave * 64 < Sh::ND;  // wave-uniform
+        const int dp = tid % NPAIR, ds = tid / NPAIR;
+        const int m = m12_0 + dp;
+        const bool mok = has_d && m < M12;
+        const int d1 = mok ? m / bd.n2 : 0, d2 = mok ? m - (m / bd.n2) * bd.n2 : 0;
+        uint32_t o1[3], o2[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o1[c] = mok ? (uint32_t)(((ds * 3 + c) * bd.n1 + d1) * ESZ) : OOB;
+            o2[c] = mok ? (uint32_t)(((ds * 3 + c) * bd.n2 + d2) * ESZ) : OOB;
+        }
+        // q3 items q = tid + WG j = ((s 3 + c) B3 + d): offsets in the chunk.
+        uint32_t o3[Sh::JQ];
+#pragma unroll
+        for (int j = 0; j < Sh::JQ; ++j) {
+            const int q = tid + WG * j;
+            const int d = q % B3, sc = q / B3;
+            o3[j] = (q < Sh::NQ && d3_0 + d < bd.n3) ? (uint32_t)((sc * bd.n3 + d3_0 + d) * ESZ) : OOB;
+        }
+        // Phase items q = tid + WG j = (s NC + jc): momentum p0 + jc at site s.
+        uint32_t ok[Sh::JP];
+#pragma unroll
+        for (int j = 0; j < Sh::JP; ++j) {
+            const int q = tid + WG * j;
+            const int jc = q % NC, s = q / NC;
+            ok[j] = (q < Sh::NP && p0 + jc < a.n_mom) ? (uint32_t)((p0 + jc) * a.kstride + s) : OOB;
+        }
+        const int krec = a.n_mom * a.kstride;
+
+        double2 u[3], v[3], w[Sh::JQ];
+        uint32_t kk[Sh::JP];
+        auto issue = [&](int ci) {
+            const int x0 = __builtin_amdgcn_readfirstlane(xs + ci * SITES);
+            if (has_d) {
+                const __amdgpu_buffer_rsrc_t rs1 = chunk_rsrc<C64>(bd.q1, bd.n1, x0, xe);
+                const __amdgpu_buffer_rsrc_t rs2 = chunk_rsrc<C64>(bd.q2, bd.n2, x0, xe);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    u[c] = ldq<C64>(rs1, o1[c]);
+                    v[c] = ldq<C64>(rs2, o2[c]);
+                }
+            }
+            const __amdgpu_buffer_rsrc_t rs3 = chunk_rsrc<C64>(bd.q3, bd.n3, x0, xe);
+#pragma unroll
+            for (int j = 0; j < Sh::JQ; ++j) w[j] = ldq<C64>(rs3, o3[j]);
+            const __amdgpu_buffer_rsrc_t rsk = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.kidx + min(x0, krec)), (short)0, max(krec - x0, 0), 0x00020000);
+#pragma unroll
+            for (int j = 0; j < Sh::JP; ++j) kk[j] = __builtin_amdgcn_raw_buffer_load_b8(rsk, ok[j], 0, 0);
+        };
+        // The loaded chunk into buffer b: diquark u_a v_b - u_b v_a
+        // (eps_{a b c} = +1) per colour, q3 as loaded, the phases
+        // roots[k] = exp(-2 pi i k / L) with their Re + Im plane.
+        auto build = [&](int b) {
+            asm volatile("" : "+s"(b));  // one base register per buffer, immediate offsets from it
+            double *base = lds + b * BUF;
+            double2 *Dt = reinterpret_cast<double2 *>(base + Sh::DOFF);
+            double2 *Qt = reinterpret_cast<double2 *>(base + Sh::QOFF);
+            double *Pr = base + Sh::POFF, *Pi = Pr + SITES * PS, *Ps = Pi + SITES * PS;
+            if (has_d) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double2 ua = u[(c + 1) % 3], ub = u[(c + 2) % 3];
+                    const double2 va = v[(c + 1) % 3], vb = v[(c + 2) % 3];
+                    const double re = __builtin_fma(ua.x, vb.x, __builtin_fma(-ua.y, vb.y, __builtin_fma(-ub.x, va.x, ub.y * va.y)));
+                    const double im = __builtin_fma(ua.x, vb.y, __builtin_fma(ua.y, vb.x, __builtin_fma(-ub.x, va.y, -(ub.y * va.x))));
+                    Dt[(c * SITES + ds) * NPAIR + dp] = make_double2(re, im);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < Sh::JQ; ++j) {
+                const int q = tid + WG * j;
+                if (q < Sh::NQ) {
+                    const int d = q % B3, sc = q / B3, s = sc / 3, c = sc - 3 * s;
+                    Qt[(c * SITES + s) * B3 + d] = w[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < Sh::JP; ++j) {
+                const int q = tid + WG * j;
+                if (q < Sh::NP) {
+                    const int jc = q % NC, s = q / NC;
+                    const double2 e = roots[kk[j]];
+                    Pr[s * PS + jc] = e.x;
+                    Pi[s * PS + jc] = e.y;
+                    Ps[s * PS + jc] = e.x + e.y;
+                }
+            }
+        };
+
+        d4_t acc[3][CF];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int n = 0; n < CF; ++n) acc[q][n] = d4_t{0.0, 0.0, 0.0, 0.0};
+        // A[i][k] from lane i + 16 k: row 16 wave + i at site k of the k-step.
+        const int li = lane & 15, kg = lane >> 4;
+        const int rw = wave * 16 + li;
+        const int pair_l = rw / B3, d3_l = rw % B3;
+
+        // One chunk from buffer b: per k-step the singlets of this lane's
+        // (row, site) from LDS, then 3 CF MFMAs; after the first k-step the
+        // next chunk's tiles go into buffer b ^ 1 and the loads of the chunk
+        // after it are issued.
+        auto chunk = [&](int b, int ci_next) {
+            asm volatile("" : "+s"(b));
+            // Per-lane bases (one address each; the k-step, colour, plane and
+            // fragment offsets are immediates).
+            const double *base = lds + b * BUF;
+            const double2 *Dl = reinterpret_cast<const double2 *>(base + Sh::DOFF) + kg * NPAIR + pair_l;
+            const double2 *Ql = reinterpret_cast<const double2 *>(base + Sh::QOFF) + kg * B3 + d3_l;
+            const double *Pl = base + Sh::POFF + kg * PS + li;
+            double2 dv[2][3], qv[2][3];
+            double br[2][CF], bi[2][CF], bs[2][CF];
+            // Operands of k-step ks into register set slot: the diquark and
+            // q3 of this lane's (row, site), the phases of its columns.
+            auto read_s = [&](int ks, int slot) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dv[slot][c] = Dl[(c * SITES + 4 * ks) * NPAIR];
+                    qv[slot][c] = Ql[(c * SITES + 4 * ks) * B3];
+                }
+#pragma unroll
+                for (int n = 0; n < CF; ++n) {
+                    br[slot][n] = Pl[4 * ks * PS + n * 16];
+                    bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * 16];
+                    bs[slot][n] = Pl[(2 * SITES + 4 * ks) * PS + n * 16];
+                }
+            };
+            read_s(0, 0);
+            fast::static_for<0, KS>([&](auto kk_) {
+                constexpr int ks = kk_, slot = ks & 1;
+                // Singlet S = sum_c D_c q3_c (complex), its Re + Im.
+                double sr = __builtin_fma(dv[slot][0].x, qv[slot][0].x, -(dv[slot][0].y * qv[slot][0].y));
+                double si = __builtin_fma(dv[slot][0].x, qv[slot][0].y, dv[slot][0].y * qv[slot][0].x);
+#pragma unroll
+                for (int c = 1; c < 3; ++c) {
+                    sr = __builtin_fma(dv[slot][c].x, qv[slot][c].x, sr);
+                    sr = __builtin_fma(-dv[slot][c].y, qv[slot][c].y, sr);
+                    si = __builtin_fma(dv[slot][c].x, qv[slot][c].y, si);
+                    si = __builtin_fma(dv[slot][c].y, qv[slot][c].x, si);
+                }
+                const double ss = sr + si;
+                // The next k-step's operands load under this one's MFMAs.
+                if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
+#pragma unroll
+                for (int n = 0; n < CF; ++n) {
+                    acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ss, bs[slot][n], acc[0][n], 0, 0, 0);
+                    acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(sr, br[slot][n], acc[1][n], 0, 0, 0);
+                    acc[2][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(si, bi[slot][n], acc[2][n], 0, 0, 0);
+                }
+                if constexpr (ks == 0) {
+                    build(b ^ 1);
+                    issue(ci_next);  // past the split the loads are out of range (zeros)
+                }
+            });
+        };
+
+        // Prologue: chunk 0 into buffer 0, chunk 1 in registers.
+        issue(0);
+        build(0);
+        issue(1);
+        __syncthreads();
+        for (int i = 0; i < n_chunks; ++i) {
+            chunk(i & 1, i + 2);
+            __syncthreads();
+        }
+
+        // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  Accumulator register
+        // e of a 16x16 f64 fragment holds row 4 e + lane / 16, column lane % 16.
+        with_put_mode(bd, tl.w, [&](auto mode) {
+#pragma unroll
+            for (int n = 0; n < CF; ++n) {
+                const int p = p0 + n * 16 + li;
+                if (p >= a.n_mom) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = wave * 16 + 4 * e + kg;
+                    const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
+                    if (mo >= M12 || d3 >= bd.n3) continue;
+                    const double p1 = acc[0][n][e], p2 = acc[1][n][e], p3 = acc[2][n][e];
+                    const double re = p2 - p3, im = (p1 - p2) - p3;
+                    const int nu = p * bd.n3 + d3;
+                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 0, re);
+                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 1, im);
+                }
+            }
+        });
+        if (bd.walk && tl.w + 1 < bd.S) {
+            ++wsp;
+            __syncthreads();  // the split's last LDS reads come before the next split's writes
+        } else {
+            wsp = 0;
+            t = next_tile(t);
+        }
+    }
+
+    if (a.counter != nullptr && tid == 0) {
+        // The last workgroup out resets both counters for the next launch.
+        __threadfence();
+        if (atomicAdd(&a.counter[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&a.counter[0], 0);
+            atomicExch(&a.counter[1], 0);
+        }
+    }
+}
+
+template <int CF, int B3, bool C64>
+hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
+{
+    contract<CF, B3, C64><<<dim3(grid), dim3(WG), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace f64p
+
+int f64p_lds_bytes(int cf, int b3)
+{
+#define BBQ_SIZE(CF_, B3_) \
+    if (cf == CF_ && b3 == B3_) return (int)f64p::Shape<CF_, B3_>::lds;
+    BBQ_SIZE(1, 16) BBQ_SIZE(2, 16) BBQ_SIZE(3, 16) BBQ_SIZE(1, 32) BBQ_SIZE(2, 32) BBQ_SIZE(3, 32)
+#undef BBQ_SIZE
+    return -1;
+}
+
+int f64p_pairs(int b3) { return b3 == 16 || b3 == 32 ? f64p::MT / b3 : -1; }
+
+hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st)
+{
+#define BBQ_CASE(CF_, B3_)          \
+    if (cf == CF_ && b3 == B3_)     \
+        return c64 ? f64p::run<CF_, B3_, true>(a, grid, st) : f64p::run<CF_, B3_, false>(a, grid, st);
+    BBQ_CASE(1, 16) BBQ_CASE(2, 16) BBQ_CASE(3, 16) BBQ_CASE(1, 32) BBQ_CASE(2, 32) BBQ_CASE(3, 32)
+#undef BBQ_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bb

@@ -197,6 +197,15 @@ hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hip
 // launch.
 int f64_lds_bytes(int cf);
 hipError_t launch_f64(int cf, int c64, const GemmArgs &a, int grid, hipStream_t st);
+// FP64 paper-order kernel (plan kernel 6): the singlet on the vector unit in
+// the MFMA operand layout, the momentum projection as a three-product complex
+// GEMM on the matrix cores; 128 rows = (d1,d2) pairs x a d3 block of 16 or
+// 32, 16 cf momenta per tile (cf 1, 2 or 3).  Static LDS bytes and pairs per
+// tile (-1 when no instantiation), launch.  Its tiles use BlockDesc.n_mt2
+// for the number of d3 blocks.
+int f64p_lds_bytes(int cf, int b3);
+int f64p_pairs(int b3);
+hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 // Offset of batch entry b of one GEMM operand, in complex elements: two
 // terms ((b / d) % m) * s, so that an operand can run with the whole batch
 // index, with an outer part of it only, or stay fixed (s = 0).

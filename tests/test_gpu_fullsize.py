@@ -4,10 +4,11 @@ with the plans the library picks by default (the plans bench.py times).
 * headline: 32^3 sites, N_dil 32, 7 momenta, complex128 -- every entry of the
   block against the oracle, in all three precisions;
 * large: 64^3 sites, N_dil 64, 33 momenta (the paper's test problem, Sec. 4)
-  -- two entries in every group of 8 consecutive (d1, d2) pairs, one in each
+  -- two entries in every group of 4 consecutive (d1, d2) pairs, one in each
   half of the d3 range, every momentum: every row tile of every kernel's
-  tiling (64-row linear tiles, 4 x 32 rectangles, 8-pair tiles) and every
-  column tile is compared, in all three precisions;
+  tiling (64- and 128-row linear tiles, 4 x 32 rectangles, 4- and 8-pair
+  tiles by d3 blocks) and every column tile is compared, in all three
+  precisions;
 * batched: one timeslice of the 48^3, N_dil 32, 27-momentum workload (its 4
   spin triples (s, s, s), complex64) in one grouped launch;
 * uneven: one timeslice of the 32^3 uneven workload -- 8 noise triples with
@@ -57,12 +58,14 @@ def err_max(got, ref):
 
 
 def cover_entries(n1, n2, n3):
-    """Two (d1, d2, d3) entries per group of 8 consecutive pairs m = d1 n2 + d2,
-    one with d3 in each half of [0, n3)."""
+    """Two (d1, d2, d3) entries per group of 4 consecutive pairs m = d1 n2 + d2,
+    one with d3 in each half of [0, n3): every row tile of every plan holds
+    some (its rows are 4 or more consecutive pairs x a d3 block of at most
+    n3 / 2 at n3 = 64, or 128 consecutive pairs)."""
     out = []
     M = n1 * n2
-    for g in range((M + 7) // 8):
-        m = min(M - 1, 8 * g + (5 * g) % 8)
+    for g in range((M + 3) // 4):
+        m = min(M - 1, 4 * g + (5 * g) % 4)
         d1, d2 = divmod(m, n2)
         h = max(1, n3 // 2)
         out.append((d1, d2, (7 * g) % h))

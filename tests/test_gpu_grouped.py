@@ -80,7 +80,8 @@ def _fields(L, shapes, workload, dtype=np.complex128):
 
 
 CASES = [("fp32", 1, 7), ("fp32", 1, 4), ("bf16x3", 1, 7), ("bf16x3", 2, 7), ("bf16x3", 4, 5), ("bf16x3", 3, 1),
-         ("bf16x3", 3, 2), ("fp32", 0, 4), ("bf16x3", 0, 2)]
+         ("bf16x3", 3, 2), ("fp32", 0, 4), ("bf16x3", 0, 2), ("fp64", 5, 7), ("fp64", 5, 2), ("fp64", 6, 2),
+         ("fp64", 6, 3), ("fp64", 0, 7)]
 
 
 @pytest.mark.parametrize("prec,kernel,nb", CASES)
@@ -90,10 +91,8 @@ def test_walking_tiles_bitwise_equal_to_split_reduction(torch_dev, prec, kernel,
     L = 20
     shapes = [(24, 20, 32), (24, 20, 32), (17, 33, 21)]
     trips = _fields(L, shapes, workload=160)
-    mom = synth.momenta("cube" if kernel == 3 else "axis")
+    mom = synth.momenta("cube" if kernel in (3, 6) else "axis")  # the paper-order kernels: many momenta
     plans = {s: dict(kernel=kernel, nb=nb, splits=2, persistent=0) for s in set(shapes)}
-    if kernel == 3:  # the paper-order kernel needs n3 >= 16
-        plans = {s: dict(kernel=3, nb=nb, splits=2, persistent=0) for s in set(shapes)}
     say("case walk vs split reduction", prec, kernel, nb)
     a, _ = _run(torch_dev, prec, L, trips, mom, "0", plans)
     b, _ = _run(torch_dev, prec, L, trips, mom, "1", plans)
