@@ -1,5 +1,6 @@
-// Internal declarations shared by the host API (bb_api.cpp) and the HIP
-// kernels (bb_kernels.hip) of libbblock.so.  Not part of the public ABI.
+// Internal types and device helpers shared by the host API (bb_api.hip) and
+// the HIP kernels of libbblock.so: the block descriptor, launch arguments and
+// the helpers every contraction kernel uses.  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -155,57 +156,6 @@ struct ReduceArgs {
     int n_list;
 };
 
-// Geometry of one kernel instantiation.
-struct KernelGeom {
-    int m_tile;       // complex rows (d1,d2) per workgroup
-    int frag_cols;    // columns per MFMA fragment
-    int lds_bytes;    // dynamic LDS for (nb, n_mom, L)
-};
-
-// Column fragments per wave available for each precision.
-int nb_options(int prec, const int **list);
-KernelGeom kernel_geom(int prec, int nb, int n_mom, int L);
-
-hipError_t launch_gemm(int prec, int nb, const GemmArgs &a, int grid, hipStream_t st);
-
-// Pipelined kernel (FP32 and BF16X3; d2 and d3 blocks of 16 or 32).
-// Returns the dynamic LDS bytes, or -1 when no instantiation exists.
-int fast_lds_bytes(int prec, int nb, int b2, int b3, int L);
-hipError_t launch_fast(int prec, int nb, int b2, int b3, int in_c64, const GemmArgs &a, int grid, hipStream_t st);
-hipError_t prepare_fast_kernels(int lds_bytes);
-// kidx[p][x] = (n_p . x) mod L for all sites of one timeslice (momenta already
-// in [0, L)), rows of kstride >= V bytes, 0 past V.
-hipError_t launch_phase_index(const int *mom, int n_mom, int L, int kstride, unsigned char *kidx, hipStream_t st);
-// Precomputed-W kernel (BF16X3; d2 blocks of 8, 16 or 32, nb 4 to 7): static
-// LDS bytes (-1 when no instantiation), bytes per W image, launches.  The
-// contraction runs with 4 waves per workgroup (one per SIMD) or 8 (two per
-// SIMD, the column fragments split between the two).
-int w3_lds_bytes(int nb, int b2);
-size_t w3_image_bytes(int nb);
-hipError_t launch_w3_image(int nb, int c64, const WImageArgs &a, int cps_max, hipStream_t st);
-hipError_t launch_w3(int nb, int b2, int waves, int c64, const GemmArgs &a, int grid, hipStream_t st);
-// Paper-order kernel (BF16X3; singlet on the VALU, momentum GEMM on MFMA;
-// nb column fragments of 32 momenta, d3 blocks of 16 or 32): (d1,d2) pairs
-// per workgroup (-1 when no instantiation), launch.  Its tiles use
-// BlockDesc.n_mt2 for the number of d3 blocks.
-int pord_pairs(int nb, int b3);
-hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
-// FP64 kernel (plan kernel 5): eight waves per workgroup, each running the
-// three-product complex GEMM of 16 rows on the matrix cores and building its
-// share of the next chunk's D and W tiles; 128 complex rows x 16 cf columns
-// per tile (cf 2, 4 or 7).  Static LDS bytes (-1 when no instantiation),
-// launch.
-int f64_lds_bytes(int cf);
-hipError_t launch_f64(int cf, int c64, const GemmArgs &a, int grid, hipStream_t st);
-// FP64 paper-order kernel (plan kernel 6): the singlet on the vector unit in
-// the MFMA operand layout, the momentum projection as a three-product complex
-// GEMM on the matrix cores; 128 rows = (d1,d2) pairs x a d3 block of 16 or
-// 32, 16 cf momenta per tile (cf 1, 2 or 3).  Static LDS bytes and pairs per
-// tile (-1 when no instantiation), launch.  Its tiles use BlockDesc.n_mt2
-// for the number of d3 blocks.
-int f64p_lds_bytes(int cf, int b3);
-int f64p_pairs(int b3);
-hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 // Offset of batch entry b of one GEMM operand, in complex elements: two
 // terms ((b / d) % m) * s, so that an operand can run with the whole batch
 // index, with an outer part of it only, or stay fixed (s = 0).
@@ -237,10 +187,8 @@ struct ZgemmArgs {
     int M, N, K, batch;
     int tiles_m, tiles_n;            // set by the launcher
 };
-int zgemm_shape(int M, int N, int K, int batch);  // index of the wave layout a launch uses
-hipError_t launch_zgemm(const ZgemmArgs &a, hipStream_t st);
-hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);
-hipError_t launch_combine(int prec, const CombineArgs &a, int max_mn, hipStream_t st);
-hipError_t prepare_kernels(int lds_bytes);  // dynamic-LDS limit of every contraction kernel
 
 }  // namespace bb
+
+// Host-side launch and geometry entry points of the kernels.
+#include "bb_launch.h"
