@@ -112,13 +112,13 @@ typedef struct {
                                three real products per complex product
                                (FP64 only, any shape; nb 2, 4 or 7 column
                                fragments of 16; 128-row tiles, D and W built
-                               in LDS; the FP64 default up to 9 momenta).
+                               in LDS; the FP64 default up to 8 momenta).
                             6: paper order in complex double: the singlet on
                                the vector unit, the momentum projection on
                                the FP64 matrix cores with three real
                                products (FP64 only, n3 >= 16; nb 1, 2 or 3
                                fragments of 16 momenta; the FP64 default
-                               from 10 momenta). */
+                               from 9 momenta). */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device (paper, Sec. 2 after

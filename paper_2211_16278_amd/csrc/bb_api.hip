@@ -38,9 +38,10 @@ constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
 constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, K_F64 = 5, K_F64P = 6;
 // FP64 momenta above which the paper-order kernel 6 is the default (at 32^3,
-// N_dil 32: kernel 5 2.19 ms against 3.13 at 7 momenta, 3.34 against 3.14 at
-// 10, 8.5 against 4.4 at 27, 11.4 against 6.1 at 33).
-constexpr int F64P_MIN_MOM = 9;
+// N_dil 32, ms per block: kernel 5 2.19 against 2.51 at 7 momenta, about
+// 2.5 for both at 8, 3.34 against 2.50 at 10, 8.5 against 4.1 at 27, 11.3
+// against 5.6 at 33).
+constexpr int F64P_MIN_MOM = 8;
 // Kernel 2 and its eight-wave form 4 share geometry, images and workspace.
 inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 
@@ -266,8 +267,11 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.lds = lds;
     } else if (kernel == K_F64P) {
         // Rows (d1,d2,d3): a block of consecutive (d1,d2) pairs x a d3 block
-        // of 16 or 32; columns: 16 nb momenta.
-        g.b3 = pipelined_block(n3);
+        // of 16 or 32; columns: 16 nb momenta.  The d3 block whose tiles run
+        // in chunks of 32 sites: 32 with one momentum fragment, else 16
+        // (measured at 32^3 and N_dil 32 or 64: 4 % faster at nb 1, 8 % at
+        // nb 2 and 3 than the other block).
+        g.b3 = n3 < 16 ? 0 : (nb == 1 && n3 >= 32 ? 32 : 16);
         if (h->prec != FP64 || g.b3 == 0) return g;
         const int pairs = f64p_pairs(g.b3), lds = f64p_lds_bytes(nb, g.b3);
         if (pairs <= 0 || lds <= 0) return g;

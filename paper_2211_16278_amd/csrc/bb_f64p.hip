@@ -23,7 +23,8 @@
 // 3 x CF accumulator fragments of v_mfma_f64_16x16x4_f64.  The A operand of
 // a k-step (4 sites) is the singlet itself: lane l forms S of row
 // 16 w + l % 16 at site l / 16 from the diquark and q3 tiles in LDS, in
-// registers, and feeds it to the MFMAs.  Per chunk of 16 sites the
+// registers, and feeds it to the MFMAs.  Per chunk of 32 sites (16 where two
+// buffers of 32 would not fit the LDS) the
 // workgroup builds the next chunk's tiles (the diquark of its pairs, q3 of
 // its d3 block, the phases of its momenta with their Re + Im plane) into the
 // other LDS buffer from registers loaded a chunk earlier, and issues the
@@ -42,24 +43,31 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 512;     // eight waves
 constexpr int MT = 128;     // rows (pair, d3) per tile, 16 per wave
-constexpr int SITES = 16;   // sites per chunk
-constexpr int KS = SITES / 4;  // k-steps per chunk
 constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past any range: loads return zero
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+// Doubles of one LDS buffer for chunks of s sites: D [3][s][pairs] and q3
+// [3][s][b3] as (re, im) pairs, then the phase planes Re, Im, Re + Im [s][ps].
+constexpr int buffer_doubles(int s, int pairs, int b3, int ps) { return 2 * 3 * s * pairs + 2 * 3 * s * b3 + 3 * s * ps; }
 
 template <int CF, int B3>
 struct Shape {
     static constexpr int NPAIR = MT / B3;                     // (d1,d2) pairs per tile
     static constexpr int NC = 16 * CF;                        // momenta per tile
     static constexpr int PS = (NC % 32 == 0) ? NC + 16 : NC;  // site stride of the phase planes (doubles)
+    // Sites per chunk: 32 where two buffers of that size fit the LDS (one
+    // barrier and one tile build per 32 sites), else 16.
+    static constexpr int SITES =
+        2 * (size_t)buffer_doubles(32, NPAIR, B3, PS) * 8 + (size_t)MAX_L * 16 <= LDS_LIMIT ? 32 : 16;
+    static constexpr int KS = SITES / 4;                      // k-steps per chunk
     static constexpr int ND = NPAIR * SITES;                  // diquark items per chunk
     static constexpr int NQ = SITES * 3 * B3;                 // q3 values per chunk
     static constexpr int NP = SITES * NC;                     // phases per chunk
     static constexpr int JQ = (NQ + WG - 1) / WG, JP = (NP + WG - 1) / WG;
-    // One buffer: D [3][SITES][NPAIR] and q3 [3][SITES][B3] as (re, im)
-    // pairs, then the phase planes Re, Im, Re + Im [SITES][PS].
     static constexpr int DOFF = 0, QOFF = 2 * 3 * SITES * NPAIR, POFF = QOFF + 2 * 3 * SITES * B3;
     static constexpr int BUF = POFF + 3 * SITES * PS;  // doubles
     static constexpr size_t lds = (size_t)2 * BUF * 8 + (size_t)MAX_L * 16;
+    static_assert(BUF == buffer_doubles(SITES, NPAIR, B3, PS) && lds <= LDS_LIMIT, "two buffers fit the LDS");
     static_assert(PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
     static_assert(B3 % 16 == 0 && MT % B3 == 0, "a wave's 16 rows are d3 values of one pair");
     static_assert(ND % 64 == 0 && ND <= WG, "diquark items end on a wave boundary, one per thread");
@@ -88,7 +96,7 @@ __device__ __forceinline__ double2 ldq(__amdgpu_buffer_rsrc_t rs, uint32_t off)
 
 // Resource over sites [x0, x0 + SITES) of a field [V][3][n] (bytes in range:
 // the sites below xe only; none when x0 >= xe).
-template <bool C64>
+template <int SITES, bool C64>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int n, int x0, int xe)
 {
     constexpr int ESZ = In<C64>::ESZ;
@@ -101,7 +109,7 @@ template <int CF, int B3, bool C64>
 __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 {
     using Sh = Shape<CF, B3>;
-    constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF;
+    constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF, SITES = Sh::SITES, KS = Sh::KS;
     constexpr int ESZ = In<C64>::ESZ;
     __shared__ __align__(16) double lds[2 * BUF];
     __shared__ double2 roots[MAX_L];
@@ -170,15 +178,15 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         auto issue = [&](int ci) {
             const int x0 = __builtin_amdgcn_readfirstlane(xs + ci * SITES);
             if (has_d) {
-                const __amdgpu_buffer_rsrc_t rs1 = chunk_rsrc<C64>(bd.q1, bd.n1, x0, xe);
-                const __amdgpu_buffer_rsrc_t rs2 = chunk_rsrc<C64>(bd.q2, bd.n2, x0, xe);
+                const __amdgpu_buffer_rsrc_t rs1 = chunk_rsrc<SITES, C64>(bd.q1, bd.n1, x0, xe);
+                const __amdgpu_buffer_rsrc_t rs2 = chunk_rsrc<SITES, C64>(bd.q2, bd.n2, x0, xe);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     u[c] = ldq<C64>(rs1, o1[c]);
                     v[c] = ldq<C64>(rs2, o2[c]);
                 }
             }
-            const __amdgpu_buffer_rsrc_t rs3 = chunk_rsrc<C64>(bd.q3, bd.n3, x0, xe);
+            const __amdgpu_buffer_rsrc_t rs3 = chunk_rsrc<SITES, C64>(bd.q3, bd.n3, x0, xe);
 #pragma unroll
             for (int j = 0; j < Sh::JQ; ++j) w[j] = ldq<C64>(rs3, o3[j]);
             const __amdgpu_buffer_rsrc_t rsk = __builtin_amdgcn_make_buffer_rsrc(

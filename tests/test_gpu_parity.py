@@ -409,9 +409,9 @@ def test_plan_validation_and_defaults(torch_dev):
                 with pytest.raises(binding.BBlockError):
                     bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=7, splits=0, persistent=0, grid=0))
             assert bb.get_plan(n, n, n, 7)["kernel"] == (5 if prec == "fp64" else 1)
-            if prec == "fp64":  # kernel 5 up to 9 momenta, the paper-order kernel 6 from 10
-                assert bb.get_plan(n, n, n, 9)["kernel"] == 5
-                assert bb.get_plan(n, n, n, 10)["kernel"] == 6
+            if prec == "fp64":  # kernel 5 up to 8 momenta, the paper-order kernel 6 from 9
+                assert bb.get_plan(n, n, n, 8)["kernel"] == 5
+                assert bb.get_plan(n, n, n, 9)["kernel"] == 6
                 assert bb.get_plan(n, n, 8, 33)["kernel"] == 5  # n3 below kernel 6's d3 block
             if prec == "fp32":
                 for kernel, nb in ((5, 7), (6, 2)):  # kernels 5 and 6 are FP64 only
