@@ -1,7 +1,7 @@
 """The allocation-free entry point bblock_compute_noalloc against
-bblock_compute, through the C ABI: two calls in a row on one handle (the
-second with a smaller input, so that the scratch array still holds the first
-call's larger contents), in every precision, to the error contract of the
+bblock_compute, through the C ABI: calls in a row on one handle (each with a
+smaller input than the one before, so that the scratch array still holds the
+earlier calls' larger contents), in every precision, to the error contract of the
 precision (FP64 1e-10, FP32 and BF16X3 1e-5 of the block's largest entry);
 and a batch too large for the static scratch array is refused with a clear
 error and leaves the output untouched."""
@@ -48,7 +48,9 @@ def _rel(a, b):
 def test_noalloc_matches_compute_two_calls(torch_dev, prec):
     torch, dev = torch_dev
     L = 8
-    calls = [((24, 20, 28), 2, "axis"), ((5, 3, 7), 1, "cube")]  # the second call is smaller
+    # Each call's input is smaller than the one before; the second runs the
+    # many-momenta plans (FP64 kernel 6, BF16X3 kernel 3).
+    calls = [((24, 20, 28), 2, "axis"), ((20, 18, 24), 1, "cube"), ((5, 3, 7), 1, "cube")]
     with binding.BaryonBlocks(L, prec=prec, in_dtype="c128", max_ndil=32) as bb:
         for k, (ns, T, mset) in enumerate(calls):
             say("case noalloc", prec, "call", k, ns, T, mset)
