@@ -44,6 +44,8 @@ def kernel_name(path, plan, n2, n3):
         return "bb::f64::contract<%d, false>" % plan["nb"]
     if plan["kernel"] == 6:
         return "bb::f64p::contract<%d, %d, false>" % (plan["nb"], 32 if plan["nb"] == 1 and n3 >= 32 else 16)
+    if plan["kernel"] == 7:
+        return "bb::f32p::contract<%d, %d, false>" % (plan["nb"], 32 if n3 >= 32 else 16)
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
         return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)
@@ -75,6 +77,7 @@ KERNEL_SOURCES = {
     "bb::bb_reduce": ("bb_kernels.hip", "bb_internal.h"),
     "bb::f64::": ("bb_f64.hip", "bb_internal.h"),
     "bb::f64p::": ("bb_f64p.hip", "bb_fast.h", "bb_internal.h"),
+    "bb::f32p::": ("bb_f32p.hip", "bb_fast.h", "bb_internal.h"),
 }
 
 
@@ -97,6 +100,8 @@ def mfma_flops_executed(path, plan, f_gemm):
         return 0.75 * f_gemm
     if plan["kernel"] == 6:
         return 0.25 * f_gemm
+    if plan["kernel"] == 7:
+        return f_gemm / 3.0
     return MFMA_PASSES[path] * f_gemm
 
 
@@ -105,6 +110,8 @@ def flops_note(path, plan):
         return "18 n_mom V n^3: three real products per complex multiply-add"
     if plan["kernel"] == 6:
         return "6 n_mom V n^3: the momentum projection with three real products"
+    if plan["kernel"] == 7:
+        return "8 n_mom V n^3: the momentum projection with four real products"
     return "%d x 24 n_mom V n^3" % MFMA_PASSES[path]
 
 
@@ -176,9 +183,9 @@ def mfma_flops(plan, V, n1, n2, n3, n_mom):
     """Flops of one MFMA pass of the formulation a plan runs: the fused GEMM
     (24 n_mom V n1 n2 n3; 18 for FP64 kernel 5's three real products) or, for
     the paper-order kernels, only the momentum projection (8 n_mom V n1 n2 n3
-    for kernel 3, 6 for FP64 kernel 6; their singlet runs on the vector
-    unit)."""
-    per = {3: 8.0, 5: 18.0, 6: 6.0}.get(plan["kernel"], 24.0)
+    for kernels 3 and 7, 6 for FP64 kernel 6; their singlet runs on the
+    vector unit)."""
+    per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 8.0}.get(plan["kernel"], 24.0)
     return per * n_mom * V * n1 * n2 * n3
 
 

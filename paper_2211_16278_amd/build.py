@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("bb_fast_bf16.hip", "bb_fast_fp32.hip", "bb_w3.hip", "bb_pord.hip", "bb_zgemm.hip", "bb_f64.hip", "bb_f64p.hip", "bb_kernels.hip",
+SOURCES = [os.path.join(CSRC, f) for f in ("bb_fast_bf16.hip", "bb_fast_fp32.hip", "bb_w3.hip", "bb_pord.hip", "bb_zgemm.hip", "bb_f64.hip", "bb_f64p.hip", "bb_f32p.hip", "bb_kernels.hip",
                                              "bb_api.hip")]
 HEADERS = [os.path.join(CSRC, "bb_internal.h"), os.path.join(CSRC, "bb_fast.h"),
            os.path.join(os.path.dirname(HERE), "include", "bblock.h")]

@@ -36,12 +36,16 @@ thread_local std::string g_create_error;
 
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
-constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, K_F64 = 5, K_F64P = 6;
+constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, K_F64 = 5, K_F64P = 6, K_F32P = 7;
 // FP64 momenta above which the paper-order kernel 6 is the default (at 32^3,
 // N_dil 32, ms per block: kernel 5 2.19 against 2.51 at 7 momenta, about
 // 2.5 for both at 8, 3.34 against 2.50 at 10, 8.5 against 4.1 at 27, 11.3
 // against 5.6 at 33).
 constexpr int F64P_MIN_MOM = 8;
+// FP32 momenta above which the paper-order kernel 7 is the default (at 32^3,
+// N_dil 32, ms per block: kernel 1 1.87 against 2.16 at 8 momenta, 2.98
+// against 2.16 at 10, 5.9 against 3.1 at 27, 8.0 against 4.1 at 33).
+constexpr int F32P_MIN_MOM = 8;
 // Kernel 2 and its eight-wave form 4 share geometry, images and workspace.
 inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 
@@ -282,6 +286,19 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
         g.n_nt = cdiv(n_mom, g.n_tile);
         g.lds = lds;
+    } else if (kernel == K_F32P) {
+        // As kernel 6, in FP32: d3 blocks of 32 (16 below 32), 16 nb momenta.
+        g.b3 = pipelined_block(n3);
+        if (h->prec != FP32 || g.b3 == 0) return g;
+        const int pairs = f32p_pairs(g.b3), lds = f32p_lds_bytes(nb, g.b3);
+        if (pairs <= 0 || lds <= 0) return g;
+        g.m_tile = pairs * g.b3;
+        g.n_tile = 16 * nb;
+        g.bp = 16 * nb;
+        g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
+        g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
+        g.n_nt = cdiv(n_mom, g.n_tile);
+        g.lds = lds;
     } else if (kernel == K_PORD) {
         // Rows (d1,d2,d3): a block of consecutive (d1,d2) pairs x a d3 block;
         // columns: 32 nb momenta.
@@ -347,6 +364,21 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
             p.kernel = K_PORD;
             p.nb = g.nb;
             p.splits = fill_splits(h, g);
+            return p;
+        }
+    }
+    if (h->prec == FP32 && n_mom > F32P_MIN_MOM) {
+        // FP32 with many momenta: the paper-order kernel 7, with the column
+        // width that pads fewest momenta (the wider on a tie).
+        for (int nb : {4, 3, 2, 1}) {
+            const Geometry g = geometry(h, K_F32P, nb, n1, n2, n3, n_mom);
+            if (g.lds < 0) continue;
+            if (best.lds < 0 || (long)g.n_nt * g.n_tile < (long)best.n_nt * best.n_tile) best = g;
+        }
+        if (best.lds >= 0) {
+            p.kernel = best.kernel;
+            p.nb = best.nb;
+            p.splits = fill_splits(h, best);
             return p;
         }
     }
@@ -628,6 +660,7 @@ bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &s
                        : sb.kernel == K_PORD    ? launch_pord(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_F64     ? launch_f64(sb.nb, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_F64P    ? launch_f64p(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
+                       : sb.kernel == K_F32P    ? launch_f32p(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                                                 : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
         if (h->profiling) {
@@ -991,7 +1024,8 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         sb.b3 = b0.g.b3;
         sb.persistent = b0.plan.persistent;
         sb.grid = b0.plan.grid > 0 ? b0.plan.grid : h->num_cu;
-        any_pipelined |= sb.kernel == K_PIPELINED || sb.kernel == K_PORD || sb.kernel == K_F64 || sb.kernel == K_F64P;
+        any_pipelined |= sb.kernel == K_PIPELINED || sb.kernel == K_PORD || sb.kernel == K_F64 || sb.kernel == K_F64P ||
+                         sb.kernel == K_F32P;
         size_t used = 0;
         long n_went = 0;
         const size_t u0 = u;
@@ -1584,7 +1618,7 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         return BBLOCK_OK;
     }
     if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && !is_w3(plan->kernel) && plan->kernel != K_PORD &&
-        plan->kernel != K_F64 && plan->kernel != K_F64P)
+        plan->kernel != K_F64 && plan->kernel != K_F64P && plan->kernel != K_F32P)
         return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
@@ -1689,13 +1723,15 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
         for (int nb : {7, 4, 2}) kn.push_back({K_F64, nb});
         for (int nb : {3, 2, 1}) kn.push_back({K_F64P, nb});
+        for (int nb : {4, 3, 2, 1}) kn.push_back({K_F32P, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
         const int N = n3 * n_mom;
         for (auto [kernel, nb] : kn) {
             const Geometry g = geometry(h, kernel, nb, n1, n2, n3, n_mom);
             if (g.lds <= 0) continue;
             const long padded = (long)g.n_nt * g.n_tile;  // columns, or momenta for the paper-order kernel
-            if (padded > 2L * std::max(kernel == K_PORD || kernel == K_F64P ? n_mom : N, 32)) continue;  // mostly padding
+            const bool by_mom = kernel == K_PORD || kernel == K_F64P || kernel == K_F32P;  // n-tiles of momenta
+            if (padded > 2L * std::max(by_mom ? n_mom : N, 32)) continue;  // mostly padding
             // Split counts as a tuned plan will run them (at least the
             // accuracy floor, in whole multiples of the wave-filling count).
             const int s_base = fill_splits(h, g), s_min = min_splits(h);

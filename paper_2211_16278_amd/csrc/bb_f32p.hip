@@ -1,0 +1,355 @@
+// FP32 paper-order contraction kernel of libbblock.so (gfx950, plan kernel 7).
+//
+// The block of the paper (Sec. 2, eq. (3)) in the order of Algorithm 1, as
+// FP64 kernel 6 does it, in single precision: per site the singlet
+//   S[x; (d1,d2), d3] = sum_c D_c[x; d1,d2] q3_c[x; d3],  D_c = eps_abc q1_a q2_b,
+// formed per lane in the MFMA operand layout, then the momentum projection
+//   B[p][(d1,d2)][d3] = sum_x S[x; (d1,d2), d3] exp(-i p.x)
+// on v_mfma_f32_16x16x4_f32 with the real embedding (four real products:
+// Re += Sr er - Si ei, Im += Sr ei + Si er), FP32 accumulation over a site
+// split of at most 4096 sites, the splits summed in FP64.  The FP32 vector
+// work (singlet, tile builds) can issue while the FP32 MFMAs run.
+//
+// Workgroup: eight wave64, two per SIMD.  Tile: 128 rows = NPAIR (d1,d2)
+// pairs x a block of B3 d3 values, 16 CF momenta, one site split; wave w
+// owns rows 16 w to 16 w + 15 (16 d3 values of one pair) and all momenta:
+// 2 x CF accumulator fragments (Re, Im).  Chunks of 32 sites, double
+// buffered in LDS: the diquark of the tile's pairs, q3 of its d3 block, the
+// phases of its momenta, built from registers loaded a chunk earlier.
+#include <algorithm>
+
+#include "bb_fast.h"
+#include "bb_internal.h"
+
+namespace bb {
+namespace f32p {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+constexpr int WG = 512;       // eight waves
+constexpr int MT = 128;       // rows (pair, d3) per tile, 16 per wave
+constexpr int SITES = 32;     // sites per chunk
+constexpr int KS = SITES / 4; // k-steps per chunk
+constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past any range: loads return zero
+
+template <int CF, int B3>
+struct Shape {
+    static constexpr int NPAIR = MT / B3;                     // (d1,d2) pairs per tile
+    static constexpr int NC = 16 * CF;                        // momenta per tile
+    static constexpr int PS = (NC % 32 == 0) ? NC + 16 : NC;  // site stride of the phase planes (floats)
+    static constexpr int ND = NPAIR * SITES;                  // diquark items per chunk
+    static constexpr int NQ = SITES * 3 * B3;                 // q3 values per chunk
+    static constexpr int NP = SITES * NC;                     // phases per chunk
+    static constexpr int JQ = (NQ + WG - 1) / WG, JP = (NP + WG - 1) / WG;
+    // One buffer (floats): D [3][SITES][NPAIR] and q3 [3][SITES][B3] as
+    // (re, im) pairs, then the phase planes Re, Im [SITES][PS].
+    static constexpr int DOFF = 0, QOFF = 2 * 3 * SITES * NPAIR, POFF = QOFF + 2 * 3 * SITES * B3;
+    static constexpr int BUF = POFF + 2 * SITES * PS;
+    static constexpr size_t lds = (size_t)2 * BUF * 4 + (size_t)MAX_L * 8;
+    static_assert(PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
+    static_assert(B3 % 16 == 0 && MT % B3 == 0, "a wave's 16 rows are d3 values of one pair");
+    static_assert(ND % 64 == 0 && ND <= WG, "diquark items end on a wave boundary, one per thread");
+    static_assert(NQ % 256 == 0 && NP % 256 == 0, "q3 and phase items end on a wave boundary");
+    static_assert(lds <= 160 * 1024, "two buffers fit the LDS");
+};
+
+template <bool C64>
+struct In {
+    static constexpr int ESZ = 16;
+};
+template <>
+struct In<true> {
+    static constexpr int ESZ = 8;
+};
+
+template <bool C64>
+__device__ __forceinline__ float2 ldq(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+{
+    if constexpr (C64) {
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    } else {
+        const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        return make_float2((float)v.x, (float)v.y);
+    }
+}
+
+// Resource over sites [x0, x0 + SITES) of a field [V][3][n] (bytes in range:
+// the sites below xe only; none when x0 >= xe).
+template <bool C64>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int n, int x0, int xe)
+{
+    constexpr int ESZ = In<C64>::ESZ;
+    const int ns = __builtin_amdgcn_readfirstlane(min(max(xe - x0, 0), SITES));  // wave-uniform: no waterfall
+    const unsigned char *base = static_cast<const unsigned char *>(q) + (size_t)x0 * 3 * n * ESZ;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, ns * 3 * n * ESZ, 0x00020000);
+}
+
+template <int CF, int B3, bool C64>
+__global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
+{
+    using Sh = Shape<CF, B3>;
+    constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF;
+    constexpr int ESZ = In<C64>::ESZ;
+    __shared__ __align__(16) float lds[2 * BUF];
+    __shared__ float2 roots[MAX_L];
+    __shared__ int s_tile;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int k = tid; k < a.L; k += WG) roots[k] = make_float2((float)a.roots[2 * k], (float)a.roots[2 * k + 1]);
+
+    auto next_tile = [&](int current) -> int {
+        if (a.counter == nullptr) return current < 0 ? (int)blockIdx.x : a.n_tiles;
+        __syncthreads();
+        if (tid == 0) s_tile = atomicAdd(&a.counter[0], 1);
+        __syncthreads();
+        return __builtin_amdgcn_readfirstlane(s_tile);
+    };
+    __syncthreads();
+
+    // A walking tile runs every split of its block in order: the loop
+    // stays on tile t and steps its split (wsp) up to the block's last.
+    for (int t = next_tile(-1), wsp = 0; t < a.n_tiles;) {
+        const int4 tl0 = wave_uniform(a.tiles[t]);
+        const BlockDesc bd = wave_uniform(a.blocks[tl0.x]);
+        const int4 tl = make_int4(tl0.x, tl0.y, tl0.z, tl0.w + wsp);
+        // m-tile = (pair block, d3 block); n_mt2 holds the number of d3 blocks.
+        const int m12_0 = (tl.y / bd.n_mt2) * NPAIR, d3_0 = (tl.y % bd.n_mt2) * B3;
+        const int p0 = tl.z * NC;
+        const int M12 = bd.M;
+        const int xs = tl.w * bd.sps;
+        const int xe = min(a.V, xs + bd.sps);
+        const int n_chunks = (xe - xs + SITES - 1) / SITES;
+
+        // ---- generation items of this thread (tile invariant) ----
+        // Diquark item: pair tid % NPAIR at site tid / NPAIR (threads past ND: none).
+        const bool has_d = wave * 64 < Sh::ND;  // wave-uniform
+        const int dp = tid % NPAIR, ds = tid / NPAIR;
+        const int m = m12_0 + dp;
+        const bool mok = has_d && m < M12;
+        const int d1 = mok ? m / bd.n2 : 0, d2 = mok ? m - (m / bd.n2) * bd.n2 : 0;
+        uint32_t o1[3], o2[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o1[c] = mok ? (uint32_t)(((ds * 3 + c) * bd.n1 + d1) * ESZ) : OOB;
+            o2[c] = mok ? (uint32_t)(((ds * 3 + c) * bd.n2 + d2) * ESZ) : OOB;
+        }
+        // q3 items q = tid + WG j = ((s 3 + c) B3 + d): offsets in the chunk.
+        uint32_t o3[Sh::JQ];
+#pragma unroll
+        for (int j = 0; j < Sh::JQ; ++j) {
+            const int q = tid + WG * j;
+            const int d = q % B3, sc = q / B3;
+            o3[j] = (q < Sh::NQ && d3_0 + d < bd.n3) ? (uint32_t)((sc * bd.n3 + d3_0 + d) * ESZ) : OOB;
+        }
+        // Phase items q = tid + WG j = (s NC + jc): momentum p0 + jc at site s.
+        uint32_t ok[Sh::JP];
+#pragma unroll
+        for (int j = 0; j < Sh::JP; ++j) {
+            const int q = tid + WG * j;
+            const int jc = q % NC, s = q / NC;
+            ok[j] = (q < Sh::NP && p0 + jc < a.n_mom) ? (uint32_t)((p0 + jc) * a.kstride + s) : OOB;
+        }
+        const int krec = a.n_mom * a.kstride;
+
+        float2 u[3], v[3], w[Sh::JQ];
+        uint32_t kk[Sh::JP];
+        auto issue = [&](int ci) {
+            const int x0 = __builtin_amdgcn_readfirstlane(xs + ci * SITES);
+            if (has_d) {
+                const __amdgpu_buffer_rsrc_t rs1 = chunk_rsrc<C64>(bd.q1, bd.n1, x0, xe);
+                const __amdgpu_buffer_rsrc_t rs2 = chunk_rsrc<C64>(bd.q2, bd.n2, x0, xe);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    u[c] = ldq<C64>(rs1, o1[c]);
+                    v[c] = ldq<C64>(rs2, o2[c]);
+                }
+            }
+            const __amdgpu_buffer_rsrc_t rs3 = chunk_rsrc<C64>(bd.q3, bd.n3, x0, xe);
+#pragma unroll
+            for (int j = 0; j < Sh::JQ; ++j) w[j] = ldq<C64>(rs3, o3[j]);
+            const __amdgpu_buffer_rsrc_t rsk = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(a.kidx + min(x0, krec)), (short)0, max(krec - x0, 0), 0x00020000);
+#pragma unroll
+            for (int j = 0; j < Sh::JP; ++j) kk[j] = __builtin_amdgcn_raw_buffer_load_b8(rsk, ok[j], 0, 0);
+        };
+        // The loaded chunk into buffer b: the diquark u_a v_b - u_b v_a
+        // (eps_{a b c} = +1) per colour with the fixed rounding of
+        // fast::cmulf, q3 as loaded, the phases roots[k] = exp(-2 pi i k / L).
+        auto build = [&](int b) {
+            asm volatile("" : "+s"(b));  // one base register per buffer, immediate offsets from it
+            float *base = lds + b * BUF;
+            float2 *Dt = reinterpret_cast<float2 *>(base + Sh::DOFF);
+            float2 *Qt = reinterpret_cast<float2 *>(base + Sh::QOFF);
+            float *Pr = base + Sh::POFF, *Pi = Pr + SITES * PS;
+            if (has_d) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float2 x = fast::cmulf(u[(c + 1) % 3], v[(c + 2) % 3]);
+                    const float2 y = fast::cmulf(u[(c + 2) % 3], v[(c + 1) % 3]);
+                    Dt[(c * SITES + ds) * NPAIR + dp] = make_float2(x.x - y.x, x.y - y.y);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < Sh::JQ; ++j) {
+                const int q = tid + WG * j;
+                if (q < Sh::NQ) {
+                    const int d = q % B3, sc = q / B3, s = sc / 3, c = sc - 3 * s;
+                    Qt[(c * SITES + s) * B3 + d] = w[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < Sh::JP; ++j) {
+                const int q = tid + WG * j;
+                if (q < Sh::NP) {
+                    const int jc = q % NC, s = q / NC;
+                    const float2 e = roots[kk[j]];
+                    Pr[s * PS + jc] = e.x;
+                    Pi[s * PS + jc] = e.y;
+                }
+            }
+        };
+
+        f4_t acc[2][CF];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int n = 0; n < CF; ++n) acc[q][n] = f4_t{0.f, 0.f, 0.f, 0.f};
+        // A[i][k] from lane i + 16 k: row 16 wave + i at site k of the k-step.
+        const int li = lane & 15, kg = lane >> 4;
+        const int rw = wave * 16 + li;
+        const int pair_l = rw / B3, d3_l = rw % B3;
+
+        // One chunk from buffer b: per k-step the singlets of this lane's
+        // (row, site) from LDS, then 4 CF MFMAs; after the first k-step the
+        // next chunk's tiles go into buffer b ^ 1 and the loads of the chunk
+        // after it are issued.
+        auto chunk = [&](int b, int ci_next) {
+            asm volatile("" : "+s"(b));
+            const float *base = lds + b * BUF;
+            const float2 *Dl = reinterpret_cast<const float2 *>(base + Sh::DOFF) + kg * NPAIR + pair_l;
+            const float2 *Ql = reinterpret_cast<const float2 *>(base + Sh::QOFF) + kg * B3 + d3_l;
+            const float *Pl = base + Sh::POFF + kg * PS + li;
+            float2 dv[2][3], qv[2][3];
+            float br[2][CF], bi[2][CF];
+            auto read_s = [&](int ks, int slot) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    dv[slot][c] = Dl[(c * SITES + 4 * ks) * NPAIR];
+                    qv[slot][c] = Ql[(c * SITES + 4 * ks) * B3];
+                }
+#pragma unroll
+                for (int n = 0; n < CF; ++n) {
+                    br[slot][n] = Pl[4 * ks * PS + n * 16];
+                    bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * 16];
+                }
+            };
+            read_s(0, 0);
+            fast::static_for<0, KS>([&](auto kk_) {
+                constexpr int ks = kk_, slot = ks & 1;
+                // Singlet S = sum_c D_c q3_c (complex).
+                float sr = __builtin_fmaf(dv[slot][0].x, qv[slot][0].x, -(dv[slot][0].y * qv[slot][0].y));
+                float si = __builtin_fmaf(dv[slot][0].x, qv[slot][0].y, dv[slot][0].y * qv[slot][0].x);
+#pragma unroll
+                for (int c = 1; c < 3; ++c) {
+                    sr = __builtin_fmaf(dv[slot][c].x, qv[slot][c].x, sr);
+                    sr = __builtin_fmaf(-dv[slot][c].y, qv[slot][c].y, sr);
+                    si = __builtin_fmaf(dv[slot][c].x, qv[slot][c].y, si);
+                    si = __builtin_fmaf(dv[slot][c].y, qv[slot][c].x, si);
+                }
+                const float nsi = -si;
+                if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
+#pragma unroll
+                for (int n = 0; n < CF; ++n) {
+                    acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[slot][n], acc[0][n], 0, 0, 0);
+                    acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, bi[slot][n], acc[1][n], 0, 0, 0);
+                    acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(nsi, bi[slot][n], acc[0][n], 0, 0, 0);
+                    acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, br[slot][n], acc[1][n], 0, 0, 0);
+                }
+                if constexpr (ks == 0) {
+                    build(b ^ 1);
+                    issue(ci_next);  // past the split the loads are out of range (zeros)
+                }
+            });
+        };
+
+        // Prologue: chunk 0 into buffer 0, chunk 1 in registers.
+        issue(0);
+        build(0);
+        issue(1);
+        __syncthreads();
+        for (int i = 0; i < n_chunks; ++i) {
+            chunk(i & 1, i + 2);
+            __syncthreads();
+        }
+
+        // Epilogue.  Accumulator register e of a 16x16 f32 fragment holds
+        // row 4 (lane / 16) + e, column lane % 16.
+        with_put_mode(bd, tl.w, [&](auto mode) {
+#pragma unroll
+            for (int n = 0; n < CF; ++n) {
+                const int p = p0 + n * 16 + li;
+                if (p >= a.n_mom) continue;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = wave * 16 + 4 * kg + e;
+                    const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
+                    if (mo >= M12 || d3 >= bd.n3) continue;
+                    const int nu = p * bd.n3 + d3;
+                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 0, (double)acc[0][n][e]);
+                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 1, (double)acc[1][n][e]);
+                }
+            }
+        });
+        if (bd.walk && tl.w + 1 < bd.S) {
+            ++wsp;
+            __syncthreads();  // the split's last LDS reads come before the next split's writes
+        } else {
+            wsp = 0;
+            t = next_tile(t);
+        }
+    }
+
+    if (a.counter != nullptr && tid == 0) {
+        // The last workgroup out resets both counters for the next launch.
+        __threadfence();
+        if (atomicAdd(&a.counter[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&a.counter[0], 0);
+            atomicExch(&a.counter[1], 0);
+        }
+    }
+}
+
+template <int CF, int B3, bool C64>
+hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
+{
+    contract<CF, B3, C64><<<dim3(grid), dim3(WG), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace f32p
+
+int f32p_lds_bytes(int cf, int b3)
+{
+#define BBR_SIZE(CF_, B3_) \
+    if (cf == CF_ && b3 == B3_) return (int)f32p::Shape<CF_, B3_>::lds;
+    BBR_SIZE(1, 16) BBR_SIZE(2, 16) BBR_SIZE(3, 16) BBR_SIZE(4, 16)
+    BBR_SIZE(1, 32) BBR_SIZE(2, 32) BBR_SIZE(3, 32) BBR_SIZE(4, 32)
+#undef BBR_SIZE
+    return -1;
+}
+
+int f32p_pairs(int b3) { return b3 == 16 || b3 == 32 ? f32p::MT / b3 : -1; }
+
+hipError_t launch_f32p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st)
+{
+#define BBR_CASE(CF_, B3_)      \
+    if (cf == CF_ && b3 == B3_) \
+        return c64 ? f32p::run<CF_, B3_, true>(a, grid, st) : f32p::run<CF_, B3_, false>(a, grid, st);
+    BBR_CASE(1, 16) BBR_CASE(2, 16) BBR_CASE(3, 16) BBR_CASE(4, 16)
+    BBR_CASE(1, 32) BBR_CASE(2, 32) BBR_CASE(3, 32) BBR_CASE(4, 32)
+#undef BBR_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bb

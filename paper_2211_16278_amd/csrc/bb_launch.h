@@ -58,6 +58,13 @@ hipError_t launch_f64(int cf, int c64, const GemmArgs &a, int grid, hipStream_t 
 int f64p_lds_bytes(int cf, int b3);
 int f64p_pairs(int b3);
 hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
+// FP32 paper-order kernel (plan kernel 7): kernel 6's design in single
+// precision, the momentum projection on v_mfma_f32_16x16x4_f32 with four real
+// products, chunks of 32 sites; 16 cf momenta per tile (cf 1 to 4).  Static
+// LDS bytes and pairs per tile (-1 when no instantiation), launch.
+int f32p_lds_bytes(int cf, int b3);
+int f32p_pairs(int b3);
+hipError_t launch_f32p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 int zgemm_shape(int M, int N, int K, int batch);  // index of the wave layout a launch uses
 hipError_t launch_zgemm(const ZgemmArgs &a, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);

@@ -81,7 +81,7 @@ def _fields(L, shapes, workload, dtype=np.complex128):
 
 CASES = [("fp32", 1, 7), ("fp32", 1, 4), ("bf16x3", 1, 7), ("bf16x3", 2, 7), ("bf16x3", 4, 5), ("bf16x3", 3, 1),
          ("bf16x3", 3, 2), ("fp32", 0, 4), ("bf16x3", 0, 2), ("fp64", 5, 7), ("fp64", 5, 2), ("fp64", 6, 2),
-         ("fp64", 6, 3), ("fp64", 0, 7)]
+         ("fp64", 6, 3), ("fp64", 0, 7), ("fp32", 7, 2), ("fp32", 7, 4)]
 
 
 @pytest.mark.parametrize("prec,kernel,nb", CASES)
@@ -91,7 +91,7 @@ def test_walking_tiles_bitwise_equal_to_split_reduction(torch_dev, prec, kernel,
     L = 20
     shapes = [(24, 20, 32), (24, 20, 32), (17, 33, 21)]
     trips = _fields(L, shapes, workload=160)
-    mom = synth.momenta("cube" if kernel in (3, 6) else "axis")  # the paper-order kernels: many momenta
+    mom = synth.momenta("cube" if kernel in (3, 6, 7) else "axis")  # the paper-order kernels: many momenta
     plans = {s: dict(kernel=kernel, nb=nb, splits=2, persistent=0) for s in set(shapes)}
     say("case walk vs split reduction", prec, kernel, nb)
     a, _ = _run(torch_dev, prec, L, trips, mom, "0", plans)

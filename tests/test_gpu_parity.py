@@ -149,6 +149,8 @@ def _plans(prec):
         kernels += [(5, 2), (5, 4), (5, 7), (6, 1), (6, 2), (6, 3)]
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
+    if prec == "fp32":
+        kernels += [(7, 1), (7, 2), (7, 3), (7, 4)]
     if prec == "bf16x3":
         kernels += [(2, 4), (2, 5), (2, 6), (2, 7), (3, 1), (3, 2), (4, 4), (4, 5), (4, 6), (4, 7)]
     for kernel, nb in kernels:
@@ -243,22 +245,24 @@ def test_paper_order_kernel(torch_dev, L, ns, mset, dtype):
 @pytest.mark.parametrize("L,ns,mset,dtype", [(5, (19, 21, 33), "cube", "c128"), (4, (16, 17, 64), "shell4", "c128"),
                                              (5, (24, 9, 40), "shell4", "c64"), (4, (7, 5, 16), "axis", "c128"),
                                              (3, (9, 11, 50), "zero", "c128")])
-def test_paper_order_fp64_kernel(torch_dev, L, ns, mset, dtype):
-    """FP64 paper-order kernel 6 (singlet on the vector unit, three-product
-    momentum GEMM on the FP64 matrix cores) for one to three momentum
-    fragments and both d3 blocks, ragged pair, d3 and momentum edges and
-    sites that end inside a chunk, against the oracle at the FP64 tolerance;
-    persistent and one-tile-per-workgroup schedules agree bitwise."""
+@pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4))])
+def test_paper_order_fp64_fp32_kernels(torch_dev, prec, kernel, nbs, L, ns, mset, dtype):
+    """FP64 paper-order kernel 6 and FP32 kernel 7 (singlet on the vector
+    unit in the MFMA operand layout, momentum GEMM on the matrix cores) for
+    every momentum-fragment width and both d3 blocks, ragged pair, d3 and
+    momentum edges and sites that end inside a chunk, against the oracle at
+    the precision's tolerance; persistent and one-tile-per-workgroup
+    schedules agree bitwise."""
     qs = fields(L, ns, workload=116, dtype=np.complex64 if dtype == "c64" else np.complex128)
     mom = synth.momenta(mset)
     ref = oracle.bblock(L, *qs, mom)
-    for nb in (1, 2, 3):
-        say("case fp64 paper-order", L, ns, mset, dtype, nb)
-        a = gpu_block(torch_dev, "fp64", L, qs, mom, dtype=dtype, plan=dict(kernel=6, nb=nb, splits=3, persistent=0))
-        b = gpu_block(torch_dev, "fp64", L, qs, mom, dtype=dtype,
-                      plan=dict(kernel=6, nb=nb, splits=3, persistent=1, grid=6))
+    for nb in nbs:
+        say("case paper-order", prec, kernel, L, ns, mset, dtype, nb)
+        a = gpu_block(torch_dev, prec, L, qs, mom, dtype=dtype, plan=dict(kernel=kernel, nb=nb, splits=3, persistent=0))
+        b = gpu_block(torch_dev, prec, L, qs, mom, dtype=dtype,
+                      plan=dict(kernel=kernel, nb=nb, splits=3, persistent=1, grid=6))
         assert np.array_equal(a, b)
-        assert err_max(a, ref) < TOL["fp64"], err_max(a, ref)
+        assert err_max(a, ref) < TOL[prec], err_max(a, ref)
 
 
 def test_precomputed_w_small_workspace_falls_back(torch_dev):
@@ -417,6 +421,10 @@ def test_plan_validation_and_defaults(torch_dev):
                 for kernel, nb in ((5, 7), (6, 2)):  # kernels 5 and 6 are FP64 only
                     with pytest.raises(binding.BBlockError):
                         bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
+                assert bb.get_plan(n, n, n, 8)["kernel"] == 1  # the paper-order kernel 7 from 9 momenta
+                assert bb.get_plan(n, n, n, 9)["kernel"] == 7
+                with pytest.raises(binding.BBlockError):  # kernel 7 has 1 to 4 momentum fragments
+                    bb.set_plan(n, n, n, 27, dict(kernel=7, nb=5, splits=0, persistent=0, grid=0))
             else:
                 for nb in (1, 2, 3):
                     bb.set_plan(n, n, n, 27, dict(kernel=6, nb=nb, splits=0, persistent=0, grid=0))
@@ -426,6 +434,8 @@ def test_plan_validation_and_defaults(torch_dev):
                         bb.set_plan(n, n, n, 27, dict(kernel=6, nb=nb, splits=0, persistent=0, grid=0))
                 with pytest.raises(binding.BBlockError):  # n3 below the d3 block of 16
                     bb.set_plan(n, n, 8, 27, dict(kernel=6, nb=2, splits=0, persistent=0, grid=0))
+                with pytest.raises(binding.BBlockError):  # kernel 7 is FP32 only
+                    bb.set_plan(n, n, n, 27, dict(kernel=7, nb=2, splits=0, persistent=0, grid=0))
                 bb.set_plan(n, n, n, 27, None)
 
 
