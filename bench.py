@@ -45,7 +45,7 @@ def kernel_name(path, plan, n2, n3):
     if plan["kernel"] == 6:
         return "bb::f64p::contract<%d, %d, false>" % (plan["nb"], 32 if plan["nb"] == 1 and n3 >= 32 else 16)
     if plan["kernel"] == 7:
-        return "bb::f32p::contract<%d, %d, false>" % (plan["nb"], 32 if n3 >= 32 else 16)
+        return "bb::f32p::contract<%d, %d, false>" % (plan["nb"], 32 if plan["nb"] > 2 and n3 >= 32 else 16)
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
         return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)

@@ -88,7 +88,7 @@ typedef struct {
     int32_t kernel;      /* 0: generic tiles (any shape, every precision);
                             1: pipelined rectangular tiles (FP32 and BF16X3,
                                n2 >= 16 and n3 >= 16; nb 4 or 7; the FP32
-                               default up to 8 momenta);
+                               default up to 7 momenta);
                             2: as 1 with the phase-weighted q3 precomputed
                                into workspace images by a separate launch
                                (BF16X3 only; n2 >= 8,
@@ -124,7 +124,7 @@ typedef struct {
                                projection on the FP32 matrix cores with
                                four real products (FP32 only, n3 >= 16; nb
                                1 to 4 fragments of 16 momenta; the FP32
-                               default from 9 momenta). */
+                               default from 8 momenta). */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device (paper, Sec. 2 after

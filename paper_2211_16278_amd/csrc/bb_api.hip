@@ -43,9 +43,9 @@ constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, 
 // against 5.6 at 33).
 constexpr int F64P_MIN_MOM = 8;
 // FP32 momenta above which the paper-order kernel 7 is the default (at 32^3,
-// N_dil 32, ms per block: kernel 1 1.87 against 2.16 at 8 momenta, 2.98
-// against 2.16 at 10, 5.9 against 3.1 at 27, 8.0 against 4.1 at 33).
-constexpr int F32P_MIN_MOM = 8;
+// N_dil 32, ms per block: kernel 1 1.56 against 1.59 at 7 momenta, 1.86
+// against 1.58 at 8, 5.9 against 2.5 at 27, 8.0 against 4.1 at 33).
+constexpr int F32P_MIN_MOM = 7;
 // Kernel 2 and its eight-wave form 4 share geometry, images and workspace.
 inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 
@@ -287,8 +287,10 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_nt = cdiv(n_mom, g.n_tile);
         g.lds = lds;
     } else if (kernel == K_F32P) {
-        // As kernel 6, in FP32: d3 blocks of 32 (16 below 32), 16 nb momenta.
-        g.b3 = pipelined_block(n3);
+        // As kernel 6, in FP32, 16 nb momenta: d3 blocks of 16 up to two
+        // momentum fragments (two workgroups then share a CU), else 32
+        // (16 below 32).
+        g.b3 = n3 < 16 ? 0 : (nb <= 2 || n3 < 32 ? 16 : 32);
         if (h->prec != FP32 || g.b3 == 0) return g;
         const int pairs = f32p_pairs(g.b3), lds = f32p_lds_bytes(nb, g.b3);
         if (pairs <= 0 || lds <= 0) return g;
@@ -333,6 +335,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
 int wg_per_cu(bblock_t h, const Geometry &g)
 {
     if (g.kernel == K_PORD) return 2;
+    if (g.kernel == K_F32P) return f32p_wgs(g.nb, g.b3);
     if (g.kernel == K_GENERIC && h->prec == FP64 && g.nb <= 7 && 2 * g.lds <= h->lds_max) return 2;
     return 1;
 }

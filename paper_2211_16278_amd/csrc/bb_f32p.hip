@@ -10,7 +10,8 @@
 // split of at most 4096 sites, the splits summed in FP64.  The FP32 vector
 // work (singlet, tile builds) can issue while the FP32 MFMAs run.
 //
-// Workgroup: eight wave64, two per SIMD.  Tile: 128 rows = NPAIR (d1,d2)
+// Workgroup: eight wave64, two per SIMD (two workgroups per CU for tiles
+// of one or two momentum fragments and d3 blocks of 16).  Tile: 128 rows = NPAIR (d1,d2)
 // pairs x a block of B3 d3 values, 16 CF momenta, one site split; wave w
 // owns rows 16 w to 16 w + 15 (16 d3 values of one pair) and all momenta:
 // 2 x CF accumulator fragments (Re, Im).  Chunks of 32 sites, double
@@ -51,6 +52,11 @@ struct Shape {
     static_assert(ND % 64 == 0 && ND <= WG, "diquark items end on a wave boundary, one per thread");
     static_assert(NQ % 256 == 0 && NP % 256 == 0, "q3 and phase items end on a wave boundary");
     static_assert(lds <= 160 * 1024, "two buffers fit the LDS");
+    // Workgroups per CU: two for the narrow tiles with d3 blocks of 16 (their
+    // LDS and at most 128 VGPRs let both fit, and four waves per SIMD hide
+    // more latency than two), one otherwise.
+    static constexpr int WGS = (B3 == 16 && CF <= 2) ? 2 : 1;
+    static_assert(WGS == 1 || 2 * lds <= 160 * 1024, "two workgroups fit the LDS");
 };
 
 template <bool C64>
@@ -85,7 +91,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int 
 }
 
 template <int CF, int B3, bool C64>
-__global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
+__global__ void __launch_bounds__(WG, (Shape<CF, B3>::WGS)) contract(GemmArgs a)
 {
     using Sh = Shape<CF, B3>;
     constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF;
@@ -340,6 +346,16 @@ int f32p_lds_bytes(int cf, int b3)
 }
 
 int f32p_pairs(int b3) { return b3 == 16 || b3 == 32 ? f32p::MT / b3 : -1; }
+
+int f32p_wgs(int cf, int b3)
+{
+#define BBR_WGS(CF_, B3_) \
+    if (cf == CF_ && b3 == B3_) return f32p::Shape<CF_, B3_>::WGS;
+    BBR_WGS(1, 16) BBR_WGS(2, 16) BBR_WGS(3, 16) BBR_WGS(4, 16)
+    BBR_WGS(1, 32) BBR_WGS(2, 32) BBR_WGS(3, 32) BBR_WGS(4, 32)
+#undef BBR_WGS
+    return 1;
+}
 
 hipError_t launch_f32p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st)
 {

@@ -64,6 +64,7 @@ hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hip
 // LDS bytes and pairs per tile (-1 when no instantiation), launch.
 int f32p_lds_bytes(int cf, int b3);
 int f32p_pairs(int b3);
+int f32p_wgs(int cf, int b3);  // workgroups of kernel 7 per CU
 hipError_t launch_f32p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 int zgemm_shape(int M, int N, int K, int batch);  // index of the wave layout a launch uses
 hipError_t launch_zgemm(const ZgemmArgs &a, hipStream_t st);

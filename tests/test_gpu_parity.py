@@ -421,8 +421,8 @@ def test_plan_validation_and_defaults(torch_dev):
                 for kernel, nb in ((5, 7), (6, 2)):  # kernels 5 and 6 are FP64 only
                     with pytest.raises(binding.BBlockError):
                         bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
-                assert bb.get_plan(n, n, n, 8)["kernel"] == 1  # the paper-order kernel 7 from 9 momenta
-                assert bb.get_plan(n, n, n, 9)["kernel"] == 7
+                assert bb.get_plan(n, n, n, 7)["kernel"] == 1  # the paper-order kernel 7 from 8 momenta
+                assert bb.get_plan(n, n, n, 8)["kernel"] == 7
                 with pytest.raises(binding.BBlockError):  # kernel 7 has 1 to 4 momentum fragments
                     bb.set_plan(n, n, n, 27, dict(kernel=7, nb=5, splits=0, persistent=0, grid=0))
             else:
