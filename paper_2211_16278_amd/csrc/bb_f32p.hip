@@ -7,8 +7,10 @@
 //   B[p][(d1,d2)][d3] = sum_x S[x; (d1,d2), d3] exp(-i p.x)
 // on v_mfma_f32_16x16x4_f32 with the real embedding (four real products:
 // Re += Sr er - Si ei, Im += Sr ei + Si er), FP32 accumulation over a site
-// split of at most 4096 sites, the splits summed in FP64.  The FP32 vector
-// work (singlet, tile builds) can issue while the FP32 MFMAs run.
+// split of at most 4096 sites, the splits summed in FP64.  As with FP64, the
+// counters show no co-execution of vector work with these MFMAs: the second
+// workgroup per CU of the narrow tiles is what covers the vector work's and
+// the LDS's latencies.
 //
 // Workgroup: eight wave64, two per SIMD (two workgroups per CU for tiles
 // of one or two momentum fragments and d3 blocks of 16).  Tile: 128 rows = NPAIR (d1,d2)
