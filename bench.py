@@ -88,20 +88,22 @@ def sources_of(kname: str):
     raise KeyError(kname)
 
 
-def mfma_flops_executed(path, plan, f_gemm):
+def mfma_flops_executed(path, plan, f_gemm, mom_frac=1.0):
     """Matrix-core flops one headline launch executes: the fused complex GEMM
     (F_gemm = 24 n_mom V n^3, 8 real flops per complex multiply-add), three
     times over for the three BF16 products of BF16x3; the FP64 kernel 5 forms
     each complex product from three real products (6 real flops per complex
     multiply-add), 3/4 of F_gemm; the FP64 paper-order kernel 6 only the
     momentum projection, with three real products (6 n_mom V n^3), 1/4 of
-    F_gemm."""
+    F_gemm, the FP32 kernel 7 with four (1/3); mom_frac: the share of the
+    momenta the matrix cores project (kernels 6 and 7 sum a zero momentum
+    of 16 k + 1 on the vector unit)."""
     if plan["kernel"] == 5:
         return 0.75 * f_gemm
     if plan["kernel"] == 6:
-        return 0.25 * f_gemm
+        return 0.25 * f_gemm * mom_frac
     if plan["kernel"] == 7:
-        return f_gemm / 3.0
+        return f_gemm / 3.0 * mom_frac
     return MFMA_PASSES[path] * f_gemm
 
 
@@ -179,14 +181,24 @@ def device_fields(torch, dev, shape_list, dtype, seed):
     return out
 
 
-def mfma_flops(plan, V, n1, n2, n3, n_mom):
+def zero_on_vector_unit(plan, mom, L):
+    """Kernels 6 and 7 sum the zero momentum (mod L) of a set of 16 k + 1 > 1
+    momenta on the vector unit and project only the other 16 k on the
+    matrix cores."""
+    n = len(mom)
+    return (plan["kernel"] in (6, 7) and n > 1 and n % 16 == 1
+            and any(all(int(c) % L == 0 for c in m) for m in mom))
+
+
+def mfma_flops(plan, V, n1, n2, n3, n_mom, zero_off=False):
     """Flops of one MFMA pass of the formulation a plan runs: the fused GEMM
     (24 n_mom V n1 n2 n3; 18 for FP64 kernel 5's three real products) or, for
     the paper-order kernels, only the momentum projection (8 n_mom V n1 n2 n3
     for kernels 3 and 7, 6 for FP64 kernel 6; their singlet runs on the
-    vector unit)."""
+    vector unit), over n_mom - 1 momenta when the zero one is summed on the
+    vector unit (zero_off)."""
     per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 8.0}.get(plan["kernel"], 24.0)
-    return per * n_mom * V * n1 * n2 * n3
+    return per * (n_mom - (1 if zero_off else 0)) * V * n1 * n2 * n3
 
 
 def batch_workload(torch, dev, name):
@@ -296,7 +308,7 @@ def run_batch_workload(args, name):
             shp = (q1.shape[-1], q2.shape[-1], q3.shape[-1], len(mom))
             plan = bb.get_plan(*shp)
             kernels.add(plan["kernel"])
-            f_mfma += mfma_flops(plan, L ** 3, *shp)
+            f_mfma += mfma_flops(plan, L ** 3, *shp, zero_off=zero_on_vector_unit(plan, mom, L))
         bb.close()
         err = None
         if name != "projected-32" and not args.no_parity:
@@ -718,7 +730,8 @@ def main() -> int:
         bb.close()
         step_ms = max(ms, wall * 1e3) / args.steps
         g_avg = gemm_ms / max(1, launches)
-        f_exec = mfma_flops_executed(pname, plan, f_gemm)
+        f_exec = mfma_flops_executed(pname, plan, f_gemm,
+                                     1.0 - (1.0 / len(mom) if zero_on_vector_unit(plan, mom, L) else 0.0))
         ach = f_exec / (g_avg * 1e-3) / 1e12
         kname = kernel_name(pname, plan, n, n)
         # HBM bytes from the committed counters; the minimal bytes of a block

@@ -124,7 +124,12 @@ typedef struct {
                                projection on the FP32 matrix cores with
                                four real products (FP32 only, n3 >= 16; nb
                                1 to 4 fragments of 16 momenta; the FP32
-                               default from 8 momenta). */
+                               default from 8 momenta).
+                            Kernels 6 and 7, given 16 k + 1 > 1 momenta of
+                            which one is zero mod L (the first such), sum
+                            that one's sites (phase 1) on the vector unit
+                            and project the other 16 k on the matrix cores:
+                            the paper's 33 momenta fill 2 fragments, not 3. */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device (paper, Sec. 2 after
@@ -297,7 +302,10 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
 bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom,
                               const bblock_plan *plan);
 
-/* The plan the handle would use for one block shape (forced, tuned or default). */
+/* The plan the handle would use for one block shape (forced, tuned or
+ * default).  At 16 k + 1 momenta it is the plan of a set that holds the
+ * zero momentum (kernels 6 and 7 then count 16 k momentum columns; the
+ * paper's momentum shells hold it). */
 bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_t n_mom,
                               bblock_plan *plan);
 

@@ -154,6 +154,7 @@ struct bblock_s {
 
     int graph_mode = 2;               // 0: eager, 1: capture and replay, 2: replay schedules of 4+ launches
     int walk_mode = 2;                // walking tiles: 0 never, 1 every unprojected batch, 2 when the partials do not fit
+    int p_skip = -1;                  // zero momentum the paper-order FP64/FP32 kernels sum on the vector unit (-1: none)
     bool profiling = false;
     int plan_gen = 0;                 // bumped whenever forced or tuned plans change
     // The last batch: when a call repeats it (same descriptors, momenta and
@@ -237,12 +238,26 @@ int w3_col_block(int n)
     return cdiv(n, cdiv(n, 32));
 }
 
+// The zero momentum the paper-order FP64/FP32 kernels take off the matrix
+// cores: the first momentum that is zero mod L, in a set of 16 k + 1 > 1
+// momenta (where dropping one saves a padded column fragment); -1 otherwise.
+int zero_momentum_column(const int32_t *mom, int n_mom, int L)
+{
+    if (n_mom < 2 || n_mom % 16 != 1) return -1;
+    for (int i = 0; i < n_mom; ++i)
+        if (mom[3 * i] % L == 0 && mom[3 * i + 1] % L == 0 && mom[3 * i + 2] % L == 0) return i;
+    return -1;
+}
+
 // Geometry of (kernel, nb) for one block shape; lds < 0 when unsupported.
 Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_mom)
 {
     Geometry g;
     g.kernel = kernel;
     g.nb = nb;
+    // Momentum columns of the paper-order FP64/FP32 kernels: all but a zero
+    // momentum they sum on the vector unit.
+    const int mcols = n_mom - (h->p_skip >= 0 ? 1 : 0);
     if (kernel == K_PIPELINED || is_w3(kernel)) {
         g.b2 = is_w3(kernel) ? w3_row_block(n2) : row_block(n2);
         g.b3 = is_w3(kernel) ? w3_col_block(n3) : pipelined_block(n3);
@@ -284,7 +299,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.bp = 16 * nb;
         g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
         g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
-        g.n_nt = cdiv(n_mom, g.n_tile);
+        g.n_nt = cdiv(mcols, g.n_tile);
         g.lds = lds;
     } else if (kernel == K_F32P) {
         // As kernel 6, in FP32, 16 nb momenta: d3 blocks of 16 up to two
@@ -299,7 +314,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.bp = 16 * nb;
         g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
         g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
-        g.n_nt = cdiv(n_mom, g.n_tile);
+        g.n_nt = cdiv(mcols, g.n_tile);
         g.lds = lds;
     } else if (kernel == K_PORD) {
         // Rows (d1,d2,d3): a block of consecutive (d1,d2) pairs x a d3 block;
@@ -628,6 +643,7 @@ bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &s
         ga.roots = h->d_roots;
         ga.kidx = mem.kidx;
         ga.kstride = kstride_of(h);
+        ga.p_skip = h->p_skip;
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
         if (is_w3(sb.kernel)) {
@@ -733,6 +749,7 @@ bblock_status launch_planned(bblock_t h, const Mem &mem, const std::vector<SubBa
     sig.push_back((long long)(uintptr_t)h->d_kidx);
     sig.push_back((long long)(uintptr_t)h->d_ws);
     for (int k = 0; k < T_COUNT; ++k) sig.push_back((long long)offs[k]);
+    sig.push_back(h->p_skip);
     for (const SubBatch &sb : subs)
         sig.insert(sig.end(), {sb.first, sb.count, sb.tile_off, sb.n_tiles, sb.list_off, sb.n_list, sb.kernel, sb.nb,
                                sb.b2, sb.b3, sb.persistent, sb.grid, sb.max_mn, sb.went_off, sb.n_went, sb.cps_max,
@@ -780,6 +797,11 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         bblock_status st = validate_desc(h, desc[i], i);
         if (st != BBLOCK_OK) return st;
     }
+
+    // A set of 16 k + 1 momenta that holds the zero momentum: the paper-order
+    // FP64/FP32 kernels project on the other 16 k in k momentum fragments and
+    // sum the sites for the zero momentum (phase 1) on the vector unit.
+    h->p_skip = zero_momentum_column(mom, n_mom, h->L);
 
     // Spin projection: output groups by out pointer, in order of first use.
     std::vector<int> group_of(n_desc, -1);
@@ -1646,7 +1668,12 @@ bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
 {
     if (!h || !plan) return fail(h, BBLOCK_EINVAL, "null argument");
     if (bblock_status st = shape_ok(h, n1, n2, n3, n_mom)) return st;
+    // The plan of a momentum set that holds the zero momentum (it differs
+    // from one without only at 16 k + 1 momenta).
+    const int saved_skip = h->p_skip;
+    h->p_skip = n_mom > 1 && n_mom % 16 == 1 ? 0 : -1;
     const Plan p = plan_for(h, n1, n2, n3, n_mom);
+    h->p_skip = saved_skip;
     plan->nb = p.nb;
     plan->splits = h->forced.count(ShapeKey{n1, n2, n3, n_mom}) ? p.splits : single_splits(p.splits, min_splits(h));
     plan->persistent = p.persistent;

@@ -31,6 +31,12 @@
 // loads of the chunk after it.  Quark and phase-index loads go through
 // per-chunk buffer resources: loads past the split, of pairs past M, of d3
 // past n3 or momenta past n_mom return zero (no masks).
+//
+// Zero momentum (instantiation Z, a.p_skip >= 0): its phase is 1 at every
+// site, so its projection is the plain site sum of the singlet.  Each lane
+// adds its singlets into two registers, the four k-groups are summed across
+// lanes at the end, and the tiles of column block 0 write it; the columns
+// hold the other momenta, so a set of 16 k + 1 momenta takes k fragments.
 #include <algorithm>
 
 #include "bb_fast.h"
@@ -105,7 +111,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int 
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, ns * 3 * n * ESZ, 0x00020000);
 }
 
-template <int CF, int B3, bool C64>
+template <int CF, int B3, bool C64, bool Z>
 __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 {
     using Sh = Shape<CF, B3>;
@@ -163,13 +169,19 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
             const int d = q % B3, sc = q / B3;
             o3[j] = (q < Sh::NQ && d3_0 + d < bd.n3) ? (uint32_t)((sc * bd.n3 + d3_0 + d) * ESZ) : OOB;
         }
-        // Phase items q = tid + WG j = (s NC + jc): momentum p0 + jc at site s.
+        // Momentum columns: every momentum but, with Z, a.p_skip (the zero
+        // momentum, summed on the vector unit and written by the tiles of
+        // column block 0).
+        const int ps = Z ? a.p_skip : -1, n_col = a.n_mom - (Z ? 1 : 0);
+        const bool zsum = Z && tl.z == 0;  // wave-uniform
+        // Phase items q = tid + WG j = (s NC + jc): column p0 + jc at site s.
         uint32_t ok[Sh::JP];
 #pragma unroll
         for (int j = 0; j < Sh::JP; ++j) {
             const int q = tid + WG * j;
-            const int jc = q % NC, s = q / NC;
-            ok[j] = (q < Sh::NP && p0 + jc < a.n_mom) ? (uint32_t)((p0 + jc) * a.kstride + s) : OOB;
+            const int jc = q % NC, s = q / NC, col = p0 + jc;
+            const int pm = col + (Z && col >= ps ? 1 : 0);
+            ok[j] = (q < Sh::NP && col < n_col) ? (uint32_t)(pm * a.kstride + s) : OOB;
         }
         const int krec = a.n_mom * a.kstride;
 
@@ -248,6 +260,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         // (row, site) from LDS, then 3 CF MFMAs; after the first k-step the
         // next chunk's tiles go into buffer b ^ 1 and the loads of the chunk
         // after it are issued.
+        double zr = 0.0, zi = 0.0;  // this lane's (row, site) singlets summed: the zero momentum
         auto chunk = [&](int b, int ci_next) {
             asm volatile("" : "+s"(b));
             // Per-lane bases (one address each; the k-step, colour, plane and
@@ -287,6 +300,10 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                     si = __builtin_fma(dv[slot][c].y, qv[slot][c].x, si);
                 }
                 const double ss = sr + si;
+                if constexpr (Z) {
+                    zr += sr;
+                    zi += si;
+                }
                 // The next k-step's operands load under this one's MFMAs.
                 if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
 #pragma unroll
@@ -311,14 +328,22 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
             chunk(i & 1, i + 2);
             __syncthreads();
         }
+        if constexpr (Z) {
+            // The four sites of a k-step sit in lanes l, l + 16, l + 32, l + 48.
+            zr += __shfl_xor(zr, 16);
+            zi += __shfl_xor(zi, 16);
+            zr += __shfl_xor(zr, 32);
+            zi += __shfl_xor(zi, 32);
+        }
 
         // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  Accumulator register
         // e of a 16x16 f64 fragment holds row 4 e + lane / 16, column lane % 16.
         with_put_mode(bd, tl.w, [&](auto mode) {
 #pragma unroll
             for (int n = 0; n < CF; ++n) {
-                const int p = p0 + n * 16 + li;
-                if (p >= a.n_mom) continue;
+                const int col = p0 + n * 16 + li;
+                if (col >= n_col) continue;
+                const int p = col + (Z && col >= ps ? 1 : 0);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int r = wave * 16 + 4 * e + kg;
@@ -329,6 +354,14 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                     const int nu = p * bd.n3 + d3;
                     put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 0, re);
                     put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 1, im);
+                }
+            }
+            if (Z && zsum && kg == 0) {
+                const int mo = m12_0 + pair_l, d3 = d3_0 + d3_l;
+                if (mo < M12 && d3 < bd.n3) {
+                    const int nu = ps * bd.n3 + d3;
+                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, ps, d3, 0, (double)zr);
+                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, ps, d3, 1, (double)zi);
                 }
             }
         });
@@ -354,7 +387,10 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 template <int CF, int B3, bool C64>
 hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
 {
-    contract<CF, B3, C64><<<dim3(grid), dim3(WG), 0, st>>>(a);
+    if (a.p_skip >= 0)
+        contract<CF, B3, C64, true><<<dim3(grid), dim3(WG), 0, st>>>(a);
+    else
+        contract<CF, B3, C64, false><<<dim3(grid), dim3(WG), 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -125,6 +125,10 @@ struct GemmArgs {
     const double *roots; // [L] complex128 exp(-2 pi i k / L)
     const unsigned char *kidx;  // [n_mom][kstride] phase index (n_p . x) mod L (pipelined, paper-order)
     int kstride;                // row stride of kidx: V rounded up to a multiple of 4 (padding reads 0)
+    // Paper-order FP64/FP32 kernels: index of a zero momentum whose
+    // projection (a plain sum over sites: its phase is 1) they form on the
+    // vector unit, its column left out of the MFMA tiles; -1 for none.
+    int p_skip;
 };
 
 // Arguments of the W-image launch of the precomputed-W kernel.

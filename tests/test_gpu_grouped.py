@@ -102,6 +102,25 @@ def test_walking_tiles_bitwise_equal_to_split_reduction(torch_dev, prec, kernel,
     assert err_max(b[2], ref) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec,kernel", (("fp64", 6), ("fp32", 7)))
+def test_walking_tiles_zero_momentum_on_vector_unit(torch_dev, prec, kernel):
+    """The paper-order FP64/FP32 kernels with the 33-momentum shell (the zero
+    momentum summed on the vector unit): walking tiles equal the split-K run
+    bitwise, and the oracle."""
+    L = 20
+    shapes = [(24, 20, 32), (17, 33, 21)]
+    trips = _fields(L, shapes, workload=163)
+    mom = synth.momenta("shell4")
+    plans = {s: dict(kernel=kernel, nb=2, splits=2, persistent=0) for s in set(shapes)}
+    say("case walk vs split reduction, zero momentum on the vector unit", prec, kernel)
+    a, _ = _run(torch_dev, prec, L, trips, mom, "0", plans)
+    b, _ = _run(torch_dev, prec, L, trips, mom, "1", plans)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    ref = oracle.bblock(L, *trips[1], mom)
+    assert err_max(b[1], ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ("fp64", "fp32", "bf16x3"))
 def test_uneven_batch_one_launch_per_instantiation(torch_dev, prec):
     """Blocks of N_dil 16, 32 and 64 interleaved as the uneven workload orders

@@ -265,6 +265,41 @@ def test_paper_order_fp64_fp32_kernels(torch_dev, prec, kernel, nbs, L, ns, mset
         assert err_max(a, ref) < TOL[prec], err_max(a, ref)
 
 
+def _zero_momentum_sets(L):
+    """Momentum sets of 16 k + 1 that hold a momentum zero mod L (the FP64 and
+    FP32 paper-order kernels then sum it on the vector unit and project on
+    the other 16 k), and a control without one."""
+    cube, shell = synth.momenta("cube"), synth.momenta("shell4")
+    mid = cube[:17]                                   # (0, 0, 0) at position 13
+    wrapped = np.delete(shell, 0, axis=0)
+    wrapped = np.insert(wrapped, 20, [L, 0, -L], axis=0)  # zero mod L at position 20
+    twice = shell.copy()
+    twice[9] = 0                                      # a second zero: a column of its own
+    none = np.delete(cube, 13, axis=0)[:17]           # 17 momenta, none zero
+    return {"mid-17": mid, "wrapped-33": wrapped, "twice-33": twice, "none-17": none}
+
+
+@pytest.mark.parametrize("mset", ["mid-17", "wrapped-33", "twice-33", "none-17"])
+@pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4))])
+def test_zero_momentum_on_vector_unit(torch_dev, prec, kernel, nbs, mset):
+    """The zero momentum of a 16 k + 1 set summed on the vector unit (wherever
+    it sits in the set, also as a multiple of L, once when repeated): every
+    column width, split partials, both schedules bitwise equal, and the
+    oracle at the precision's tolerance."""
+    L, ns = 5, (19, 21, 40)
+    qs = fields(L, ns, workload=117)
+    mom = _zero_momentum_sets(L)[mset]
+    ref = oracle.bblock(L, *qs, mom)
+    for nb in nbs:
+        say("case zero momentum", prec, kernel, mset, nb)
+        a = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(kernel=kernel, nb=nb, splits=3, persistent=0))
+        b = gpu_block(torch_dev, prec, L, qs, mom, plan=dict(kernel=kernel, nb=nb, splits=3, persistent=1, grid=6))
+        assert np.array_equal(a, b)
+        assert err_max(a, ref) < TOL[prec], err_max(a, ref)
+    c = gpu_block(torch_dev, prec, L, qs, mom)  # the default plan
+    assert err_max(c, ref) < TOL[prec], err_max(c, ref)
+
+
 def test_precomputed_w_small_workspace_falls_back(torch_dev):
     """A workspace cap too small for the W images: the planner runs the block
     with the in-LDS W kernel instead, with the same result."""
@@ -417,12 +452,16 @@ def test_plan_validation_and_defaults(torch_dev):
                 assert bb.get_plan(n, n, n, 8)["kernel"] == 5
                 assert bb.get_plan(n, n, n, 9)["kernel"] == 6
                 assert bb.get_plan(n, n, 8, 33)["kernel"] == 5  # n3 below kernel 6's d3 block
+                # 33 momenta with the zero one: 32 columns, two fragments.
+                assert (bb.get_plan(n, n, n, 33)["kernel"], bb.get_plan(n, n, n, 33)["nb"]) == (6, 2)
             if prec == "fp32":
                 for kernel, nb in ((5, 7), (6, 2)):  # kernels 5 and 6 are FP64 only
                     with pytest.raises(binding.BBlockError):
                         bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
                 assert bb.get_plan(n, n, n, 7)["kernel"] == 1  # the paper-order kernel 7 from 8 momenta
                 assert bb.get_plan(n, n, n, 8)["kernel"] == 7
+                # 33 momenta with the zero one: 32 columns, two fragments.
+                assert (bb.get_plan(n, n, n, 33)["kernel"], bb.get_plan(n, n, n, 33)["nb"]) == (7, 2)
                 with pytest.raises(binding.BBlockError):  # kernel 7 has 1 to 4 momentum fragments
                     bb.set_plan(n, n, n, 27, dict(kernel=7, nb=5, splits=0, persistent=0, grid=0))
             else:
