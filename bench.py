@@ -38,14 +38,19 @@ TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
 PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
-def kernel_name(path, plan, n2, n3):
-    """Name of the contraction kernel a plan launches (as rocprofv3 lists it)."""
+def kernel_name(path, plan, n2, n3, zero_off=False):
+    """Name of the contraction kernel a plan launches with complex128 inputs
+    (as rocprofv3 lists it)."""
+    z = "true" if zero_off else "false"
     if plan["kernel"] == 5:
         return "bb::f64::contract<%d, false>" % plan["nb"]
     if plan["kernel"] == 6:
-        return "bb::f64p::contract<%d, %d, false>" % (plan["nb"], 32 if plan["nb"] == 1 and n3 >= 32 else 16)
+        return "bb::f64p::contract<%d, %d, false, %s, 16, 1>" % (plan["nb"], 32 if plan["nb"] == 1 and n3 >= 32 else 16,
+                                                                  z)
+    if plan["kernel"] == 8:
+        return "bb::f64p::contract<%d, 16, false, false, 4, 2>" % plan["nb"]
     if plan["kernel"] == 7:
-        return "bb::f32p::contract<%d, %d, false>" % (plan["nb"], 32 if plan["nb"] > 2 and n3 >= 32 else 16)
+        return "bb::f32p::contract<%d, %d, false, %s>" % (plan["nb"], 32 if plan["nb"] > 2 and n3 >= 32 else 16, z)
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
         return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)
@@ -88,32 +93,45 @@ def sources_of(kname: str):
     raise KeyError(kname)
 
 
-def mfma_flops_executed(path, plan, f_gemm, mom_frac=1.0):
-    """Matrix-core flops one headline launch executes: the fused complex GEMM
-    (F_gemm = 24 n_mom V n^3, 8 real flops per complex multiply-add), three
-    times over for the three BF16 products of BF16x3; the FP64 kernel 5 forms
-    each complex product from three real products (6 real flops per complex
-    multiply-add), 3/4 of F_gemm; the FP64 paper-order kernel 6 only the
-    momentum projection, with three real products (6 n_mom V n^3), 1/4 of
-    F_gemm, the FP32 kernel 7 with four (1/3); mom_frac: the share of the
-    momenta the matrix cores project (kernels 6 and 7 sum a zero momentum
-    of 16 k + 1 on the vector unit)."""
-    if plan["kernel"] == 5:
-        return 0.75 * f_gemm
-    if plan["kernel"] == 6:
-        return 0.25 * f_gemm * mom_frac
-    if plan["kernel"] == 7:
-        return f_gemm / 3.0 * mom_frac
-    return MFMA_PASSES[path] * f_gemm
+def executed_flops(path, plan, V, n, n_mom, zero_off=False):
+    """FP flops one headline launch executes on the pipes its roofline prices.
+    Fused kernels: the complex GEMM on the matrix cores (F_gemm = 24 n_mom V
+    n^3, 8 real flops per complex multiply-add), three times over for the
+    three BF16 products of BF16x3; FP64 kernel 5 forms each complex product
+    from three real products (6 real flops per complex multiply-add): 3/4 of
+    F_gemm.  Paper-order kernels: the momentum projection on the matrix
+    cores (6 flops per padded momentum with three real products for FP64
+    kernels 6 and 8, 8 with four for FP32 kernel 7), plus for the FP64
+    kernels their vector work, the diquark (42 V n^2) and the singlet with
+    its Re + Im (23 V n^3): FP64 vector and matrix work share one 78.6
+    TFLOP/s issue rate on gfx950 and never overlap, so both count against
+    that peak.  zero_off: kernels 6 and 7 project n_mom - 1 momenta (the
+    zero one is summed on the vector unit)."""
+    k, nb = plan["kernel"], plan["nb"]
+    vn3 = float(V) * n ** 3
+    m = n_mom - (1 if zero_off else 0)
+    if k == 5:
+        return 0.75 * 24.0 * n_mom * vn3
+    if k in (6, 8):
+        w = 16 if k == 6 else 4
+        padded = -(-m // (w * nb)) * w * nb
+        return 6.0 * padded * vn3 + 23.0 * vn3 + 42.0 * V * n * n
+    if k == 7:
+        padded = -(-m // (16 * nb)) * 16 * nb
+        return 8.0 * padded * vn3
+    return MFMA_PASSES[path] * 24.0 * n_mom * vn3
 
 
 def flops_note(path, plan):
-    if plan["kernel"] == 5:
-        return "18 n_mom V n^3: three real products per complex multiply-add"
-    if plan["kernel"] == 6:
-        return "6 n_mom V n^3: the momentum projection with three real products"
-    if plan["kernel"] == 7:
-        return "8 n_mom V n^3: the momentum projection with four real products"
+    k = plan["kernel"]
+    if k == 5:
+        return "18 n_mom V n^3: three real products per complex multiply-add on the matrix cores"
+    if k in (6, 8):
+        return ("6 n_pad V n^3 on the matrix cores (the momentum projection with three real products, n_pad the "
+                "momenta padded to fragments of %d) + 23 V n^3 + 42 V n^2 on the vector unit (singlet, diquark), "
+                "one FP64 issue rate" % (16 if k == 6 else 4))
+    if k == 7:
+        return "8 n_pad V n^3: the momentum projection with four real products"
     return "%d x 24 n_mom V n^3" % MFMA_PASSES[path]
 
 
@@ -194,10 +212,10 @@ def mfma_flops(plan, V, n1, n2, n3, n_mom, zero_off=False):
     """Flops of one MFMA pass of the formulation a plan runs: the fused GEMM
     (24 n_mom V n1 n2 n3; 18 for FP64 kernel 5's three real products) or, for
     the paper-order kernels, only the momentum projection (8 n_mom V n1 n2 n3
-    for kernels 3 and 7, 6 for FP64 kernel 6; their singlet runs on the
+    for kernels 3 and 7, 6 for FP64 kernels 6 and 8; their singlet runs on the
     vector unit), over n_mom - 1 momenta when the zero one is summed on the
     vector unit (zero_off)."""
-    per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 8.0}.get(plan["kernel"], 24.0)
+    per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 8.0, 8: 6.0}.get(plan["kernel"], 24.0)
     return per * (n_mom - (1 if zero_off else 0)) * V * n1 * n2 * n3
 
 
@@ -730,10 +748,9 @@ def main() -> int:
         bb.close()
         step_ms = max(ms, wall * 1e3) / args.steps
         g_avg = gemm_ms / max(1, launches)
-        f_exec = mfma_flops_executed(pname, plan, f_gemm,
-                                     1.0 - (1.0 / len(mom) if zero_on_vector_unit(plan, mom, L) else 0.0))
+        f_exec = executed_flops(pname, plan, L ** 3, n, len(mom), zero_on_vector_unit(plan, mom, L))
         ach = f_exec / (g_avg * 1e-3) / 1e12
-        kname = kernel_name(pname, plan, n, n)
+        kname = kernel_name(pname, plan, n, n, zero_on_vector_unit(plan, mom, L))
         # HBM bytes from the committed counters; the minimal bytes of a block
         # are its inputs read once and its output written once.
         traffic, step_traffic, minimal_bytes = read_traffic(pname, "headline-32", kname)
@@ -760,7 +777,7 @@ def main() -> int:
                          "step_traffic": step_traffic,
                          "minimal_bytes": minimal_bytes,
                          "flops_per_launch": f_exec,
-                         "note": "achieved = MFMA flops one launch executes (%s) / mean event-timed duration of the "
+                         "note": "achieved = flops one launch executes (%s) / mean event-timed duration of the "
                                  "contraction kernel; step_frac uses the whole step" % flops_note(pname, plan)},
         }
         print("# %-6s %.3f ms/block  %.1f blocks/s  contraction %.3f ms  reduce %.3f ms  w-image %.3f ms  "

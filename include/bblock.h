@@ -113,18 +113,23 @@ typedef struct {
                                three real products per complex product
                                (FP64 only, any shape; nb 2, 4 or 7 column
                                fragments of 16; 128-row tiles, D and W built
-                               in LDS; the FP64 default up to 8 momenta).
+                               in LDS; the FP64 default up to 4 momenta).
                             6: paper order in complex double: the singlet on
                                the vector unit, the momentum projection on
                                the FP64 matrix cores with three real
                                products (FP64 only, n3 >= 16; nb 1, 2 or 3
                                fragments of 16 momenta; the FP64 default
-                               from 9 momenta).
+                               from 13 momenta).
                             7: kernel 6's order in FP32: the momentum
                                projection on the FP32 matrix cores with
                                four real products (FP32 only, n3 >= 16; nb
                                1 to 4 fragments of 16 momenta; the FP32
                                default from 8 momenta).
+                            8: kernel 6 with fragments of 4 momenta on the
+                               FP64 matrix cores' 4x4x4 form and two row
+                               sets of 16 per wave (FP64 only, n3 >= 16;
+                               nb 1 to 4 fragments of 4; the FP64 default
+                               from 5 to 12 momenta, kernel 5 up to 4).
                             Kernels 6 and 7, given 16 k + 1 > 1 momenta of
                             which one is zero mod L (the first such), sum
                             that one's sites (phase 1) on the vector unit

@@ -36,12 +36,15 @@ thread_local std::string g_create_error;
 
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
-constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, K_F64 = 5, K_F64P = 6, K_F32P = 7;
-// FP64 momenta above which the paper-order kernel 6 is the default (at 32^3,
-// N_dil 32, ms per block: kernel 5 2.19 against 2.51 at 7 momenta, about
-// 2.5 for both at 8, 3.34 against 2.50 at 10, 8.5 against 4.1 at 27, 11.3
-// against 5.6 at 33).
-constexpr int F64P_MIN_MOM = 8;
+constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, K_F64 = 5, K_F64P = 6, K_F32P = 7,
+              K_F64N = 8;
+// FP64 defaults by momentum count (at 32^3, N_dil 32, ms per block): kernel
+// 5 up to F64N_MIN_MOM (4 momenta: 1.28 against kernel 8's 1.41), kernel 8
+// (fragments of 4) up to F64P_MIN_MOM (5 to 8 momenta: 1.76 against kernel
+// 5's 2.02-2.16 and kernel 6's 2.51; 12: 2.11 against 2.52), kernel 6
+// above (16: 2.51 against 2.50; 27: 4.1 against kernel 5's 8.5).
+constexpr int F64N_MIN_MOM = 4;
+constexpr int F64P_MIN_MOM = 12;
 // FP32 momenta above which the paper-order kernel 7 is the default (at 32^3,
 // N_dil 32, ms per block: kernel 1 1.56 against 1.59 at 7 momenta, 1.86
 // against 1.58 at 8, 5.9 against 2.5 at 27, 8.0 against 4.1 at 33).
@@ -292,7 +295,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         // nb 2 and 3 than the other block).
         g.b3 = n3 < 16 ? 0 : (nb == 1 && n3 >= 32 ? 32 : 16);
         if (h->prec != FP64 || g.b3 == 0) return g;
-        const int pairs = f64p_pairs(g.b3), lds = f64p_lds_bytes(nb, g.b3);
+        const int pairs = f64p_pairs(g.b3, 16), lds = f64p_lds_bytes(nb, g.b3, 16);
         if (pairs <= 0 || lds <= 0) return g;
         g.m_tile = pairs * g.b3;
         g.n_tile = 16 * nb;
@@ -300,6 +303,19 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
         g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
         g.n_nt = cdiv(mcols, g.n_tile);
+        g.lds = lds;
+    } else if (kernel == K_F64N) {
+        // Kernel 6 with fragments of 4 momenta (nb 1 to 4), d3 blocks of 16.
+        g.b3 = n3 < 16 ? 0 : 16;
+        if (h->prec != FP64 || g.b3 == 0) return g;
+        const int pairs = f64p_pairs(g.b3, 4), lds = f64p_lds_bytes(nb, g.b3, 4);
+        if (pairs <= 0 || lds <= 0) return g;
+        g.m_tile = pairs * g.b3;
+        g.n_tile = 4 * nb;
+        g.bp = 4 * nb;
+        g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
+        g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
+        g.n_nt = cdiv(n_mom, g.n_tile);
         g.lds = lds;
     } else if (kernel == K_F32P) {
         // As kernel 6, in FP32, 16 nb momenta: d3 blocks of 16 up to two
@@ -397,6 +413,16 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
             p.kernel = best.kernel;
             p.nb = best.nb;
             p.splits = fill_splits(h, best);
+            return p;
+        }
+    }
+    if (h->prec == FP64 && n_mom > F64N_MIN_MOM && n_mom <= F64P_MIN_MOM) {
+        // FP64 with a few momenta: the paper-order kernel 8, fragments of 4.
+        const Geometry g = geometry(h, K_F64N, cdiv(n_mom, 4), n1, n2, n3, n_mom);
+        if (g.lds > 0) {
+            p.kernel = K_F64N;
+            p.nb = g.nb;
+            p.splits = fill_splits(h, g);
             return p;
         }
     }
@@ -643,7 +669,7 @@ bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &s
         ga.roots = h->d_roots;
         ga.kidx = mem.kidx;
         ga.kstride = kstride_of(h);
-        ga.p_skip = h->p_skip;
+        ga.p_skip = sb.kernel == K_F64P || sb.kernel == K_F32P ? h->p_skip : -1;
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
         if (is_w3(sb.kernel)) {
@@ -679,6 +705,7 @@ bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &s
                        : sb.kernel == K_PORD    ? launch_pord(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_F64     ? launch_f64(sb.nb, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_F64P    ? launch_f64p(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
+                       : sb.kernel == K_F64N    ? launch_f64n(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_F32P    ? launch_f32p(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                                                 : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
@@ -1050,7 +1077,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         sb.persistent = b0.plan.persistent;
         sb.grid = b0.plan.grid > 0 ? b0.plan.grid : h->num_cu;
         any_pipelined |= sb.kernel == K_PIPELINED || sb.kernel == K_PORD || sb.kernel == K_F64 || sb.kernel == K_F64P ||
-                         sb.kernel == K_F32P;
+                         sb.kernel == K_F32P || sb.kernel == K_F64N;
         size_t used = 0;
         long n_went = 0;
         const size_t u0 = u;
@@ -1643,7 +1670,7 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         return BBLOCK_OK;
     }
     if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && !is_w3(plan->kernel) && plan->kernel != K_PORD &&
-        plan->kernel != K_F64 && plan->kernel != K_F64P && plan->kernel != K_F32P)
+        plan->kernel != K_F64 && plan->kernel != K_F64P && plan->kernel != K_F32P && plan->kernel != K_F64N)
         return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
@@ -1753,6 +1780,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         for (int nb : {7, 4}) kn.push_back({K_PIPELINED, nb});
         for (int nb : {7, 4, 2}) kn.push_back({K_F64, nb});
         for (int nb : {3, 2, 1}) kn.push_back({K_F64P, nb});
+        for (int nb : {4, 3, 2, 1}) kn.push_back({K_F64N, nb});
         for (int nb : {4, 3, 2, 1}) kn.push_back({K_F32P, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
         const int N = n3 * n_mom;
@@ -1760,7 +1788,7 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
             const Geometry g = geometry(h, kernel, nb, n1, n2, n3, n_mom);
             if (g.lds <= 0) continue;
             const long padded = (long)g.n_nt * g.n_tile;  // columns, or momenta for the paper-order kernel
-            const bool by_mom = kernel == K_PORD || kernel == K_F64P || kernel == K_F32P;  // n-tiles of momenta
+            const bool by_mom = kernel == K_PORD || kernel == K_F64P || kernel == K_F32P || kernel == K_F64N;
             if (padded > 2L * std::max(by_mom ? n_mom : N, 32)) continue;  // mostly padding
             // Split counts as a tuned plan will run them (at least the
             // accuracy floor, in whole multiples of the wave-filling count).

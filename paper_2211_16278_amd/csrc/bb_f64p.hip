@@ -48,7 +48,7 @@ namespace f64p {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 512;     // eight waves
-constexpr int MT = 128;     // rows (pair, d3) per tile, 16 per wave
+constexpr int MT = 128;     // rows (pair, d3) per tile and row set, 16 per wave
 constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past any range: loads return zero
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
@@ -56,11 +56,20 @@ constexpr size_t LDS_LIMIT = 160 * 1024;
 // [3][s][b3] as (re, im) pairs, then the phase planes Re, Im, Re + Im [s][ps].
 constexpr int buffer_doubles(int s, int pairs, int b3, int ps) { return 2 * 3 * s * pairs + 2 * 3 * s * b3 + 3 * s * ps; }
 
-template <int CF, int B3>
+// Column fragments of W momenta: W = 16 on v_mfma_f64_16x16x4_f64 (plan
+// kernel 6), W = 4 on v_mfma_f64_4x4x4_f64 with its four blocks taking the
+// wave's 16 rows four at a time against one shared set of 4 columns (plan
+// kernel 8: few momenta pad to a multiple of 4, not of 16).  RS row sets of
+// 16 rows per wave: with RS = 2 (d3 blocks of 16) a wave holds the same 16
+// d3 values of two pairs, reads q3 once for both singlets and has two
+// independent singlet chains per k-step.
+template <int CF, int B3, int W = 16, int RS = 1>
 struct Shape {
-    static constexpr int NPAIR = MT / B3;                     // (d1,d2) pairs per tile
-    static constexpr int NC = 16 * CF;                        // momenta per tile
-    static constexpr int PS = (NC % 32 == 0) ? NC + 16 : NC;  // site stride of the phase planes (doubles)
+    static constexpr int NPAIR = RS * MT / B3;                // (d1,d2) pairs per tile
+    static constexpr int NC = W * CF;                         // momenta per tile
+    // Site stride of the phase planes (doubles): the two k-groups of a
+    // half-wave read disjoint banks.
+    static constexpr int PS = (W == 4) ? NC : (NC % 32 == 0) ? NC + 16 : NC;
     // Sites per chunk: 32 where two buffers of that size fit the LDS (one
     // barrier and one tile build per 32 sites), else 16.
     static constexpr int SITES =
@@ -74,10 +83,12 @@ struct Shape {
     static constexpr int BUF = POFF + 3 * SITES * PS;  // doubles
     static constexpr size_t lds = (size_t)2 * BUF * 8 + (size_t)MAX_L * 16;
     static_assert(BUF == buffer_doubles(SITES, NPAIR, B3, PS) && lds <= LDS_LIMIT, "two buffers fit the LDS");
-    static_assert(PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
+    static_assert(W == 4 || PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
+    static_assert(W == 16 || W == 4, "16- or 4-wide column fragments");
     static_assert(B3 % 16 == 0 && MT % B3 == 0, "a wave's 16 rows are d3 values of one pair");
+    static_assert(RS == 1 || (RS == 2 && B3 == 16), "two row sets: the same d3 block of two pairs");
     static_assert(ND % 64 == 0 && ND <= WG, "diquark items end on a wave boundary, one per thread");
-    static_assert(NQ % 256 == 0 && NP % 256 == 0, "q3 and phase items end on a wave boundary");
+    static_assert(NQ % 64 == 0 && NP % 64 == 0, "q3 and phase items end on a wave boundary");
 };
 
 template <bool C64>
@@ -111,10 +122,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int 
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, ns * 3 * n * ESZ, 0x00020000);
 }
 
-template <int CF, int B3, bool C64, bool Z>
+template <int CF, int B3, bool C64, bool Z, int W, int RS>
 __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 {
-    using Sh = Shape<CF, B3>;
+    static_assert(!(Z && W == 4), "the zero momentum on the vector unit saves a fragment of 16");
+    static_assert(!(Z && RS > 1), "one row set with the zero momentum");
+    using Sh = Shape<CF, B3, W, RS>;
+    using AccT = std::conditional_t<W == 16, d4_t, double>;
     constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF, SITES = Sh::SITES, KS = Sh::KS;
     constexpr int ESZ = In<C64>::ESZ;
     __shared__ __align__(16) double lds[2 * BUF];
@@ -246,15 +260,18 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
             }
         };
 
-        d4_t acc[3][CF];
+        AccT acc[RS][3][CF];
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
+        for (int r = 0; r < RS; ++r)
 #pragma unroll
-            for (int n = 0; n < CF; ++n) acc[q][n] = d4_t{0.0, 0.0, 0.0, 0.0};
-        // A[i][k] from lane i + 16 k: row 16 wave + i at site k of the k-step.
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int n = 0; n < CF; ++n) acc[r][q][n] = AccT{};
+        // A[i][k] from lane i + 16 k: row 16 (RS wave + r) + i of row set r
+        // at site k of the k-step (row sets r of a wave: the same d3 values).
         const int li = lane & 15, kg = lane >> 4;
-        const int rw = wave * 16 + li;
-        const int pair_l = rw / B3, d3_l = rw % B3;
+        const int rw = wave * RS * 16 + li;
+        const int pair_l = rw / B3, d3_l = rw % B3;  // row set r: pair pair_l + r
 
         // One chunk from buffer b: per k-step the singlets of this lane's
         // (row, site) from LDS, then 3 CF MFMAs; after the first k-step the
@@ -268,50 +285,66 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
             const double *base = lds + b * BUF;
             const double2 *Dl = reinterpret_cast<const double2 *>(base + Sh::DOFF) + kg * NPAIR + pair_l;
             const double2 *Ql = reinterpret_cast<const double2 *>(base + Sh::QOFF) + kg * B3 + d3_l;
-            const double *Pl = base + Sh::POFF + kg * PS + li;
-            double2 dv[2][3], qv[2][3];
+            // B[k][j]: lane j + 16 k (W = 16); lane j + 4 b + 16 k for every
+            // block b (W = 4: the blocks share the columns).
+            const double *Pl = base + Sh::POFF + kg * PS + (W == 16 ? li : (li & 3));
+            double2 dv[2][RS][3], qv[2][3];
             double br[2][CF], bi[2][CF], bs[2][CF];
             // Operands of k-step ks into register set slot: the diquark and
             // q3 of this lane's (row, site), the phases of its columns.
             auto read_s = [&](int ks, int slot) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    dv[slot][c] = Dl[(c * SITES + 4 * ks) * NPAIR];
+#pragma unroll
+                    for (int r = 0; r < RS; ++r) dv[slot][r][c] = Dl[(c * SITES + 4 * ks) * NPAIR + r];
                     qv[slot][c] = Ql[(c * SITES + 4 * ks) * B3];
                 }
 #pragma unroll
                 for (int n = 0; n < CF; ++n) {
-                    br[slot][n] = Pl[4 * ks * PS + n * 16];
-                    bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * 16];
-                    bs[slot][n] = Pl[(2 * SITES + 4 * ks) * PS + n * 16];
+                    br[slot][n] = Pl[4 * ks * PS + n * W];
+                    bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * W];
+                    bs[slot][n] = Pl[(2 * SITES + 4 * ks) * PS + n * W];
                 }
             };
             read_s(0, 0);
             fast::static_for<0, KS>([&](auto kk_) {
                 constexpr int ks = kk_, slot = ks & 1;
-                // Singlet S = sum_c D_c q3_c (complex), its Re + Im.
-                double sr = __builtin_fma(dv[slot][0].x, qv[slot][0].x, -(dv[slot][0].y * qv[slot][0].y));
-                double si = __builtin_fma(dv[slot][0].x, qv[slot][0].y, dv[slot][0].y * qv[slot][0].x);
+                // Singlet S = sum_c D_c q3_c (complex) of each row set, its Re + Im.
+                double sr[RS], si[RS], ss[RS];
 #pragma unroll
-                for (int c = 1; c < 3; ++c) {
-                    sr = __builtin_fma(dv[slot][c].x, qv[slot][c].x, sr);
-                    sr = __builtin_fma(-dv[slot][c].y, qv[slot][c].y, sr);
-                    si = __builtin_fma(dv[slot][c].x, qv[slot][c].y, si);
-                    si = __builtin_fma(dv[slot][c].y, qv[slot][c].x, si);
+                for (int r = 0; r < RS; ++r) {
+                    const double2 *dr = dv[slot][r];
+                    sr[r] = __builtin_fma(dr[0].x, qv[slot][0].x, -(dr[0].y * qv[slot][0].y));
+                    si[r] = __builtin_fma(dr[0].x, qv[slot][0].y, dr[0].y * qv[slot][0].x);
+#pragma unroll
+                    for (int c = 1; c < 3; ++c) {
+                        sr[r] = __builtin_fma(dr[c].x, qv[slot][c].x, sr[r]);
+                        sr[r] = __builtin_fma(-dr[c].y, qv[slot][c].y, sr[r]);
+                        si[r] = __builtin_fma(dr[c].x, qv[slot][c].y, si[r]);
+                        si[r] = __builtin_fma(dr[c].y, qv[slot][c].x, si[r]);
+                    }
+                    ss[r] = sr[r] + si[r];
                 }
-                const double ss = sr + si;
                 if constexpr (Z) {
-                    zr += sr;
-                    zi += si;
+                    zr += sr[0];
+                    zi += si[0];
                 }
                 // The next k-step's operands load under this one's MFMAs.
                 if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
 #pragma unroll
-                for (int n = 0; n < CF; ++n) {
-                    acc[0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ss, bs[slot][n], acc[0][n], 0, 0, 0);
-                    acc[1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(sr, br[slot][n], acc[1][n], 0, 0, 0);
-                    acc[2][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(si, bi[slot][n], acc[2][n], 0, 0, 0);
-                }
+                for (int r = 0; r < RS; ++r)
+#pragma unroll
+                    for (int n = 0; n < CF; ++n) {
+                        if constexpr (W == 16) {
+                            acc[r][0][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ss[r], bs[slot][n], acc[r][0][n], 0, 0, 0);
+                            acc[r][1][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(sr[r], br[slot][n], acc[r][1][n], 0, 0, 0);
+                            acc[r][2][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(si[r], bi[slot][n], acc[r][2][n], 0, 0, 0);
+                        } else {
+                            acc[r][0][n] = __builtin_amdgcn_mfma_f64_4x4x4f64(ss[r], bs[slot][n], acc[r][0][n], 0, 0, 0);
+                            acc[r][1][n] = __builtin_amdgcn_mfma_f64_4x4x4f64(sr[r], br[slot][n], acc[r][1][n], 0, 0, 0);
+                            acc[r][2][n] = __builtin_amdgcn_mfma_f64_4x4x4f64(si[r], bi[slot][n], acc[r][2][n], 0, 0, 0);
+                        }
+                    }
                 if constexpr (ks == 0) {
                     build(b ^ 1);
                     issue(ci_next);  // past the split the loads are out of range (zeros)
@@ -336,28 +369,42 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
             zi += __shfl_xor(zi, 32);
         }
 
-        // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  Accumulator register
-        // e of a 16x16 f64 fragment holds row 4 e + lane / 16, column lane % 16.
+        // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  W = 16: accumulator
+        // register e of a fragment holds row 4 e + lane / 16, column
+        // lane % 16.  W = 4: the lane's one value is block b = (lane / 4) % 4,
+        // row i = lane / 16 of it (wave row 4 b + i), column lane % 4.
         with_put_mode(bd, tl.w, [&](auto mode) {
 #pragma unroll
-            for (int n = 0; n < CF; ++n) {
-                const int col = p0 + n * 16 + li;
-                if (col >= n_col) continue;
-                const int p = col + (Z && col >= ps ? 1 : 0);
+            for (int rs = 0; rs < RS; ++rs)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int r = wave * 16 + 4 * e + kg;
-                    const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
-                    if (mo >= M12 || d3 >= bd.n3) continue;
-                    const double p1 = acc[0][n][e], p2 = acc[1][n][e], p3 = acc[2][n][e];
-                    const double re = p2 - p3, im = (p1 - p2) - p3;
-                    const int nu = p * bd.n3 + d3;
-                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 0, re);
-                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 1, im);
+                for (int n = 0; n < CF; ++n) {
+                    const int col = p0 + n * W + (W == 16 ? li : (lane & 3));
+                    if (col >= n_col) continue;
+                    const int p = col + (Z && col >= ps ? 1 : 0);
+                    constexpr int NE = W == 16 ? 4 : 1;
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) {
+                        const int r = (wave * RS + rs) * 16 + (W == 16 ? 4 * e + kg : 4 * ((lane >> 2) & 3) + kg);
+                        const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
+                        if (mo >= M12 || d3 >= bd.n3) continue;
+                        double p1, p2, p3;
+                        if constexpr (W == 16) {
+                            p1 = acc[rs][0][n][e];
+                            p2 = acc[rs][1][n][e];
+                            p3 = acc[rs][2][n][e];
+                        } else {
+                            p1 = acc[rs][0][n];
+                            p2 = acc[rs][1][n];
+                            p3 = acc[rs][2][n];
+                        }
+                        const double re = p2 - p3, im = (p1 - p2) - p3;
+                        const int nu = p * bd.n3 + d3;
+                        put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 0, re);
+                        put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, p, d3, 1, im);
+                    }
                 }
-            }
             if (Z && zsum && kg == 0) {
-                const int mo = m12_0 + pair_l, d3 = d3_0 + d3_l;
+                const int mo = m12_0 + pair_l, d3 = d3_0 + d3_l;  // one row set
                 if (mo < M12 && d3 < bd.n3) {
                     const int nu = ps * bd.n3 + d3;
                     put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, ps, d3, 0, (double)zr);
@@ -388,24 +435,41 @@ template <int CF, int B3, bool C64>
 hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
 {
     if (a.p_skip >= 0)
-        contract<CF, B3, C64, true><<<dim3(grid), dim3(WG), 0, st>>>(a);
+        contract<CF, B3, C64, true, 16, 1><<<dim3(grid), dim3(WG), 0, st>>>(a);
     else
-        contract<CF, B3, C64, false><<<dim3(grid), dim3(WG), 0, st>>>(a);
+        contract<CF, B3, C64, false, 16, 1><<<dim3(grid), dim3(WG), 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <int CF, int B3, bool C64>
+hipError_t run_narrow(const GemmArgs &a, int grid, hipStream_t st)
+{
+    if (a.p_skip >= 0) return hipErrorInvalidValue;  // a fragment of 4 gains nothing from it
+    contract<CF, B3, C64, false, 4, F64N_ROW_SETS><<<dim3(grid), dim3(WG), 0, st>>>(a);
     return hipGetLastError();
 }
 
 }  // namespace f64p
 
-int f64p_lds_bytes(int cf, int b3)
+int f64p_lds_bytes(int cf, int b3, int w)
 {
+#define BBQ_SIZE(CF_, B3_, W_) \
+    if (cf == CF_ && b3 == B3_ && w == W_) return (int)f64p::Shape<CF_, B3_, W_>::lds;
+    BBQ_SIZE(1, 16, 16) BBQ_SIZE(2, 16, 16) BBQ_SIZE(3, 16, 16) BBQ_SIZE(1, 32, 16) BBQ_SIZE(2, 32, 16)
+    BBQ_SIZE(3, 32, 16)
+#undef BBQ_SIZE
 #define BBQ_SIZE(CF_, B3_) \
-    if (cf == CF_ && b3 == B3_) return (int)f64p::Shape<CF_, B3_>::lds;
-    BBQ_SIZE(1, 16) BBQ_SIZE(2, 16) BBQ_SIZE(3, 16) BBQ_SIZE(1, 32) BBQ_SIZE(2, 32) BBQ_SIZE(3, 32)
+    if (cf == CF_ && b3 == B3_ && w == 4) return (int)f64p::Shape<CF_, B3_, 4, F64N_ROW_SETS>::lds;
+    BBQ_SIZE(1, 16) BBQ_SIZE(2, 16) BBQ_SIZE(3, 16) BBQ_SIZE(4, 16)
 #undef BBQ_SIZE
     return -1;
 }
 
-int f64p_pairs(int b3) { return b3 == 16 || b3 == 32 ? f64p::MT / b3 : -1; }
+int f64p_pairs(int b3, int w)
+{
+    if (b3 != 16 && (b3 != 32 || w == 4)) return -1;
+    return (w == 4 ? F64N_ROW_SETS : 1) * f64p::MT / b3;
+}
 
 hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st)
 {
@@ -413,6 +477,16 @@ hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hip
     if (cf == CF_ && b3 == B3_)     \
         return c64 ? f64p::run<CF_, B3_, true>(a, grid, st) : f64p::run<CF_, B3_, false>(a, grid, st);
     BBQ_CASE(1, 16) BBQ_CASE(2, 16) BBQ_CASE(3, 16) BBQ_CASE(1, 32) BBQ_CASE(2, 32) BBQ_CASE(3, 32)
+#undef BBQ_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_f64n(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st)
+{
+#define BBQ_CASE(CF_, B3_)          \
+    if (cf == CF_ && b3 == B3_)     \
+        return c64 ? f64p::run_narrow<CF_, B3_, true>(a, grid, st) : f64p::run_narrow<CF_, B3_, false>(a, grid, st);
+    BBQ_CASE(1, 16) BBQ_CASE(2, 16) BBQ_CASE(3, 16) BBQ_CASE(4, 16)
 #undef BBQ_CASE
     return hipErrorInvalidValue;
 }

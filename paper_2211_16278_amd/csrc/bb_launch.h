@@ -55,9 +55,14 @@ hipError_t launch_f64(int cf, int c64, const GemmArgs &a, int grid, hipStream_t 
 // 32, 16 cf momenta per tile (cf 1, 2 or 3).  Static LDS bytes and pairs per
 // tile (-1 when no instantiation), launch.  Its tiles use BlockDesc.n_mt2
 // for the number of d3 blocks.
-int f64p_lds_bytes(int cf, int b3);
-int f64p_pairs(int b3);
+// w: the momentum fragment width, 16 for kernel 6, 4 for kernel 8 (the same
+// design on v_mfma_f64_4x4x4_f64, 4 cf momenta per tile, cf 1 to 4, d3
+// blocks of 16, F64N_ROW_SETS row sets of 16 rows per wave).
+constexpr int F64N_ROW_SETS = 2;
+int f64p_lds_bytes(int cf, int b3, int w);
+int f64p_pairs(int b3, int w);
 hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
+hipError_t launch_f64n(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 // FP32 paper-order kernel (plan kernel 7): kernel 6's design in single
 // precision, the momentum projection on v_mfma_f32_16x16x4_f32 with four real
 // products, chunks of 32 sites; 16 cf momenta per tile (cf 1 to 4).  Static

@@ -146,7 +146,7 @@ def _plans(prec):
     out = []
     kernels = [(0, nb) for nb in ((1, 2, 4, 7, 14) if prec == "fp64" else (1, 2, 4, 7))]
     if prec == "fp64":
-        kernels += [(5, 2), (5, 4), (5, 7), (6, 1), (6, 2), (6, 3)]
+        kernels += [(5, 2), (5, 4), (5, 7), (6, 1), (6, 2), (6, 3), (8, 1), (8, 2), (8, 3), (8, 4)]
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
     if prec == "fp32":
@@ -245,11 +245,13 @@ def test_paper_order_kernel(torch_dev, L, ns, mset, dtype):
 @pytest.mark.parametrize("L,ns,mset,dtype", [(5, (19, 21, 33), "cube", "c128"), (4, (16, 17, 64), "shell4", "c128"),
                                              (5, (24, 9, 40), "shell4", "c64"), (4, (7, 5, 16), "axis", "c128"),
                                              (3, (9, 11, 50), "zero", "c128")])
-@pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4))])
+@pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4)),
+                                             ("fp64", 8, (1, 2, 3, 4))])
 def test_paper_order_fp64_fp32_kernels(torch_dev, prec, kernel, nbs, L, ns, mset, dtype):
-    """FP64 paper-order kernel 6 and FP32 kernel 7 (singlet on the vector
-    unit in the MFMA operand layout, momentum GEMM on the matrix cores) for
-    every momentum-fragment width and both d3 blocks, ragged pair, d3 and
+    """FP64 paper-order kernels 6 and 8 (fragments of 16 and of 4 momenta)
+    and FP32 kernel 7 (singlet on the vector unit in the MFMA operand
+    layout, momentum GEMM on the matrix cores) for every momentum-fragment
+    count and both d3 blocks, ragged pair, d3 and
     momentum edges and sites that end inside a chunk, against the oracle at
     the precision's tolerance; persistent and one-tile-per-workgroup
     schedules agree bitwise."""
@@ -280,12 +282,14 @@ def _zero_momentum_sets(L):
 
 
 @pytest.mark.parametrize("mset", ["mid-17", "wrapped-33", "twice-33", "none-17"])
-@pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4))])
+@pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4)),
+                                             ("fp64", 8, (1, 2, 3, 4))])
 def test_zero_momentum_on_vector_unit(torch_dev, prec, kernel, nbs, mset):
     """The zero momentum of a 16 k + 1 set summed on the vector unit (wherever
     it sits in the set, also as a multiple of L, once when repeated): every
     column width, split partials, both schedules bitwise equal, and the
-    oracle at the precision's tolerance."""
+    oracle at the precision's tolerance.  Kernel 8 (fragments of 4) keeps
+    the zero momentum a column of its own in the same sets."""
     L, ns = 5, (19, 21, 40)
     qs = fields(L, ns, workload=117)
     mom = _zero_momentum_sets(L)[mset]
@@ -447,15 +451,25 @@ def test_plan_validation_and_defaults(torch_dev):
             for kernel in (2, 4):
                 with pytest.raises(binding.BBlockError):
                     bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=7, splits=0, persistent=0, grid=0))
-            assert bb.get_plan(n, n, n, 7)["kernel"] == (5 if prec == "fp64" else 1)
-            if prec == "fp64":  # kernel 5 up to 8 momenta, the paper-order kernel 6 from 9
-                assert bb.get_plan(n, n, n, 8)["kernel"] == 5
-                assert bb.get_plan(n, n, n, 9)["kernel"] == 6
+            assert bb.get_plan(n, n, n, 7)["kernel"] == (8 if prec == "fp64" else 1)
+            if prec == "fp64":  # kernel 5 up to 4 momenta, kernel 8 from 5 to 12, kernel 6 beyond
+                assert bb.get_plan(n, n, n, 4)["kernel"] == 5
+                for nm in (5, 8, 9, 12):
+                    got = bb.get_plan(n, n, n, nm)
+                    assert (got["kernel"], got["nb"]) == (8, -(-nm // 4))
+                assert bb.get_plan(n, n, n, 13)["kernel"] == 6
                 assert bb.get_plan(n, n, 8, 33)["kernel"] == 5  # n3 below kernel 6's d3 block
+                assert bb.get_plan(n, n, 8, 7)["kernel"] == 5  # and kernel 8's
+                for nb in (1, 2, 3, 4):
+                    bb.set_plan(n, n, n, 7, dict(kernel=8, nb=nb, splits=0, persistent=0, grid=0))
+                    assert bb.get_plan(n, n, n, 7)["kernel"] == 8
+                with pytest.raises(binding.BBlockError):  # kernel 8 has 1 to 4 fragments of 4
+                    bb.set_plan(n, n, n, 7, dict(kernel=8, nb=5, splits=0, persistent=0, grid=0))
+                bb.set_plan(n, n, n, 7, None)
                 # 33 momenta with the zero one: 32 columns, two fragments.
                 assert (bb.get_plan(n, n, n, 33)["kernel"], bb.get_plan(n, n, n, 33)["nb"]) == (6, 2)
             if prec == "fp32":
-                for kernel, nb in ((5, 7), (6, 2)):  # kernels 5 and 6 are FP64 only
+                for kernel, nb in ((5, 7), (6, 2), (8, 2)):  # kernels 5, 6 and 8 are FP64 only
                     with pytest.raises(binding.BBlockError):
                         bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
                 assert bb.get_plan(n, n, n, 7)["kernel"] == 1  # the paper-order kernel 7 from 8 momenta
