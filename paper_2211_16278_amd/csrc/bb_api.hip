@@ -54,6 +54,9 @@ inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 
 struct Plan {
     int kernel = K_GENERIC, nb = 0, splits = 0, persistent = 0, grid = 0;
+    // A forced plan whose split count the planner fills in: recomputed at
+    // run time from the geometry of the batch's momentum set.
+    bool auto_splits = false;
 };
 
 using ShapeKey = std::array<int, 4>;  // n1, n2, n3, n_mom
@@ -289,13 +292,12 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.lds = lds;
     } else if (kernel == K_F64P) {
         // Rows (d1,d2,d3): a block of consecutive (d1,d2) pairs x a d3 block
-        // of 16 or 32; columns: 16 nb momenta.  The d3 block whose tiles run
-        // in chunks of 32 sites: 32 with one momentum fragment, else 16
-        // (measured at 32^3 and N_dil 32 or 64: 4 % faster at nb 1, 8 % at
-        // nb 2 and 3 than the other block).
-        g.b3 = n3 < 16 ? 0 : (nb == 1 && n3 >= 32 ? 32 : 16);
+        // of 16, two row sets per wave up to nb 2 (one wave reads q3 for
+        // two pairs: 4-7 % faster at 32^3, N_dil 32, 16 to 33 momenta, than
+        // one row set with the d3 block of 32 or 16); columns: 16 nb momenta.
+        g.b3 = n3 < 16 ? 0 : 16;
         if (h->prec != FP64 || g.b3 == 0) return g;
-        const int pairs = f64p_pairs(g.b3, 16), lds = f64p_lds_bytes(nb, g.b3, 16);
+        const int pairs = f64p_pairs(nb, g.b3, 16), lds = f64p_lds_bytes(nb, g.b3, 16);
         if (pairs <= 0 || lds <= 0) return g;
         g.m_tile = pairs * g.b3;
         g.n_tile = 16 * nb;
@@ -308,7 +310,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         // Kernel 6 with fragments of 4 momenta (nb 1 to 4), d3 blocks of 16.
         g.b3 = n3 < 16 ? 0 : 16;
         if (h->prec != FP64 || g.b3 == 0) return g;
-        const int pairs = f64p_pairs(g.b3, 4), lds = f64p_lds_bytes(nb, g.b3, 4);
+        const int pairs = f64p_pairs(nb, g.b3, 4), lds = f64p_lds_bytes(nb, g.b3, 4);
         if (pairs <= 0 || lds <= 0) return g;
         g.m_tile = pairs * g.b3;
         g.n_tile = 4 * nb;
@@ -935,7 +937,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
             const bool fixed = h->forced.count(k) && bp.plan.splits > 0;
             int S;
             if (fixed)
-                S = bp.plan.splits;
+                S = bp.plan.auto_splits ? single_splits(fill_splits(h, bp.g), s_min) : bp.plan.splits;
             else if (walk_of(bp))
                 S = s_min;
             else if (n_desc == 1 && bp.plan.splits > 0)
@@ -1686,6 +1688,7 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         return fail(h, BBLOCK_EINVAL, "splits=%d is below the accuracy floor of %d splits (at most %d sites per "
                     "split in FP32 accumulation)", plan->splits, s_min, ACCURACY_MAX_SITES);
     Plan p{plan->kernel, plan->nb, plan->splits, plan->persistent, plan->grid};
+    p.auto_splits = p.splits == 0;
     if (p.splits == 0) p.splits = single_splits(fill_splits(h, geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom)), s_min);
     h->forced[k] = p;
     return BBLOCK_OK;
@@ -1699,7 +1702,9 @@ bblock_status bblock_get_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
     // from one without only at 16 k + 1 momenta).
     const int saved_skip = h->p_skip;
     h->p_skip = n_mom > 1 && n_mom % 16 == 1 ? 0 : -1;
-    const Plan p = plan_for(h, n1, n2, n3, n_mom);
+    Plan p = plan_for(h, n1, n2, n3, n_mom);
+    if (p.auto_splits)
+        p.splits = single_splits(fill_splits(h, geometry(h, p.kernel, p.nb, n1, n2, n3, n_mom)), min_splits(h));
     h->p_skip = saved_skip;
     plan->nb = p.nb;
     plan->splits = h->forced.count(ShapeKey{n1, n2, n3, n_mom}) ? p.splits : single_splits(p.splits, min_splits(h));

@@ -126,7 +126,6 @@ template <int CF, int B3, bool C64, bool Z, int W, int RS>
 __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 {
     static_assert(!(Z && W == 4), "the zero momentum on the vector unit saves a fragment of 16");
-    static_assert(!(Z && RS > 1), "one row set with the zero momentum");
     using Sh = Shape<CF, B3, W, RS>;
     using AccT = std::conditional_t<W == 16, d4_t, double>;
     constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF, SITES = Sh::SITES, KS = Sh::KS;
@@ -277,7 +276,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         // (row, site) from LDS, then 3 CF MFMAs; after the first k-step the
         // next chunk's tiles go into buffer b ^ 1 and the loads of the chunk
         // after it are issued.
-        double zr = 0.0, zi = 0.0;  // this lane's (row, site) singlets summed: the zero momentum
+        double zr[RS] = {}, zi[RS] = {};  // this lane's (row, site) singlets summed: the zero momentum
         auto chunk = [&](int b, int ci_next) {
             asm volatile("" : "+s"(b));
             // Per-lane bases (one address each; the k-step, colour, plane and
@@ -326,8 +325,11 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                     ss[r] = sr[r] + si[r];
                 }
                 if constexpr (Z) {
-                    zr += sr[0];
-                    zi += si[0];
+#pragma unroll
+                    for (int r = 0; r < RS; ++r) {
+                        zr[r] += sr[r];
+                        zi[r] += si[r];
+                    }
                 }
                 // The next k-step's operands load under this one's MFMAs.
                 if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
@@ -363,10 +365,13 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         }
         if constexpr (Z) {
             // The four sites of a k-step sit in lanes l, l + 16, l + 32, l + 48.
-            zr += __shfl_xor(zr, 16);
-            zi += __shfl_xor(zi, 16);
-            zr += __shfl_xor(zr, 32);
-            zi += __shfl_xor(zi, 32);
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                zr[r] += __shfl_xor(zr[r], 16);
+                zi[r] += __shfl_xor(zi[r], 16);
+                zr[r] += __shfl_xor(zr[r], 32);
+                zi[r] += __shfl_xor(zi[r], 32);
+            }
         }
 
         // Epilogue: Re = P2 - P3, Im = P1 - P2 - P3.  W = 16: accumulator
@@ -404,11 +409,14 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                     }
                 }
             if (Z && zsum && kg == 0) {
-                const int mo = m12_0 + pair_l, d3 = d3_0 + d3_l;  // one row set
-                if (mo < M12 && d3 < bd.n3) {
-                    const int nu = ps * bd.n3 + d3;
-                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, ps, d3, 0, (double)zr);
-                    put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, ps, d3, 1, (double)zi);
+#pragma unroll
+                for (int r = 0; r < RS; ++r) {
+                    const int mo = m12_0 + pair_l + r, d3 = d3_0 + d3_l;
+                    if (mo < M12 && d3 < bd.n3) {
+                        const int nu = ps * bd.n3 + d3;
+                        put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, ps, d3, 0, zr[r]);
+                        put_result<decltype(mode)::value, double>(bd, tl.w, mo, nu, ps, d3, 1, zi[r]);
+                    }
                 }
             }
         });
@@ -431,13 +439,13 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
     }
 }
 
-template <int CF, int B3, bool C64>
+template <int CF, int B3, bool C64, int RS>
 hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
 {
     if (a.p_skip >= 0)
-        contract<CF, B3, C64, true, 16, 1><<<dim3(grid), dim3(WG), 0, st>>>(a);
+        contract<CF, B3, C64, true, 16, RS><<<dim3(grid), dim3(WG), 0, st>>>(a);
     else
-        contract<CF, B3, C64, false, 16, 1><<<dim3(grid), dim3(WG), 0, st>>>(a);
+        contract<CF, B3, C64, false, 16, RS><<<dim3(grid), dim3(WG), 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -453,30 +461,30 @@ hipError_t run_narrow(const GemmArgs &a, int grid, hipStream_t st)
 
 int f64p_lds_bytes(int cf, int b3, int w)
 {
-#define BBQ_SIZE(CF_, B3_, W_) \
-    if (cf == CF_ && b3 == B3_ && w == W_) return (int)f64p::Shape<CF_, B3_, W_>::lds;
-    BBQ_SIZE(1, 16, 16) BBQ_SIZE(2, 16, 16) BBQ_SIZE(3, 16, 16) BBQ_SIZE(1, 32, 16) BBQ_SIZE(2, 32, 16)
-    BBQ_SIZE(3, 32, 16)
-#undef BBQ_SIZE
-#define BBQ_SIZE(CF_, B3_) \
-    if (cf == CF_ && b3 == B3_ && w == 4) return (int)f64p::Shape<CF_, B3_, 4, F64N_ROW_SETS>::lds;
-    BBQ_SIZE(1, 16) BBQ_SIZE(2, 16) BBQ_SIZE(3, 16) BBQ_SIZE(4, 16)
+    if (b3 != 16) return -1;
+#define BBQ_SIZE(CF_, W_, RS_) \
+    if (cf == CF_ && w == W_) return (int)f64p::Shape<CF_, 16, W_, RS_>::lds;
+    BBQ_SIZE(1, 16, f64p_row_sets(1)) BBQ_SIZE(2, 16, f64p_row_sets(2)) BBQ_SIZE(3, 16, f64p_row_sets(3))
+    BBQ_SIZE(1, 4, F64N_ROW_SETS) BBQ_SIZE(2, 4, F64N_ROW_SETS) BBQ_SIZE(3, 4, F64N_ROW_SETS)
+    BBQ_SIZE(4, 4, F64N_ROW_SETS)
 #undef BBQ_SIZE
     return -1;
 }
 
-int f64p_pairs(int b3, int w)
+int f64p_pairs(int cf, int b3, int w)
 {
-    if (b3 != 16 && (b3 != 32 || w == 4)) return -1;
-    return (w == 4 ? F64N_ROW_SETS : 1) * f64p::MT / b3;
+    if (b3 != 16) return -1;
+    return (w == 4 ? F64N_ROW_SETS : f64p_row_sets(cf)) * f64p::MT / b3;
 }
 
 hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st)
 {
-#define BBQ_CASE(CF_, B3_)          \
-    if (cf == CF_ && b3 == B3_)     \
-        return c64 ? f64p::run<CF_, B3_, true>(a, grid, st) : f64p::run<CF_, B3_, false>(a, grid, st);
-    BBQ_CASE(1, 16) BBQ_CASE(2, 16) BBQ_CASE(3, 16) BBQ_CASE(1, 32) BBQ_CASE(2, 32) BBQ_CASE(3, 32)
+    if (b3 != 16) return hipErrorInvalidValue;
+#define BBQ_CASE(CF_)                                                                \
+    if (cf == CF_)                                                                   \
+        return c64 ? f64p::run<CF_, 16, true, f64p_row_sets(CF_)>(a, grid, st)      \
+                   : f64p::run<CF_, 16, false, f64p_row_sets(CF_)>(a, grid, st);
+    BBQ_CASE(1) BBQ_CASE(2) BBQ_CASE(3)
 #undef BBQ_CASE
     return hipErrorInvalidValue;
 }

@@ -49,18 +49,19 @@ hipError_t launch_pord(int nb, int b3, int c64, const GemmArgs &a, int grid, hip
 // launch.
 int f64_lds_bytes(int cf);
 hipError_t launch_f64(int cf, int c64, const GemmArgs &a, int grid, hipStream_t st);
-// FP64 paper-order kernel (plan kernel 6): the singlet on the vector unit in
-// the MFMA operand layout, the momentum projection as a three-product complex
-// GEMM on the matrix cores; 128 rows = (d1,d2) pairs x a d3 block of 16 or
-// 32, 16 cf momenta per tile (cf 1, 2 or 3).  Static LDS bytes and pairs per
-// tile (-1 when no instantiation), launch.  Its tiles use BlockDesc.n_mt2
-// for the number of d3 blocks.
-// w: the momentum fragment width, 16 for kernel 6, 4 for kernel 8 (the same
-// design on v_mfma_f64_4x4x4_f64, 4 cf momenta per tile, cf 1 to 4, d3
-// blocks of 16, F64N_ROW_SETS row sets of 16 rows per wave).
+// FP64 paper-order kernels 6 and 8: the singlet on the vector unit in the
+// MFMA operand layout, the momentum projection as a three-product complex
+// GEMM on the matrix cores; tiles of 128 rows ((d1,d2) pairs x a d3 block of
+// 16) per row set of 16 rows a wave holds, w cf momenta: kernel 6 w = 16 on
+// v_mfma_f64_16x16x4_f64 (cf 1 to 3, f64p_row_sets(cf) row sets), kernel 8
+// w = 4 on v_mfma_f64_4x4x4_f64 (cf 1 to 4, F64N_ROW_SETS row sets).  Static
+// LDS bytes and pairs per tile (-1 when no instantiation), launches.  Their
+// tiles use BlockDesc.n_mt2 for the number of d3 blocks.
 constexpr int F64N_ROW_SETS = 2;
+// Two row sets up to two fragments of 16 (at three they spill).
+constexpr int f64p_row_sets(int cf) { return cf <= 2 ? 2 : 1; }
 int f64p_lds_bytes(int cf, int b3, int w);
-int f64p_pairs(int b3, int w);
+int f64p_pairs(int cf, int b3, int w);
 hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 hipError_t launch_f64n(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 // FP32 paper-order kernel (plan kernel 7): kernel 6's design in single
