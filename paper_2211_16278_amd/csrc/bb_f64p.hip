@@ -52,9 +52,10 @@ constexpr int MT = 128;     // rows (pair, d3) per tile and row set, 16 per wave
 constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past any range: loads return zero
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
-// Doubles of one LDS buffer for chunks of s sites: D [3][s][pairs] and q3
-// [3][s][b3] as (re, im) pairs, then the phase planes Re, Im, Re + Im [s][ps].
-constexpr int buffer_doubles(int s, int pairs, int b3, int ps) { return 2 * 3 * s * pairs + 2 * 3 * s * b3 + 3 * s * ps; }
+// Doubles of one LDS buffer for chunks of s sites: D [3][s][dst] (dst: the
+// site stride, pairs + 1) and q3 [3][s][b3] as (re, im) pairs, then the
+// phase planes Re, Im, Re + Im [s][ps].
+constexpr int buffer_doubles(int s, int dst, int b3, int ps) { return 2 * 3 * s * dst + 2 * 3 * s * b3 + 3 * s * ps; }
 
 // Column fragments of W momenta: W = 16 on v_mfma_f64_16x16x4_f64 (plan
 // kernel 6), W = 4 on v_mfma_f64_4x4x4_f64 with its four blocks taking the
@@ -66,6 +67,10 @@ constexpr int buffer_doubles(int s, int pairs, int b3, int ps) { return 2 * 3 * 
 template <int CF, int B3, int W = 16, int RS = 1>
 struct Shape {
     static constexpr int NPAIR = RS * MT / B3;                // (d1,d2) pairs per tile
+    // Site stride of the diquark tile (double2): one past the pairs, so
+    // that the four k-groups' broadcast reads of one pair sit in different
+    // banks (at a multiple of 256 bytes they conflict four ways).
+    static constexpr int DST = NPAIR + 1;
     static constexpr int NC = W * CF;                         // momenta per tile
     // Site stride of the phase planes (doubles): the two k-groups of a
     // half-wave read disjoint banks.
@@ -73,16 +78,16 @@ struct Shape {
     // Sites per chunk: 32 where two buffers of that size fit the LDS (one
     // barrier and one tile build per 32 sites), else 16.
     static constexpr int SITES =
-        2 * (size_t)buffer_doubles(32, NPAIR, B3, PS) * 8 + (size_t)MAX_L * 16 <= LDS_LIMIT ? 32 : 16;
+        2 * (size_t)buffer_doubles(32, DST, B3, PS) * 8 + (size_t)MAX_L * 16 <= LDS_LIMIT ? 32 : 16;
     static constexpr int KS = SITES / 4;                      // k-steps per chunk
     static constexpr int ND = NPAIR * SITES;                  // diquark items per chunk
     static constexpr int NQ = SITES * 3 * B3;                 // q3 values per chunk
     static constexpr int NP = SITES * NC;                     // phases per chunk
     static constexpr int JQ = (NQ + WG - 1) / WG, JP = (NP + WG - 1) / WG;
-    static constexpr int DOFF = 0, QOFF = 2 * 3 * SITES * NPAIR, POFF = QOFF + 2 * 3 * SITES * B3;
+    static constexpr int DOFF = 0, QOFF = 2 * 3 * SITES * DST, POFF = QOFF + 2 * 3 * SITES * B3;
     static constexpr int BUF = POFF + 3 * SITES * PS;  // doubles
     static constexpr size_t lds = (size_t)2 * BUF * 8 + (size_t)MAX_L * 16;
-    static_assert(BUF == buffer_doubles(SITES, NPAIR, B3, PS) && lds <= LDS_LIMIT, "two buffers fit the LDS");
+    static_assert(BUF == buffer_doubles(SITES, DST, B3, PS) && lds <= LDS_LIMIT, "two buffers fit the LDS");
     static_assert(W == 4 || PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
     static_assert(W == 16 || W == 4, "16- or 4-wide column fragments");
     static_assert(B3 % 16 == 0 && MT % B3 == 0, "a wave's 16 rows are d3 values of one pair");
@@ -235,7 +240,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                     const double2 va = v[(c + 1) % 3], vb = v[(c + 2) % 3];
                     const double re = __builtin_fma(ua.x, vb.x, __builtin_fma(-ua.y, vb.y, __builtin_fma(-ub.x, va.x, ub.y * va.y)));
                     const double im = __builtin_fma(ua.x, vb.y, __builtin_fma(ua.y, vb.x, __builtin_fma(-ub.x, va.y, -(ub.y * va.x))));
-                    Dt[(c * SITES + ds) * NPAIR + dp] = make_double2(re, im);
+                    Dt[(c * SITES + ds) * Sh::DST + dp] = make_double2(re, im);
                 }
             }
 #pragma unroll
@@ -282,7 +287,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
             // Per-lane bases (one address each; the k-step, colour, plane and
             // fragment offsets are immediates).
             const double *base = lds + b * BUF;
-            const double2 *Dl = reinterpret_cast<const double2 *>(base + Sh::DOFF) + kg * NPAIR + pair_l;
+            const double2 *Dl = reinterpret_cast<const double2 *>(base + Sh::DOFF) + kg * Sh::DST + pair_l;
             const double2 *Ql = reinterpret_cast<const double2 *>(base + Sh::QOFF) + kg * B3 + d3_l;
             // B[k][j]: lane j + 16 k (W = 16); lane j + 4 b + 16 k for every
             // block b (W = 4: the blocks share the columns).
@@ -295,7 +300,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
 #pragma unroll
-                    for (int r = 0; r < RS; ++r) dv[slot][r][c] = Dl[(c * SITES + 4 * ks) * NPAIR + r];
+                    for (int r = 0; r < RS; ++r) dv[slot][r][c] = Dl[(c * SITES + 4 * ks) * Sh::DST + r];
                     qv[slot][c] = Ql[(c * SITES + 4 * ks) * B3];
                 }
 #pragma unroll
