@@ -1,4 +1,5 @@
-// FP64 paper-order contraction kernel of libbblock.so (gfx950, plan kernel 6).
+// FP64 paper-order contraction kernels of libbblock.so (gfx950, plan kernels
+// 6 and 8: momentum fragments of 16 and of 4).
 //
 // The block of the paper (Sec. 2, eq. (3)) in the order of Algorithm 1: per
 // site the singlet
@@ -17,13 +18,16 @@
 //   P1 = (Sr + Si)(er + ei),  P2 = Sr er,  P3 = Si ei,
 //   Re = P2 - P3,  Im = P1 - P2 - P3,  e = exp(-i p.x).
 //
-// Workgroup: eight wave64, two per SIMD.  Tile: 128 rows = NPAIR (d1,d2)
-// pairs x a block of B3 d3 values, 16 CF momenta, one site split.  Wave w
-// owns rows 16 w to 16 w + 15 (16 d3 values of one pair) and all momenta:
-// 3 x CF accumulator fragments of v_mfma_f64_16x16x4_f64.  The A operand of
-// a k-step (4 sites) is the singlet itself: lane l forms S of row
-// 16 w + l % 16 at site l / 16 from the diquark and q3 tiles in LDS, in
-// registers, and feeds it to the MFMAs.  Per chunk of 32 sites (16 where two
+// Workgroup: eight wave64, two per SIMD.  Tile: 128 RS rows = NPAIR (d1,d2)
+// pairs x a block of B3 d3 values, W CF momenta, one site split.  Wave w
+// owns RS row sets of 16 rows (the same 16 d3 values of RS pairs) and all
+// momenta: 3 x CF accumulator fragments per row set, of
+// v_mfma_f64_16x16x4_f64 (W = 16) or v_mfma_f64_4x4x4_f64 (W = 4: its four
+// blocks take the 16 rows four at a time against the same 4 momenta).  The
+// A operand of a k-step (4 sites) is the singlet itself: lane l forms S of
+// row l % 16 of each row set at site l / 16 from the diquark and q3 tiles in
+// LDS, in registers, and feeds it to the MFMAs (both MFMA forms take A[i][k]
+// from lane i + 16 k).  Per chunk of 32 sites (16 where two
 // buffers of 32 would not fit the LDS) the
 // workgroup builds the next chunk's tiles (the diquark of its pairs, q3 of
 // its d3 block, the phases of its momenta with their Re + Im plane) into the
