@@ -53,7 +53,7 @@ def kernel_name(path, plan, n2, n3, zero_off=False):
         return "bb::f32p::contract<%d, %d, false, %s>" % (plan["nb"], 32 if plan["nb"] > 2 and n3 >= 32 else 16, z)
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
-        return "bb::pord::contract<%d, %d, false>" % (plan["nb"], b3)
+        return "bb::pord::contract<%d, %d, false, %s>" % (plan["nb"], b3, z)
     if plan["kernel"] in (2, 4):
         b2 = 32 if n2 >= 32 else 16
         return "bb::w3::contract%s<%d, %d, false>" % ("8" if plan["kernel"] == 4 else "", plan["nb"], b2)
@@ -202,10 +202,10 @@ def device_fields(torch, dev, shape_list, dtype, seed):
 def zero_on_vector_unit(plan, mom, L):
     """Kernels 6 and 7 sum the zero momentum (mod L) of a set of 16 k + 1 > 1
     momenta on the vector unit and project only the other 16 k on the
-    matrix cores."""
+    matrix cores; kernel 3 with one fragment does so at 32 k + 1."""
     n = len(mom)
-    return (plan["kernel"] in (6, 7) and n > 1 and n % 16 == 1
-            and any(all(int(c) % L == 0 for c in m) for m in mom))
+    skips = (plan["kernel"] in (6, 7) and n % 16 == 1) or (plan["kernel"] == 3 and plan["nb"] == 1 and n % 32 == 1)
+    return n > 1 and skips and any(all(int(c) % L == 0 for c in m) for m in mom)
 
 
 def mfma_flops(plan, V, n1, n2, n3, n_mom, zero_off=False):

@@ -255,6 +255,10 @@ int zero_momentum_column(const int32_t *mom, int n_mom, int L)
     return -1;
 }
 
+// Kernel 3 sums the zero momentum on the vector unit for 32 k + 1 momenta at
+// one fragment (32 of the 33 of the paper's shell: one fragment, not two).
+bool pord_skips(bblock_t h, int nb, int n_mom) { return h->p_skip >= 0 && nb == 1 && n_mom % 32 == 1; }
+
 // Geometry of (kernel, nb) for one block shape; lds < 0 when unsupported.
 Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_mom)
 {
@@ -262,8 +266,10 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
     g.kernel = kernel;
     g.nb = nb;
     // Momentum columns of the paper-order FP64/FP32 kernels: all but a zero
-    // momentum they sum on the vector unit.
+    // momentum they sum on the vector unit (kernel 3 too, where that saves
+    // its second fragment of 32).
     const int mcols = n_mom - (h->p_skip >= 0 ? 1 : 0);
+    const int pcols = pord_skips(h, nb, n_mom) ? n_mom - 1 : n_mom;
     if (kernel == K_PIPELINED || is_w3(kernel)) {
         g.b2 = is_w3(kernel) ? w3_row_block(n2) : row_block(n2);
         g.b3 = is_w3(kernel) ? w3_col_block(n3) : pipelined_block(n3);
@@ -346,7 +352,7 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.bp = 32 * nb;
         g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
         g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
-        g.n_nt = cdiv(n_mom, g.n_tile);
+        g.n_nt = cdiv(pcols, g.n_tile);
         g.lds = 32768;  // static, well below the limit
     } else {
         const KernelGeom k = kernel_geom(h->prec, nb, n_mom, h->L);
@@ -395,7 +401,8 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
     // flops per momentum; measured at 32^3, N_dil 32 it is the cheaper one
     // from 17 momenta on).
     if (h->prec == BF16X3 && n_mom > 16) {
-        const Geometry g = geometry(h, K_PORD, n_mom > 32 ? 2 : 1, n1, n2, n3, n_mom);
+        const int cols = n_mom - (h->p_skip >= 0 && n_mom % 32 == 1 ? 1 : 0);
+        const Geometry g = geometry(h, K_PORD, cols > 32 ? 2 : 1, n1, n2, n3, n_mom);
         if (g.lds > 0) {
             p.kernel = K_PORD;
             p.nb = g.nb;
@@ -671,7 +678,9 @@ bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &s
         ga.roots = h->d_roots;
         ga.kidx = mem.kidx;
         ga.kstride = kstride_of(h);
-        ga.p_skip = sb.kernel == K_F64P || sb.kernel == K_F32P ? h->p_skip : -1;
+        ga.p_skip = sb.kernel == K_F64P || sb.kernel == K_F32P || (sb.kernel == K_PORD && pord_skips(h, sb.nb, n_mom))
+                        ? h->p_skip
+                        : -1;
         const int grid = sb.persistent ? std::min(sb.grid, sb.n_tiles) : sb.n_tiles;
         std::array<hipEvent_t, 2> ev{nullptr, nullptr};
         if (is_w3(sb.kernel)) {

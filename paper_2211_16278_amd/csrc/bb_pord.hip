@@ -52,9 +52,10 @@ struct Shape {
     static_assert(ND <= THREADS, "one diquark item per thread");
 };
 
-template <int NB, int B3, bool C64>
+template <int NB, int B3, bool C64, bool Z>
 __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
 {
+    static_assert(!Z || NB == 1, "the zero momentum off the matrix cores saves the second fragment");
     using Sh = Shape<NB, B3>;
     using IT = typename fast::InT<C64>::T;
     constexpr int F = Sh::F, PPF = Sh::PPF, NPAIR = Sh::NPAIR;
@@ -67,6 +68,9 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
     // Im-part lo) a lane needs for one site: the real output takes
     // (Re ph, -Im ph), the imaginary one (Im ph, Re ph).
     __shared__ __align__(16) uint32_t bops[MAX_L][4];
+    // Z: the zero momentum's site sums of each wave's rows, (Re, Im) per
+    // (fragment, row, k-group), accumulated per chunk.
+    __shared__ __align__(8) float2 zacc[Z ? 4 * Sh::F * 64 : 1];
     __shared__ int s_tile;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -143,11 +147,19 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
         // dword (rows padded to 4 bytes; momenta past the set read 0).
         const __amdgpu_buffer_rsrc_t rsk = __builtin_amdgcn_make_buffer_rsrc(
             (void *)a.kidx, (short)0, (int)((uint32_t)a.n_mom * (uint32_t)a.kstride), 0x00020000);
+        // Z: the columns hold every momentum but a.p_skip (the zero one).
+        const int ps = Z ? a.p_skip : -1, n_col = a.n_mom - (Z ? 1 : 0);
         const int pcol = p0 + r;
         uint32_t ko[NB];
 #pragma unroll
-        for (int n = 0; n < NB; ++n)
-            ko[n] = pcol + 32 * n < a.n_mom ? (uint32_t)((pcol + 32 * n) * a.kstride + xs + 4 * g) : 0x80000000u;
+        for (int n = 0; n < NB; ++n) {
+            const int col = pcol + 32 * n, pm = col + (Z && col >= ps ? 1 : 0);
+            ko[n] = col < n_col ? (uint32_t)(pm * a.kstride + xs + 4 * g) : 0x80000000u;
+        }
+        float2 *zw = zacc + (Z ? wave * F * 64 : 0);  // this wave's rows: [f][g][r]
+        if constexpr (Z) {
+            for (int i = lane; i < F * 64; i += 64) zw[i] = make_float2(0.f, 0.f);
+        }
 
         IT u[3], v[3], w[Sh::JQ];
         uint32_t kw[NB], kn[NB];
@@ -240,9 +252,21 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                 // buffered hi/lo), one slice per MFMA slot.
                 float2 dvf[12];
                 float sre = 0.f, sim = 0.f;
+                float zre = 0.f, zim = 0.f;  // Z: the fragment's singlets over the lane's 4 sites
                 uint32_t sh[2][4], sl[2][4];
                 auto singlet = [&](auto ff, auto ss) {
                     constexpr int f = ff, st = ss, B = f & 1;
+                    if constexpr (Z && st == 0) {
+                        zre = 0.f;
+                        zim = 0.f;
+                    }
+                    if constexpr (Z && st == 16) {
+                        // Each lane adds its k-group's sums into a slot of its
+                        // own (the lane's (f, g, r)): no two lanes meet.
+                        float2 *zp = &zw[f * 64 + lane];
+                        const float2 z = *zp;
+                        *zp = make_float2(z.x + zre, z.y + zim);
+                    }
                     if constexpr (st == 0) {
                         const int pi = (wave * F + f) * PPF + r / B3;  // pair of the lane's row
                         const float2 *D = &dtile[b][(pi * CHUNK_SITES + 4 * g) * 3];
@@ -258,6 +282,7 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                                 sre = __builtin_fmaf(-dvf[j * 3 + c].y, q[j][c].y, sre);
                             }
                             pin(sre);
+                            if constexpr (Z) zre += sre;
                         } else if constexpr (part == 1) {
                             sim = 0.f;
 #pragma unroll
@@ -266,6 +291,7 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                                 sim = __builtin_fmaf(dvf[j * 3 + c].y, q[j][c].x, sim);
                             }
                             pin(sim);
+                            if constexpr (Z) zim += sim;
                         } else if constexpr (part == 2) {
                             sh[B][j] = pack_bf16(sre, sim);
                             pin(sh[B][j]);
@@ -351,8 +377,8 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
             for (int f = 0; f < F; ++f)
 #pragma unroll
                 for (int n = 0; n < NB; ++n) {
-                    const int p = pcol + 32 * n;
-                    if (p >= a.n_mom) continue;
+                    const int col = pcol + 32 * n, p = col + (Z && col >= ps ? 1 : 0);
+                    if (col >= n_col) continue;
 #pragma unroll
                     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -365,13 +391,26 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                                                   (double)acc[f][n][s][e]);
                         }
                 }
+            if constexpr (Z) {
+                if (tl.z == 0) {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        const int pi = (wave * F + f) * PPF + r / B3;
+                        const int m = m12_0 + pi, d3 = d3_0 + r % B3;
+                        if (m >= M12 || d3 >= bd.n3) continue;
+                        const float2 z0 = zw[f * 64 + r], z1 = zw[f * 64 + 32 + r];
+                        const float v = g ? z0.y + z1.y : z0.x + z1.x;
+                        (void)unsafeAtomicAdd(bd.out + (((size_t)ps * M12 + m) * bd.n3 + d3) * 2 + g, (double)v);
+                    }
+                }
+            }
         } else {
 #pragma unroll
             for (int f = 0; f < F; ++f)
 #pragma unroll
                 for (int n = 0; n < NB; ++n) {
-                    const int p = pcol + 32 * n;
-                    if (p >= a.n_mom) continue;
+                    const int col = pcol + 32 * n, p = col + (Z && col >= ps ? 1 : 0);
+                    if (col >= n_col) continue;
 #pragma unroll
                     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -387,6 +426,23 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                                     acc[f][n][s][e];
                         }
                 }
+            if constexpr (Z) {
+                // The zero momentum's sums: lanes of k-group g write part g.
+                if (tl.z == 0) {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        const int pi = (wave * F + f) * PPF + r / B3;
+                        const int m = m12_0 + pi, d3 = d3_0 + r % B3;
+                        if (m >= M12 || d3 >= bd.n3) continue;
+                        const float2 z0 = zw[f * 64 + r], z1 = zw[f * 64 + 32 + r];
+                        const float v = g ? z0.y + z1.y : z0.x + z1.x;
+                        if (bd.direct || bd.walk)
+                            bd.out[(((size_t)ps * M12 + m) * bd.n3 + d3) * 2 + g] = (double)v;
+                        else
+                            reinterpret_cast<float *>(bd.ws)[(((size_t)tl.w * 2 + g) * M12 + m) * bd.N + ps * bd.n3 + d3] = v;
+                    }
+                }
+            }
         }
         if (bd.walk && tl.w + 1 < bd.S) {
             ++wsp;
@@ -409,7 +465,15 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
 template <int NB, int B3, bool C64>
 hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
 {
-    contract<NB, B3, C64><<<dim3(grid), dim3(THREADS), 0, st>>>(a);
+    if constexpr (NB == 1) {
+        if (a.p_skip >= 0) {
+            contract<NB, B3, C64, true><<<dim3(grid), dim3(THREADS), 0, st>>>(a);
+            return hipGetLastError();
+        }
+    } else if (a.p_skip >= 0) {
+        return hipErrorInvalidValue;
+    }
+    contract<NB, B3, C64, false><<<dim3(grid), dim3(THREADS), 0, st>>>(a);
     return hipGetLastError();
 }
 

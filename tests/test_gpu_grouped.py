@@ -102,8 +102,8 @@ def test_walking_tiles_bitwise_equal_to_split_reduction(torch_dev, prec, kernel,
     assert err_max(b[2], ref) < TOL[prec]
 
 
-@pytest.mark.parametrize("prec,kernel", (("fp64", 6), ("fp32", 7)))
-def test_walking_tiles_zero_momentum_on_vector_unit(torch_dev, prec, kernel):
+@pytest.mark.parametrize("prec,kernel,nb", (("fp64", 6, 2), ("fp32", 7, 2), ("bf16x3", 3, 1)))
+def test_walking_tiles_zero_momentum_on_vector_unit(torch_dev, prec, kernel, nb):
     """The paper-order FP64/FP32 kernels with the 33-momentum shell (the zero
     momentum summed on the vector unit): walking tiles equal the split-K run
     bitwise, and the oracle."""
@@ -111,7 +111,7 @@ def test_walking_tiles_zero_momentum_on_vector_unit(torch_dev, prec, kernel):
     shapes = [(24, 20, 32), (17, 33, 21)]
     trips = _fields(L, shapes, workload=163)
     mom = synth.momenta("shell4")
-    plans = {s: dict(kernel=kernel, nb=2, splits=2, persistent=0) for s in set(shapes)}
+    plans = {s: dict(kernel=kernel, nb=nb, splits=2, persistent=0) for s in set(shapes)}
     say("case walk vs split reduction, zero momentum on the vector unit", prec, kernel)
     a, _ = _run(torch_dev, prec, L, trips, mom, "0", plans)
     b, _ = _run(torch_dev, prec, L, trips, mom, "1", plans)
