@@ -134,7 +134,9 @@ typedef struct {
                             which one is zero mod L (the first such), sum
                             that one's sites (phase 1) on the vector unit
                             and project the other 16 k on the matrix cores:
-                            the paper's 33 momenta fill 2 fragments, not 3. */
+                            the paper's 33 momenta fill 2 fragments, not 3;
+                            kernel 3 with nb 1 does the same at 32 k + 1
+                            (33 momenta: one fragment of 32, not two). */
 } bblock_plan;
 
 /* Create a handle bound to the current HIP device (paper, Sec. 2 after
