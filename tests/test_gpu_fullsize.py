@@ -6,9 +6,10 @@ with the plans the library picks by default (the plans bench.py times).
 * large: 64^3 sites, N_dil 64, 33 momenta (the paper's test problem, Sec. 4)
   -- two entries in every group of 4 consecutive (d1, d2) pairs, one in each
   half of the d3 range, every momentum: every row tile of every kernel's
-  tiling (64- and 128-row linear tiles, 4 x 32 rectangles, 4- and 8-pair
-  tiles by d3 blocks) and every column tile is compared, in all three
-  precisions;
+  tiling (64- and 128-row linear tiles, 4 x 32 rectangles, 4-, 8- and
+  16-pair tiles by d3 blocks) and every column tile is compared, in all
+  three precisions (the paper-order kernels with the zero momentum of the
+  33 on the vector unit);
 * batched: one timeslice of the 48^3, N_dil 32, 27-momentum workload (its 4
   spin triples (s, s, s), complex64) in one grouped launch;
 * uneven: one timeslice of the 32^3 uneven workload -- 8 noise triples with
