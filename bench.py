@@ -44,9 +44,8 @@ def kernel_name(path, plan, n2, n3, zero_off=False):
     z = "true" if zero_off else "false"
     if plan["kernel"] == 5:
         return "bb::f64::contract<%d, false>" % plan["nb"]
-    if plan["kernel"] == 6:
-        return "bb::f64p::contract<%d, %d, false, %s, 16, 1>" % (plan["nb"], 32 if plan["nb"] == 1 and n3 >= 32 else 16,
-                                                                  z)
+    if plan["kernel"] == 6:  # d3 blocks of 16; two row sets up to two fragments
+        return "bb::f64p::contract<%d, 16, false, %s, 16, %d>" % (plan["nb"], z, 2 if plan["nb"] <= 2 else 1)
     if plan["kernel"] == 8:
         return "bb::f64p::contract<%d, 16, false, false, 4, 2>" % plan["nb"]
     if plan["kernel"] == 7:
