@@ -40,9 +40,9 @@ constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, 
               K_F64N = 8;
 // FP64 defaults by momentum count (at 32^3, N_dil 32, ms per block): kernel
 // 5 up to F64N_MIN_MOM (4 momenta: 1.28 against kernel 8's 1.41), kernel 8
-// (fragments of 4) up to F64P_MIN_MOM (5 to 8 momenta: 1.76 against kernel
-// 5's 2.02-2.16 and kernel 6's 2.51; 12: 2.11 against 2.52), kernel 6
-// above (16: 2.51 against 2.50; 27: 4.1 against kernel 5's 8.5).
+// (fragments of 4) up to F64P_MIN_MOM (5 to 8 momenta: 1.67-1.70 against
+// kernel 5's 2.02-2.52 and kernel 6's 2.26; 12: 2.05 against 2.26), kernel
+// 6 above (16: 2.26 against kernel 8's 2.50; 27: 3.75 against kernel 5's 8.5).
 constexpr int F64N_MIN_MOM = 4;
 constexpr int F64P_MIN_MOM = 12;
 // FP32 momenta above which the paper-order kernel 7 is the default (at 32^3,
