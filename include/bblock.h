@@ -88,7 +88,7 @@ typedef struct {
     int32_t kernel;      /* 0: generic tiles (any shape, every precision);
                             1: pipelined rectangular tiles (FP32 and BF16X3,
                                n2 >= 16 and n3 >= 16; nb 4 or 7; the FP32
-                               default up to 7 momenta);
+                               default up to 4 momenta);
                             2: as 1 with the phase-weighted q3 precomputed
                                into workspace images by a separate launch
                                (BF16X3 only; n2 >= 8,
@@ -122,9 +122,10 @@ typedef struct {
                                from 13 momenta).
                             7: kernel 6's order in FP32: the momentum
                                projection on the FP32 matrix cores with
-                               four real products (FP32 only, n3 >= 16; nb
-                               1 to 4 fragments of 16 momenta; the FP32
-                               default from 8 momenta).
+                               three real products at nb 1, four above
+                               (FP32 only, n3 >= 16; nb 1 to 4 fragments of
+                               16 momenta; the FP32 default from 5
+                               momenta).
                             8: kernel 6 with fragments of 4 momenta on the
                                FP64 matrix cores' 4x4x4 form and two row
                                sets of 16 per wave (FP64 only, n3 >= 16;

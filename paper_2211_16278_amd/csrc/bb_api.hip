@@ -46,9 +46,10 @@ constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, 
 constexpr int F64N_MIN_MOM = 4;
 constexpr int F64P_MIN_MOM = 12;
 // FP32 momenta above which the paper-order kernel 7 is the default (at 32^3,
-// N_dil 32, ms per block: kernel 1 1.56 against 1.59 at 7 momenta, 1.86
-// against 1.58 at 8, 5.9 against 2.5 at 27, 8.0 against 4.1 at 33).
-constexpr int F32P_MIN_MOM = 7;
+// N_dil 32, ms per block: kernel 1 0.93-0.94 against 1.34 up to 4 momenta,
+// 1.50-1.51 against 1.35 from 5 to 7; kernel 7 1.35-1.36 from 1 to 16
+// momenta, 2.5 at 27 against kernel 1's 5.9).
+constexpr int F32P_MIN_MOM = 4;
 // Kernel 2 and its eight-wave form 4 share geometry, images and workspace.
 inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 

@@ -51,10 +51,15 @@ struct Shape {
     static constexpr int NQ = SITES * 3 * B3;                 // q3 values per chunk
     static constexpr int NP = SITES * NC;                     // phases per chunk
     static constexpr int JQ = (NQ + WG - 1) / WG, JP = (NP + WG - 1) / WG;
+    // Complex products: three real products (Gauss, as in the FP64 kernels)
+    // at one momentum fragment, where the third accumulator and phase plane
+    // still leave two workgroups per CU; four (the real embedding) above.
+    static constexpr bool G3 = CF == 1;
+    static constexpr int NPL = G3 ? 3 : 2;                    // phase planes
     // One buffer (floats): D [3][SITES][NPAIR] and q3 [3][SITES][B3] as
-    // (re, im) pairs, then the phase planes Re, Im [SITES][PS].
+    // (re, im) pairs, then the phase planes Re, Im (and Re + Im) [SITES][PS].
     static constexpr int DOFF = 0, QOFF = 2 * 3 * SITES * NPAIR, POFF = QOFF + 2 * 3 * SITES * B3;
-    static constexpr int BUF = POFF + 2 * SITES * PS;
+    static constexpr int BUF = POFF + NPL * SITES * PS;
     static constexpr size_t lds = (size_t)2 * BUF * 4 + (size_t)MAX_L * 8;
     static_assert(PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
     static_assert(B3 % 16 == 0 && MT % B3 == 0, "a wave's 16 rows are d3 values of one pair");
@@ -204,7 +209,7 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
             float *base = lds + b * BUF;
             float2 *Dt = reinterpret_cast<float2 *>(base + Sh::DOFF);
             float2 *Qt = reinterpret_cast<float2 *>(base + Sh::QOFF);
-            float *Pr = base + Sh::POFF, *Pi = Pr + SITES * PS;
+            float *Pr = base + Sh::POFF, *Pi = Pr + SITES * PS, *Ps = Pi + SITES * PS;
             if (has_d) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -229,13 +234,15 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
                     const float2 e = roots[kk[j]];
                     Pr[s * PS + jc] = e.x;
                     Pi[s * PS + jc] = e.y;
+                    if constexpr (Sh::G3) Ps[s * PS + jc] = e.x + e.y;
                 }
             }
         };
 
-        f4_t acc[2][CF];
+        constexpr int NACC = Sh::G3 ? 3 : 2;  // (P1, P2, P3) or (Re, Im)
+        f4_t acc[NACC][CF];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < NACC; ++q)
 #pragma unroll
             for (int n = 0; n < CF; ++n) acc[q][n] = f4_t{0.f, 0.f, 0.f, 0.f};
         // A[i][k] from lane i + 16 k: row 16 wave + i at site k of the k-step.
@@ -255,7 +262,7 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
             const float2 *Ql = reinterpret_cast<const float2 *>(base + Sh::QOFF) + kg * B3 + d3_l;
             const float *Pl = base + Sh::POFF + kg * PS + li;
             float2 dv[2][3], qv[2][3];
-            float br[2][CF], bi[2][CF];
+            float br[2][CF], bi[2][CF], bs[2][CF];
             auto read_s = [&](int ks, int slot) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -266,6 +273,7 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
                 for (int n = 0; n < CF; ++n) {
                     br[slot][n] = Pl[4 * ks * PS + n * 16];
                     bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * 16];
+                    if constexpr (Sh::G3) bs[slot][n] = Pl[(2 * SITES + 4 * ks) * PS + n * 16];
                 }
             };
             read_s(0, 0);
@@ -281,7 +289,7 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
                     si = __builtin_fmaf(dv[slot][c].x, qv[slot][c].y, si);
                     si = __builtin_fmaf(dv[slot][c].y, qv[slot][c].x, si);
                 }
-                const float nsi = -si;
+                const float nsi = -si, ss = sr + si;
                 if constexpr (Z) {
                     zr += sr;
                     zi += si;
@@ -289,10 +297,16 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
                 if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
 #pragma unroll
                 for (int n = 0; n < CF; ++n) {
-                    acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[slot][n], acc[0][n], 0, 0, 0);
-                    acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, bi[slot][n], acc[1][n], 0, 0, 0);
-                    acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(nsi, bi[slot][n], acc[0][n], 0, 0, 0);
-                    acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, br[slot][n], acc[1][n], 0, 0, 0);
+                    if constexpr (Sh::G3) {
+                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(ss, bs[slot][n], acc[0][n], 0, 0, 0);
+                        acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[slot][n], acc[1][n], 0, 0, 0);
+                        acc[NACC - 1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, bi[slot][n], acc[NACC - 1][n], 0, 0, 0);
+                    } else {
+                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[slot][n], acc[0][n], 0, 0, 0);
+                        acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, bi[slot][n], acc[1][n], 0, 0, 0);
+                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(nsi, bi[slot][n], acc[0][n], 0, 0, 0);
+                        acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, br[slot][n], acc[1][n], 0, 0, 0);
+                    }
                 }
                 if constexpr (ks == 0) {
                     build(b ^ 1);
@@ -332,8 +346,14 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
                     const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
                     if (mo >= M12 || d3 >= bd.n3) continue;
                     const int nu = p * bd.n3 + d3;
-                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 0, (double)acc[0][n][e]);
-                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 1, (double)acc[1][n][e]);
+                    float re = acc[0][n][e], im = acc[1][n][e];
+                    if constexpr (Sh::G3) {  // Re = P2 - P3, Im = P1 - P2 - P3
+                        const float p3 = acc[NACC - 1][n][e];
+                        re = acc[1][n][e] - p3;
+                        im = (acc[0][n][e] - acc[1][n][e]) - p3;
+                    }
+                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 0, (double)re);
+                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 1, (double)im);
                 }
             }
             if (Z && zsum && kg == 0) {

@@ -452,7 +452,7 @@ def test_plan_validation_and_defaults(torch_dev):
             for kernel in (2, 4):
                 with pytest.raises(binding.BBlockError):
                     bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=7, splits=0, persistent=0, grid=0))
-            assert bb.get_plan(n, n, n, 7)["kernel"] == (8 if prec == "fp64" else 1)
+            assert bb.get_plan(n, n, n, 7)["kernel"] == (8 if prec == "fp64" else 7)
             if prec == "fp64":  # kernel 5 up to 4 momenta, kernel 8 from 5 to 12, kernel 6 beyond
                 assert bb.get_plan(n, n, n, 4)["kernel"] == 5
                 for nm in (5, 8, 9, 12):
@@ -473,8 +473,8 @@ def test_plan_validation_and_defaults(torch_dev):
                 for kernel, nb in ((5, 7), (6, 2), (8, 2)):  # kernels 5, 6 and 8 are FP64 only
                     with pytest.raises(binding.BBlockError):
                         bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
-                assert bb.get_plan(n, n, n, 7)["kernel"] == 1  # the paper-order kernel 7 from 8 momenta
-                assert bb.get_plan(n, n, n, 8)["kernel"] == 7
+                assert bb.get_plan(n, n, n, 4)["kernel"] == 1  # the paper-order kernel 7 from 5 momenta
+                assert bb.get_plan(n, n, n, 5)["kernel"] == 7
                 # 33 momenta with the zero one: 32 columns, two fragments.
                 assert (bb.get_plan(n, n, n, 33)["kernel"], bb.get_plan(n, n, n, 33)["nb"]) == (7, 2)
                 with pytest.raises(binding.BBlockError):  # kernel 7 has 1 to 4 momentum fragments
