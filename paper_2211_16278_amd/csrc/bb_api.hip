@@ -1212,6 +1212,15 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         });
         sb.tile_off = (int)tiles.size();
         sb.n_tiles = (int)items.size();
+        // One workgroup per tile launches n_tiles x block-size work-items,
+        // and a launch holds fewer than 2^32 of them: past 2^20 tiles the
+        // sub-batch runs persistent workgroups that take tiles from the
+        // counter (uneven-32 in FP32 with the paper-order kernel: 12.7
+        // million tiles of 512 threads).
+        if (!sb.persistent && sb.n_tiles > (1 << 20)) {
+            sb.persistent = 1;
+            sb.grid = h->num_cu * wg_per_cu(h, b0.g);
+        }
         // XCD-aware order.  The dispatcher hands workgroup g to XCD g mod
         // n_xcd, and each XCD has its own L2.  The tiles of one (block,
         // split) read the same q2/q3 site range, so they are dealt to one
