@@ -86,17 +86,33 @@ def test_noalloc_headline_size_fp64(torch_dev):
 
 
 def test_noalloc_refuses_what_does_not_fit(torch_dev):
-    """FP32 at 32^3, N_dil 64: at least 8 splits of 4096 x 448 complex FP32
-    partials (117 MB) exceed the 64 MiB array: BBLOCK_ENOMEM, nothing written."""
+    """FP32 at 32^3, N_dil 64 with the fused kernel 1 forced: its tiles do not
+    fill the device twice, so it keeps split partials, and at least 8 splits
+    of 4096 x 448 complex FP32 partials (117 MB) exceed the 64 MiB array:
+    BBLOCK_ENOMEM, nothing written.  The default plan (the paper-order kernel
+    7, enough tiles to walk) needs no partials and runs in the array, within
+    the FP32 contract of the allocating entry point's result."""
     torch, dev = torch_dev
     L, n = 32, 64
     say("case noalloc too large")
-    q = [torch.zeros((1, L ** 3, 3, n), dtype=torch.complex128, device=dev) for _ in range(3)]
+    g = torch.Generator(device=dev)
+    g.manual_seed(16278 * 1000 + 93)
+    q = [torch.view_as_complex(torch.empty((1, L ** 3, 3, n, 2), dtype=torch.float64, device=dev).normal_(generator=g))
+         for _ in range(3)]
     mom = synth.momenta("axis")
     out = torch.full((1, len(mom), n, n, n), 7.0, dtype=torch.complex128, device=dev)
     with binding.BaryonBlocks(L, prec="fp32", in_dtype="c128", max_ndil=64) as bb:
+        bb.set_plan(n, n, n, len(mom), dict(kernel=1, nb=7, splits=0, persistent=0, grid=0))
         with pytest.raises(binding.BBlockError) as ei:
             bb.compute_noalloc(*q, mom, out=out)
         assert ei.value.status == 2 and "static scratch" in str(ei.value)
         bb.sync()
-    assert torch.all(out == 7.0).item()
+        assert torch.all(out == 7.0).item()
+        bb.set_plan(n, n, n, len(mom), None)
+        say("  default plan", bb.get_plan(n, n, n, len(mom)))
+        bb.compute_noalloc(*q, mom, out=out)
+        ref = bb.compute(*q, mom)
+        bb.sync()
+    e = _rel(out.cpu().numpy(), ref.cpu().numpy())
+    say("  rel err against the allocating entry point %.3e" % e)
+    assert e < 1e-5
