@@ -115,9 +115,9 @@ def executed_flops(path, plan, V, n, n_mom, zero_off=False):
         w = 16 if k == 6 else 4
         padded = -(-m // (w * nb)) * w * nb
         return 6.0 * padded * vn3 + 23.0 * vn3 + 42.0 * V * n * n
-    if k == 7:  # three real products at one fragment, four above
+    if k == 7:  # three real products up to two fragments, four above
         padded = -(-m // (16 * nb)) * 16 * nb
-        return (6.0 if nb == 1 else 8.0) * padded * vn3
+        return (6.0 if nb <= 2 else 8.0) * padded * vn3
     return MFMA_PASSES[path] * 24.0 * n_mom * vn3
 
 
@@ -130,7 +130,7 @@ def flops_note(path, plan):
                 "momenta padded to fragments of %d) + 23 V n^3 + 42 V n^2 on the vector unit (singlet, diquark), "
                 "one FP64 issue rate" % (16 if k == 6 else 4))
     if k == 7:
-        return ("6 n_pad V n^3: the momentum projection with three real products" if plan["nb"] == 1 else
+        return ("6 n_pad V n^3: the momentum projection with three real products" if plan["nb"] <= 2 else
                 "8 n_pad V n^3: the momentum projection with four real products")
     return "%d x 24 n_mom V n^3" % MFMA_PASSES[path]
 
@@ -215,7 +215,7 @@ def mfma_flops(plan, V, n1, n2, n3, n_mom, zero_off=False):
     for kernels 3 and 7, 6 for FP64 kernels 6 and 8; their singlet runs on the
     vector unit), over n_mom - 1 momenta when the zero one is summed on the
     vector unit (zero_off)."""
-    per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 6.0 if plan["nb"] == 1 else 8.0, 8: 6.0}.get(plan["kernel"], 24.0)
+    per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 6.0 if plan["nb"] <= 2 else 8.0, 8: 6.0}.get(plan["kernel"], 24.0)
     return per * (n_mom - (1 if zero_off else 0)) * V * n1 * n2 * n3
 
 

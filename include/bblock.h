@@ -122,7 +122,7 @@ typedef struct {
                                from 13 momenta).
                             7: kernel 6's order in FP32: the momentum
                                projection on the FP32 matrix cores with
-                               three real products at nb 1, four above
+                               three real products up to nb 2, four above
                                (FP32 only, n3 >= 16; nb 1 to 4 fragments of
                                16 momenta; the FP32 default from 5
                                momenta).

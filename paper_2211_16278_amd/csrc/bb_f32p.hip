@@ -51,13 +51,14 @@ struct Shape {
     static constexpr int NQ = SITES * 3 * B3;                 // q3 values per chunk
     static constexpr int NP = SITES * NC;                     // phases per chunk
     static constexpr int JQ = (NQ + WG - 1) / WG, JP = (NP + WG - 1) / WG;
-    // Complex products: three real products (Gauss, as in the FP64 kernels)
-    // at one momentum fragment, where the third accumulator and phase plane
-    // still leave two workgroups per CU; four (the real embedding) above.
-    static constexpr bool G3 = CF == 1;
-    static constexpr int NPL = G3 ? 3 : 2;                    // phase planes
+    // Complex products: three real products (Gauss, as in the FP64 kernels,
+    // with the phase's Re + Im formed per k-step) up to two momentum
+    // fragments, where the third accumulator still leaves two workgroups per
+    // CU; four (the real embedding) above.
+    static constexpr bool G3 = CF <= 2;
+    static constexpr int NPL = 2;                             // phase planes
     // One buffer (floats): D [3][SITES][NPAIR] and q3 [3][SITES][B3] as
-    // (re, im) pairs, then the phase planes Re, Im (and Re + Im) [SITES][PS].
+    // (re, im) pairs, then the phase planes Re, Im [SITES][PS].
     static constexpr int DOFF = 0, QOFF = 2 * 3 * SITES * NPAIR, POFF = QOFF + 2 * 3 * SITES * B3;
     static constexpr int BUF = POFF + NPL * SITES * PS;
     static constexpr size_t lds = (size_t)2 * BUF * 4 + (size_t)MAX_L * 8;
@@ -104,10 +105,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int 
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, ns * 3 * n * ESZ, 0x00020000);
 }
 
-// Launch bounds: the Z kernels are held to the registers of WGS workgroups
-// per CU (2 WGS waves per SIMD); the others fit them unforced.
+// Launch bounds: held to the registers of WGS workgroups per CU (2 WGS
+// waves per SIMD).
 template <int CF, int B3, bool C64, bool Z>
-__global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3>::WGS)) contract(GemmArgs a)
+__global__ void __launch_bounds__(WG, (2 * Shape<CF, B3>::WGS)) contract(GemmArgs a)
 {
     using Sh = Shape<CF, B3>;
     constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF;
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
             float *base = lds + b * BUF;
             float2 *Dt = reinterpret_cast<float2 *>(base + Sh::DOFF);
             float2 *Qt = reinterpret_cast<float2 *>(base + Sh::QOFF);
-            float *Pr = base + Sh::POFF, *Pi = Pr + SITES * PS, *Ps = Pi + SITES * PS;
+            float *Pr = base + Sh::POFF, *Pi = Pr + SITES * PS;
             if (has_d) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -234,7 +235,6 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
                     const float2 e = roots[kk[j]];
                     Pr[s * PS + jc] = e.x;
                     Pi[s * PS + jc] = e.y;
-                    if constexpr (Sh::G3) Ps[s * PS + jc] = e.x + e.y;
                 }
             }
         };
@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
             const float2 *Ql = reinterpret_cast<const float2 *>(base + Sh::QOFF) + kg * B3 + d3_l;
             const float *Pl = base + Sh::POFF + kg * PS + li;
             float2 dv[2][3], qv[2][3];
-            float br[2][CF], bi[2][CF], bs[2][CF];
+            float br[2][CF], bi[2][CF];
             auto read_s = [&](int ks, int slot) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -273,7 +273,6 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
                 for (int n = 0; n < CF; ++n) {
                     br[slot][n] = Pl[4 * ks * PS + n * 16];
                     bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * 16];
-                    if constexpr (Sh::G3) bs[slot][n] = Pl[(2 * SITES + 4 * ks) * PS + n * 16];
                 }
             };
             read_s(0, 0);
@@ -298,7 +297,7 @@ __global__ void __launch_bounds__(WG, (Z ? 2 * Shape<CF, B3>::WGS : Shape<CF, B3
 #pragma unroll
                 for (int n = 0; n < CF; ++n) {
                     if constexpr (Sh::G3) {
-                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(ss, bs[slot][n], acc[0][n], 0, 0, 0);
+                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(ss, br[slot][n] + bi[slot][n], acc[0][n], 0, 0, 0);
                         acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[slot][n], acc[1][n], 0, 0, 0);
                         acc[NACC - 1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, bi[slot][n], acc[NACC - 1][n], 0, 0, 0);
                     } else {

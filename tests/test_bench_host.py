@@ -40,8 +40,9 @@ def test_executed_flops_per_kernel():
     assert bench.executed_flops("fp64", {"kernel": 6, "nb": 1}, V, n, 7) == 6.0 * 16 * vn3 + vec
     # 33 momenta with the zero one on the vector unit: 32 columns in 2 fragments of 16.
     assert bench.executed_flops("fp64", {"kernel": 6, "nb": 2}, V, n, 33, zero_off=True) == 6.0 * 32 * vn3 + vec
-    assert bench.executed_flops("fp32", {"kernel": 7, "nb": 2}, V, n, 33, zero_off=True) == 8.0 * 32 * vn3
-    # Kernel 7 at one fragment: three real products.
+    assert bench.executed_flops("fp32", {"kernel": 7, "nb": 2}, V, n, 33, zero_off=True) == 6.0 * 32 * vn3
+    assert bench.executed_flops("fp32", {"kernel": 7, "nb": 3}, V, n, 33) == 8.0 * 48 * vn3
+    # Kernel 7 up to two fragments: three real products.
     assert bench.executed_flops("fp32", {"kernel": 7, "nb": 1}, V, n, 7) == 6.0 * 16 * vn3
 
 

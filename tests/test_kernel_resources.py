@@ -30,7 +30,7 @@ BUDGET = {
     "_ZN2bb4fast7bb_fastILi1": 160,  # FP32 kernel 1
     "_ZN2bb4pord8contract": 160,    # BF16X3 kernel 3 (its zero-momentum form: 132)
     "_ZN2bb4f64p8contract": 0,      # FP64 kernel 6
-    "_ZN2bb4f32p8contract": 16,     # FP32 kernel 7
+    "_ZN2bb4f32p8contract": 32,     # FP32 kernel 7 (two fragments in 128 VGPRs: 12-28)
 }
 
 
