@@ -5,9 +5,11 @@
 //   S[x; (d1,d2), d3] = sum_c D_c[x; d1,d2] q3_c[x; d3],  D_c = eps_abc q1_a q2_b,
 // formed per lane in the MFMA operand layout, then the momentum projection
 //   B[p][(d1,d2)][d3] = sum_x S[x; (d1,d2), d3] exp(-i p.x)
-// on v_mfma_f32_16x16x4_f32 with the real embedding (four real products:
-// Re += Sr er - Si ei, Im += Sr ei + Si er), FP32 accumulation over a site
-// split of at most 4096 sites, the splits summed in FP64.  As with FP64, the
+// on v_mfma_f32_16x16x4_f32 with three real products up to two momentum
+// fragments (P1 = (Sr + Si)(er + ei), P2 = Sr er, P3 = Si ei; Re = P2 - P3,
+// Im = P1 - P2 - P3) and the real embedding above (four: Re += Sr er -
+// Si ei, Im += Sr ei + Si er), FP32 accumulation over a site split of at
+// most 4096 sites, the splits summed in FP64.  As with FP64, the
 // counters show no co-execution of vector work with these MFMAs: the second
 // workgroup per CU of the narrow tiles is what covers the vector work's and
 // the LDS's latencies.
