@@ -303,10 +303,10 @@ def run_batch_workload(args, name):
             step = lambda: bb.compute_projected(descs, coefs, mom)  # noqa: E731
         else:
             step = lambda: bb.compute_batch(descs, mom)  # noqa: E731
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        with no_gc():
+        with no_gc():  # collected once, before the warmup (no idle pause before the timed steps)
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0 = time.perf_counter()
             e0.record(stream)
@@ -444,19 +444,19 @@ def run_mode_workload(args, name):
         # One triple per call, for comparison.
         B1 = torch.empty((len(mom), n_dil, n_dil, n_dil), dtype=torch.complex128, device=dev)
         single = lambda: bb.mode_contract(T, *[q[0] for q in Qs], out=B1)  # noqa: E731
-        for _ in range(args.warmup):
-            single()
-        torch.cuda.synchronize()
         with no_gc():
+            for _ in range(args.warmup):
+                single()
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(args.steps):
                 single()
             torch.cuda.synchronize()
             extra["single_triple_blocks_per_s"] = args.steps / (time.perf_counter() - t0)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    with no_gc():
+    with no_gc():  # collected once, before the warmup (no idle pause before the timed steps)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
@@ -712,10 +712,13 @@ def main() -> int:
         if args.no_graph:
             bb.set_graph(False)
         plan = bb.get_plan(n, n, n, n_mom)
-        for _ in range(args.warmup):
-            bb.compute(*tq, mom, out=out)
-        torch.cuda.synchronize()
+        # The collector runs once, before the warmup: a collection between
+        # the warmup and the timed steps leaves the GPU idle for tens of ms,
+        # and the first steps after such a pause run at lower clocks.
         with no_gc():
+            for _ in range(args.warmup):
+                bb.compute(*tq, mom, out=out)
+            torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0 = time.perf_counter()
             e0.record(stream)
@@ -724,9 +727,7 @@ def main() -> int:
             e1.record(stream)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1)
-        # Per-step durations: an event pair around every step of a second pass.
-        with no_gc():
+            # Per-step durations: an event pair around every step of a second pass.
             evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                    for _ in range(args.steps)]
             for a, b in evs:
@@ -734,6 +735,7 @@ def main() -> int:
                 bb.compute(*tq, mom, out=out)
                 b.record(stream)
             torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
         per_step = sorted(a.elapsed_time(b) for a, b in evs)
         # Per-kernel durations: HIP events around each launch on the library's stream.
         bb.profile(True)
