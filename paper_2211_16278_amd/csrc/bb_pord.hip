@@ -249,7 +249,9 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                 // hi/lo, in 17 steps: the 12 D reads, then per site the Re chain,
                 // the Im chain, the hi pack and the lo split.  Fragment 0's runs
                 // before its MFMAs, fragment f+1's between fragment f's (double-
-                // buffered hi/lo), one slice per MFMA slot.
+                // buffered hi/lo): the D reads alone after the first MFMA, so
+                // that their latency runs under the second, the 16 arithmetic
+                // steps spread over the five slots after it.
                 float2 dvf[12];
                 float sre = 0.f, sim = 0.f;
                 float zre = 0.f, zim = 0.f;  // Z: the fragment's singlets over the lane's 4 sites
@@ -311,13 +313,16 @@ __global__ void __launch_bounds__(THREADS, 2) contract(GemmArgs a)
                     // accumulator, the accumulators interleaved.
                     static_for<0, NSLOT>([&](auto kk) {
                         constexpr int k = kk, prod = k / (2 * NB), n = (k % (2 * NB)) / 2, sp = k % 2;
+                        // Steps of fragment f+1 after this MFMA: step 0 (the D
+                        // reads) after the first, steps 1..16 over the rest.
+                        constexpr int s_lo = k == 0 ? 0 : 1 + ((k - 1) * (NSTEP - 1) + NSLOT - 2) / (NSLOT - 1);
+                        constexpr int s_hi = 1 + (k * (NSTEP - 1) + NSLOT - 2) / (NSLOT - 1);
                         const bf8_t Bh = __builtin_bit_cast(bf8_t, bh[n][sp]), Bl = __builtin_bit_cast(bf8_t, bl[n][sp]);
                         acc[f][n][sp] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(prod == 0 ? Al : Ah, prod == 1 ? Bl : Bh,
                                                                                  acc[f][n][sp], 0, 0, 0);
                         __builtin_amdgcn_sched_barrier(0);
                         if constexpr (f + 1 < F)
-                            static_for<(k * NSTEP + NSLOT - 1) / NSLOT, ((k + 1) * NSTEP + NSLOT - 1) / NSLOT>(
-                                [&](auto ss) { singlet(std::integral_constant<int, f + 1>{}, ss); });
+                            static_for<s_lo, s_hi>([&](auto ss) { singlet(std::integral_constant<int, f + 1>{}, ss); });
                         __builtin_amdgcn_sched_barrier(0);
                     });
                 });
