@@ -49,7 +49,9 @@ def kernel_name(path, plan, n2, n3, zero_off=False):
     if plan["kernel"] == 8:
         return "bb::f64p::contract<%d, 16, false, false, 4, 2>" % plan["nb"]
     if plan["kernel"] == 7:
-        return "bb::f32p::contract<%d, %d, false, %s>" % (plan["nb"], 32 if plan["nb"] > 2 and n3 >= 32 else 16, z)
+        return "bb::f32p::contract<%d, %d, false, %s, 16>" % (plan["nb"], 32 if plan["nb"] > 2 and n3 >= 32 else 16, z)
+    if plan["kernel"] == 9:
+        return "bb::f32p::contract<%d, 16, false, false, 4>" % plan["nb"]
     if plan["kernel"] == 3:
         b3 = 32 if n3 >= 32 else 16
         return "bb::pord::contract<%d, %d, false, %s>" % (plan["nb"], b3, z)
@@ -99,8 +101,9 @@ def executed_flops(path, plan, V, n, n_mom, zero_off=False):
     three BF16 products of BF16x3; FP64 kernel 5 forms each complex product
     from three real products (6 real flops per complex multiply-add): 3/4 of
     F_gemm.  Paper-order kernels: the momentum projection on the matrix
-    cores (6 flops per padded momentum with three real products for FP64
-    kernels 6 and 8, 8 with four for FP32 kernel 7), plus for the FP64
+    cores (6 flops per padded momentum with three real products: FP64
+    kernels 6 and 8, FP32 kernels 7 and 9 up to two fragments; 8 with four
+    for FP32 above), plus for the FP64
     kernels their vector work, the diquark (42 V n^2) and the singlet with
     its Re + Im (23 V n^3): FP64 vector and matrix work share one 78.6
     TFLOP/s issue rate on gfx950 and never overlap, so both count against
@@ -115,8 +118,9 @@ def executed_flops(path, plan, V, n, n_mom, zero_off=False):
         w = 16 if k == 6 else 4
         padded = -(-m // (w * nb)) * w * nb
         return 6.0 * padded * vn3 + 23.0 * vn3 + 42.0 * V * n * n
-    if k == 7:  # three real products up to two fragments, four above
-        padded = -(-m // (16 * nb)) * 16 * nb
+    if k in (7, 9):  # three real products up to two fragments, four above
+        w = 16 if k == 7 else 4
+        padded = -(-m // (w * nb)) * w * nb
         return (6.0 if nb <= 2 else 8.0) * padded * vn3
     return MFMA_PASSES[path] * 24.0 * n_mom * vn3
 
@@ -129,9 +133,10 @@ def flops_note(path, plan):
         return ("6 n_pad V n^3 on the matrix cores (the momentum projection with three real products, n_pad the "
                 "momenta padded to fragments of %d) + 23 V n^3 + 42 V n^2 on the vector unit (singlet, diquark), "
                 "one FP64 issue rate" % (16 if k == 6 else 4))
-    if k == 7:
-        return ("6 n_pad V n^3: the momentum projection with three real products" if plan["nb"] <= 2 else
-                "8 n_pad V n^3: the momentum projection with four real products")
+    if k in (7, 9):
+        pad = "n_pad the momenta padded to fragments of %d" % (16 if k == 7 else 4)
+        return ("6 n_pad V n^3: the momentum projection with three real products, " + pad if plan["nb"] <= 2 else
+                "8 n_pad V n^3: the momentum projection with four real products, " + pad)
     return "%d x 24 n_mom V n^3" % MFMA_PASSES[path]
 
 
@@ -212,10 +217,12 @@ def mfma_flops(plan, V, n1, n2, n3, n_mom, zero_off=False):
     """Flops of one MFMA pass of the formulation a plan runs: the fused GEMM
     (24 n_mom V n1 n2 n3; 18 for FP64 kernel 5's three real products) or, for
     the paper-order kernels, only the momentum projection (8 n_mom V n1 n2 n3
-    for kernels 3 and 7, 6 for FP64 kernels 6 and 8; their singlet runs on the
+    for kernels 3, 7 and 9 (6 for 7 and 9 up to two fragments), 6 for FP64
+    kernels 6 and 8; their singlet runs on the
     vector unit), over n_mom - 1 momenta when the zero one is summed on the
     vector unit (zero_off)."""
-    per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 6.0 if plan["nb"] <= 2 else 8.0, 8: 6.0}.get(plan["kernel"], 24.0)
+    per = {3: 8.0, 5: 18.0, 6: 6.0, 7: 6.0 if plan["nb"] <= 2 else 8.0, 8: 6.0,
+           9: 6.0 if plan["nb"] <= 2 else 8.0}.get(plan["kernel"], 24.0)
     return per * (n_mom - (1 if zero_off else 0)) * V * n1 * n2 * n3
 
 

@@ -124,14 +124,21 @@ typedef struct {
                                projection on the FP32 matrix cores with
                                three real products up to nb 2, four above
                                (FP32 only, n3 >= 16; nb 1 to 4 fragments of
-                               16 momenta; the FP32 default from 5
+                               16 momenta; the FP32 default from 9
                                momenta).
                             8: kernel 6 with fragments of 4 momenta on the
                                FP64 matrix cores' 4x4x4 form and two row
                                sets of 16 per wave (FP64 only, n3 >= 16;
                                nb 1 to 4 fragments of 4; the FP64 default
                                from 5 to 12 momenta, kernel 5 up to 4).
-                            Kernels 6 and 7, given 16 k + 1 > 1 momenta of
+                            9: kernel 7 with fragments of 4 momenta on the
+                               FP32 matrix cores' 4x4x1 form of 16 blocks
+                               (FP32 only, n3 >= 16; nb 1 to 4 fragments
+                               of 4; the FP32 default from 5 to 8 momenta,
+                               kernel 1 up to 4).
+                            Kernels 6 and 7 (not 8 and 9, whose fragments
+                            of 4 keep every momentum a column), given
+                            16 k + 1 > 1 momenta of
                             which one is zero mod L (the first such), sum
                             that one's sites (phase 1) on the vector unit
                             and project the other 16 k on the matrix cores:

@@ -37,7 +37,7 @@ thread_local std::string g_create_error;
 constexpr int MAX_NDIL = 4096;
 constexpr int ACCURACY_MAX_SITES = 4096;  // FP32-accumulating paths: sites per split at most
 constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, K_F64 = 5, K_F64P = 6, K_F32P = 7,
-              K_F64N = 8;
+              K_F64N = 8, K_F32N = 9;
 // FP64 defaults by momentum count (at 32^3, N_dil 32, ms per block): kernel
 // 5 up to F64N_MIN_MOM (4 momenta: 1.28 against kernel 8's 1.41), kernel 8
 // (fragments of 4) up to F64P_MIN_MOM (5 to 8 momenta: 1.67-1.70 against
@@ -45,11 +45,14 @@ constexpr int K_GENERIC = 0, K_PIPELINED = 1, K_W3 = 2, K_PORD = 3, K_W3W8 = 4, 
 // 6 above (16: 2.26 against kernel 8's 2.50; 27: 3.75 against kernel 5's 8.5).
 constexpr int F64N_MIN_MOM = 4;
 constexpr int F64P_MIN_MOM = 12;
-// FP32 momenta above which the paper-order kernel 7 is the default (at 32^3,
-// N_dil 32, ms per block: kernel 1 0.93-0.94 against 1.34 up to 4 momenta,
-// 1.50-1.51 against 1.35 from 5 to 7; kernel 7 1.35-1.36 from 1 to 16
-// momenta, 2.5 at 27 against kernel 1's 5.9).
+// FP32 momenta above which the paper-order kernels are the default (at
+// 32^3, N_dil 32, ms per block: kernel 1 0.93-0.94 against 1.34 up to 4
+// momenta, 1.50-1.51 against 1.35 from 5 to 7; kernel 7 1.35-1.36 from 1 to
+// 16 momenta, 2.5 at 27 against kernel 1's 5.9), kernel 9 (fragments of 4)
+// up to F32N_MAX_MOM (5 to 8 momenta: 1.27-1.29 against kernel 7's
+// 1.32; 9 to 12: 1.86 against 1.32-1.34).
 constexpr int F32P_MIN_MOM = 4;
+constexpr int F32N_MAX_MOM = 8;
 // Kernel 2 and its eight-wave form 4 share geometry, images and workspace.
 inline bool is_w3(int kernel) { return kernel == K_W3 || kernel == K_W3W8; }
 
@@ -326,13 +329,26 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
         g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
         g.n_nt = cdiv(n_mom, g.n_tile);
         g.lds = lds;
+    } else if (kernel == K_F32N) {
+        // Kernel 7 with fragments of 4 momenta (nb 1 to 4), d3 blocks of 16.
+        g.b3 = n3 < 16 ? 0 : 16;
+        if (h->prec != FP32 || g.b3 == 0) return g;
+        const int pairs = f32p_pairs(g.b3), lds = f32p_lds_bytes(nb, g.b3, 4);
+        if (pairs <= 0 || lds <= 0) return g;
+        g.m_tile = pairs * g.b3;
+        g.n_tile = 4 * nb;
+        g.bp = 4 * nb;
+        g.n_mt2 = cdiv(n3, g.b3);  // d3 blocks
+        g.n_mt = cdiv(n1 * n2, pairs) * g.n_mt2;
+        g.n_nt = cdiv(n_mom, g.n_tile);
+        g.lds = lds;
     } else if (kernel == K_F32P) {
         // As kernel 6, in FP32, 16 nb momenta: d3 blocks of 16 up to two
         // momentum fragments (two workgroups then share a CU), else 32
         // (16 below 32).
         g.b3 = n3 < 16 ? 0 : (nb <= 2 || n3 < 32 ? 16 : 32);
         if (h->prec != FP32 || g.b3 == 0) return g;
-        const int pairs = f32p_pairs(g.b3), lds = f32p_lds_bytes(nb, g.b3);
+        const int pairs = f32p_pairs(g.b3), lds = f32p_lds_bytes(nb, g.b3, 16);
         if (pairs <= 0 || lds <= 0) return g;
         g.m_tile = pairs * g.b3;
         g.n_tile = 16 * nb;
@@ -375,7 +391,8 @@ Geometry geometry(bblock_t h, int kernel, int nb, int n1, int n2, int n3, int n_
 int wg_per_cu(bblock_t h, const Geometry &g)
 {
     if (g.kernel == K_PORD) return 2;
-    if (g.kernel == K_F32P) return f32p_wgs(g.nb, g.b3);
+    if (g.kernel == K_F32P) return f32p_wgs(g.nb, g.b3, 16);
+    if (g.kernel == K_F32N) return f32p_wgs(g.nb, g.b3, 4);
     if (g.kernel == K_GENERIC && h->prec == FP64 && g.nb <= 7 && 2 * g.lds <= h->lds_max) return 2;
     return 1;
 }
@@ -424,6 +441,16 @@ Plan default_plan(bblock_t h, int n1, int n2, int n3, int n_mom)
         const Geometry g = geometry(h, K_PORD, cols > 32 ? 2 : 1, n1, n2, n3, n_mom);
         if (g.lds > 0) {
             p.kernel = K_PORD;
+            p.nb = g.nb;
+            p.splits = fill_splits(h, g);
+            return p;
+        }
+    }
+    if (h->prec == FP32 && n_mom > F32P_MIN_MOM && n_mom <= F32N_MAX_MOM) {
+        // FP32 with a few momenta: kernel 9, fragments of 4.
+        const Geometry g = geometry(h, K_F32N, cdiv(n_mom, 4), n1, n2, n3, n_mom);
+        if (g.lds > 0) {
+            p.kernel = K_F32N;
             p.nb = g.nb;
             p.splits = fill_splits(h, g);
             return p;
@@ -737,6 +764,7 @@ bblock_status enqueue(bblock_t h, const Mem &mem, const std::vector<SubBatch> &s
                        : sb.kernel == K_F64P    ? launch_f64p(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_F64N    ? launch_f64n(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
                        : sb.kernel == K_F32P    ? launch_f32p(sb.nb, sb.b3, ga.in_c64, ga, grid, st)
+                       : sb.kernel == K_F32N    ? launch_f32n(sb.nb, ga.in_c64, ga, grid, st)
                                                 : launch_gemm(h->prec, sb.nb, ga, grid, st);
         if (e != hipSuccess) return hip_fail(h, e, "launch of the contraction kernel");
         if (h->profiling) {
@@ -1107,7 +1135,7 @@ bblock_status run_batch(bblock_t h, const bblock_desc *desc, int n_desc, const i
         sb.persistent = b0.plan.persistent;
         sb.grid = b0.plan.grid > 0 ? b0.plan.grid : h->num_cu;
         any_pipelined |= sb.kernel == K_PIPELINED || sb.kernel == K_PORD || sb.kernel == K_F64 || sb.kernel == K_F64P ||
-                         sb.kernel == K_F32P || sb.kernel == K_F64N;
+                         sb.kernel == K_F32P || sb.kernel == K_F64N || sb.kernel == K_F32N;
         size_t used = 0;
         long n_went = 0;
         const size_t u0 = u;
@@ -1709,7 +1737,8 @@ bblock_status bblock_set_plan(bblock_t h, int32_t n1, int32_t n2, int32_t n3, in
         return BBLOCK_OK;
     }
     if (plan->kernel != K_GENERIC && plan->kernel != K_PIPELINED && !is_w3(plan->kernel) && plan->kernel != K_PORD &&
-        plan->kernel != K_F64 && plan->kernel != K_F64P && plan->kernel != K_F32P && plan->kernel != K_F64N)
+        plan->kernel != K_F64 && plan->kernel != K_F64P && plan->kernel != K_F32P && plan->kernel != K_F64N &&
+        plan->kernel != K_F32N)
         return fail(h, BBLOCK_EINVAL, "unknown kernel %d", plan->kernel);
     if (plan->splits < 0 || plan->grid < 0 || (plan->persistent != 0 && plan->persistent != 1))
         return fail(h, BBLOCK_EINVAL, "bad plan fields");
@@ -1824,13 +1853,15 @@ bblock_status bblock_tune(bblock_t h, int32_t n1, int32_t n2, int32_t n3, int32_
         for (int nb : {3, 2, 1}) kn.push_back({K_F64P, nb});
         for (int nb : {4, 3, 2, 1}) kn.push_back({K_F64N, nb});
         for (int nb : {4, 3, 2, 1}) kn.push_back({K_F32P, nb});
+        for (int nb : {4, 3, 2, 1}) kn.push_back({K_F32N, nb});
         for (int i = 0; i < n_opts; ++i) kn.push_back({K_GENERIC, opts[i]});
         const int N = n3 * n_mom;
         for (auto [kernel, nb] : kn) {
             const Geometry g = geometry(h, kernel, nb, n1, n2, n3, n_mom);
             if (g.lds <= 0) continue;
             const long padded = (long)g.n_nt * g.n_tile;  // columns, or momenta for the paper-order kernel
-            const bool by_mom = kernel == K_PORD || kernel == K_F64P || kernel == K_F32P || kernel == K_F64N;
+            const bool by_mom = kernel == K_PORD || kernel == K_F64P || kernel == K_F32P || kernel == K_F64N ||
+                                kernel == K_F32N;
             if (padded > 2L * std::max(by_mom ? n_mom : N, 32)) continue;  // mostly padding
             // Split counts as a tuned plan will run them (at least the
             // accuracy floor, in whole multiples of the wave-filling count).

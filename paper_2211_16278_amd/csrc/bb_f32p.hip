@@ -44,11 +44,15 @@ constexpr int SITES = 32;     // sites per chunk
 constexpr int KS = SITES / 4; // k-steps per chunk
 constexpr uint32_t OOB = 0x80000000u;  // a buffer offset past any range: loads return zero
 
-template <int CF, int B3>
+// W: momenta per column fragment, 16 (v_mfma_f32_16x16x4_f32) or 4
+// (v_mfma_f32_4x4x1_16b_f32, plan kernel 9).
+template <int CF, int B3, int W = 16>
 struct Shape {
     static constexpr int NPAIR = MT / B3;                     // (d1,d2) pairs per tile
-    static constexpr int NC = 16 * CF;                        // momenta per tile
-    static constexpr int PS = (NC % 32 == 0) ? NC + 16 : NC;  // site stride of the phase planes (floats)
+    static constexpr int NC = W * CF;                         // momenta per tile
+    // Site stride of the phase planes (floats): the k-groups 0 and 1 of a
+    // half-wave read 16 floats apart modulo 32 banks.
+    static constexpr int PS = W == 4 ? 16 : (NC % 32 == 0) ? NC + 16 : NC;
     static constexpr int ND = NPAIR * SITES;                  // diquark items per chunk
     static constexpr int NQ = SITES * 3 * B3;                 // q3 values per chunk
     static constexpr int NP = SITES * NC;                     // phases per chunk
@@ -67,7 +71,8 @@ struct Shape {
     static_assert(PS % 32 == 16, "the two k-groups of a half-wave must read disjoint banks");
     static_assert(B3 % 16 == 0 && MT % B3 == 0, "a wave's 16 rows are d3 values of one pair");
     static_assert(ND % 64 == 0 && ND <= WG, "diquark items end on a wave boundary, one per thread");
-    static_assert(NQ % 256 == 0 && NP % 256 == 0, "q3 and phase items end on a wave boundary");
+    static_assert(NQ % 256 == 0 && NP % 64 == 0, "q3 and phase items end on a wave boundary");
+    static_assert(W == 16 || (W == 4 && B3 == 16), "fragments of 4 momenta with d3 blocks of 16");
     static_assert(lds <= 160 * 1024, "two buffers fit the LDS");
     // Workgroups per CU: two for the narrow tiles with d3 blocks of 16 (their
     // LDS and at most 128 VGPRs let both fit, and four waves per SIMD hide
@@ -107,12 +112,26 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const void *q, int 
     return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, ns * 3 * n * ESZ, 0x00020000);
 }
 
+// One MFMA of the projection: a 16 x 16 fragment over 4 sites (W = 16), or
+// 16 blocks of 4 x 4 over one site each (W = 4: block b holds rows
+// 4 (b % 4) .. 4 (b % 4) + 3 at site b / 4 of the k-step, the sites summed
+// across blocks in the epilogue).
+template <int W>
+__device__ __forceinline__ f4_t mfma(float a, float b, f4_t c)
+{
+    if constexpr (W == 16)
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
 // Launch bounds: held to the registers of WGS workgroups per CU (2 WGS
 // waves per SIMD).
-template <int CF, int B3, bool C64, bool Z>
-__global__ void __launch_bounds__(WG, (2 * Shape<CF, B3>::WGS)) contract(GemmArgs a)
+template <int CF, int B3, bool C64, bool Z, int W = 16>
+__global__ void __launch_bounds__(WG, (2 * Shape<CF, B3, W>::WGS)) contract(GemmArgs a)
 {
-    using Sh = Shape<CF, B3>;
+    static_assert(!Z || W == 16, "fragments of 4 keep the zero momentum a column");
+    using Sh = Shape<CF, B3, W>;
     constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF;
     constexpr int ESZ = In<C64>::ESZ;
     __shared__ __align__(16) float lds[2 * BUF];
@@ -262,7 +281,9 @@ __global__ void __launch_bounds__(WG, (2 * Shape<CF, B3>::WGS)) contract(GemmArg
             const float *base = lds + b * BUF;
             const float2 *Dl = reinterpret_cast<const float2 *>(base + Sh::DOFF) + kg * NPAIR + pair_l;
             const float2 *Ql = reinterpret_cast<const float2 *>(base + Sh::QOFF) + kg * B3 + d3_l;
-            const float *Pl = base + Sh::POFF + kg * PS + li;
+            // B[k][j] (W = 16) or B[b][0][j] (W = 4, j = lane % 4): the
+            // phase of column j at the lane's site.
+            const float *Pl = base + Sh::POFF + kg * PS + (W == 16 ? li : (lane & 3));
             float2 dv[2][3], qv[2][3];
             float br[2][CF], bi[2][CF];
             auto read_s = [&](int ks, int slot) {
@@ -273,8 +294,8 @@ __global__ void __launch_bounds__(WG, (2 * Shape<CF, B3>::WGS)) contract(GemmArg
                 }
 #pragma unroll
                 for (int n = 0; n < CF; ++n) {
-                    br[slot][n] = Pl[4 * ks * PS + n * 16];
-                    bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * 16];
+                    br[slot][n] = Pl[4 * ks * PS + n * W];
+                    bi[slot][n] = Pl[(SITES + 4 * ks) * PS + n * W];
                 }
             };
             read_s(0, 0);
@@ -299,14 +320,14 @@ __global__ void __launch_bounds__(WG, (2 * Shape<CF, B3>::WGS)) contract(GemmArg
 #pragma unroll
                 for (int n = 0; n < CF; ++n) {
                     if constexpr (Sh::G3) {
-                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(ss, br[slot][n] + bi[slot][n], acc[0][n], 0, 0, 0);
-                        acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[slot][n], acc[1][n], 0, 0, 0);
-                        acc[NACC - 1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, bi[slot][n], acc[NACC - 1][n], 0, 0, 0);
+                        acc[0][n] = mfma<W>(ss, br[slot][n] + bi[slot][n], acc[0][n]);
+                        acc[1][n] = mfma<W>(sr, br[slot][n], acc[1][n]);
+                        acc[NACC - 1][n] = mfma<W>(si, bi[slot][n], acc[NACC - 1][n]);
                     } else {
-                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[slot][n], acc[0][n], 0, 0, 0);
-                        acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, bi[slot][n], acc[1][n], 0, 0, 0);
-                        acc[0][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(nsi, bi[slot][n], acc[0][n], 0, 0, 0);
-                        acc[1][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, br[slot][n], acc[1][n], 0, 0, 0);
+                        acc[0][n] = mfma<W>(sr, br[slot][n], acc[0][n]);
+                        acc[1][n] = mfma<W>(sr, bi[slot][n], acc[1][n]);
+                        acc[0][n] = mfma<W>(nsi, bi[slot][n], acc[0][n]);
+                        acc[1][n] = mfma<W>(si, br[slot][n], acc[1][n]);
                     }
                 }
                 if constexpr (ks == 0) {
@@ -333,9 +354,52 @@ __global__ void __launch_bounds__(WG, (2 * Shape<CF, B3>::WGS)) contract(GemmArg
             zi += __shfl_xor(zi, 32);
         }
 
+        if constexpr (W == 4) {
+            // Block b = lane / 4 summed over the sites of its k-group only:
+            // add the four k-groups (lanes l, l ^ 16, l ^ 32, l ^ 48).
+#pragma unroll
+            for (int q = 0; q < NACC; ++q)
+#pragma unroll
+                for (int n = 0; n < CF; ++n)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        float x = acc[q][n][e];
+                        x += __shfl_xor(x, 16);
+                        x += __shfl_xor(x, 32);
+                        acc[q][n][e] = x;
+                    }
+        }
+
         // Epilogue.  Accumulator register e of a 16x16 f32 fragment holds
-        // row 4 (lane / 16) + e, column lane % 16.
+        // row 4 (lane / 16) + e, column lane % 16; of the 4 x 4 blocks (the
+        // k-groups added above), row 4 ((lane / 4) % 4) + e, column lane % 4:
+        // there k-group kg writes register kg.
         with_put_mode(bd, tl.w, [&](auto mode) {
+            if constexpr (W == 4) {
+#pragma unroll
+                for (int n = 0; n < CF; ++n) {
+                    const int col = p0 + n * 4 + (lane & 3);
+                    if (col >= n_col) continue;
+                    const int r = wave * 16 + 4 * ((lane >> 2) & 3) + kg;
+                    const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
+                    if (mo >= M12 || d3 >= bd.n3) continue;
+                    const int nu = col * bd.n3 + d3;
+                    float x[NACC];
+#pragma unroll
+                    for (int q = 0; q < NACC; ++q) {
+                        const f4_t v = acc[q][n];
+                        x[q] = kg == 0 ? v[0] : kg == 1 ? v[1] : kg == 2 ? v[2] : v[3];
+                    }
+                    float re = x[0], im = x[1];
+                    if constexpr (Sh::G3) {  // Re = P2 - P3, Im = P1 - P2 - P3
+                        re = x[1] - x[NACC - 1];
+                        im = (x[0] - x[1]) - x[NACC - 1];
+                    }
+                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, col, d3, 0, (double)re);
+                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, col, d3, 1, (double)im);
+                }
+                return;
+            }
 #pragma unroll
             for (int n = 0; n < CF; ++n) {
                 const int col = p0 + n * 16 + li;
@@ -395,26 +459,37 @@ hipError_t run(const GemmArgs &a, int grid, hipStream_t st)
     return hipGetLastError();
 }
 
+// Fragments of 4 momenta (plan kernel 9): every momentum is a column.
+template <int CF, bool C64>
+hipError_t run_narrow(const GemmArgs &a, int grid, hipStream_t st)
+{
+    if (a.p_skip >= 0) return hipErrorInvalidValue;
+    contract<CF, 16, C64, false, 4><<<dim3(grid), dim3(WG), 0, st>>>(a);
+    return hipGetLastError();
+}
+
 }  // namespace f32p
 
-int f32p_lds_bytes(int cf, int b3)
+int f32p_lds_bytes(int cf, int b3, int w)
 {
-#define BBR_SIZE(CF_, B3_) \
-    if (cf == CF_ && b3 == B3_) return (int)f32p::Shape<CF_, B3_>::lds;
-    BBR_SIZE(1, 16) BBR_SIZE(2, 16) BBR_SIZE(3, 16) BBR_SIZE(4, 16)
-    BBR_SIZE(1, 32) BBR_SIZE(2, 32) BBR_SIZE(3, 32) BBR_SIZE(4, 32)
+#define BBR_SIZE(CF_, B3_, W_) \
+    if (cf == CF_ && b3 == B3_ && w == W_) return (int)f32p::Shape<CF_, B3_, W_>::lds;
+    BBR_SIZE(1, 16, 16) BBR_SIZE(2, 16, 16) BBR_SIZE(3, 16, 16) BBR_SIZE(4, 16, 16)
+    BBR_SIZE(1, 32, 16) BBR_SIZE(2, 32, 16) BBR_SIZE(3, 32, 16) BBR_SIZE(4, 32, 16)
+    BBR_SIZE(1, 16, 4) BBR_SIZE(2, 16, 4) BBR_SIZE(3, 16, 4) BBR_SIZE(4, 16, 4)
 #undef BBR_SIZE
     return -1;
 }
 
 int f32p_pairs(int b3) { return b3 == 16 || b3 == 32 ? f32p::MT / b3 : -1; }
 
-int f32p_wgs(int cf, int b3)
+int f32p_wgs(int cf, int b3, int w)
 {
-#define BBR_WGS(CF_, B3_) \
-    if (cf == CF_ && b3 == B3_) return f32p::Shape<CF_, B3_>::WGS;
-    BBR_WGS(1, 16) BBR_WGS(2, 16) BBR_WGS(3, 16) BBR_WGS(4, 16)
-    BBR_WGS(1, 32) BBR_WGS(2, 32) BBR_WGS(3, 32) BBR_WGS(4, 32)
+#define BBR_WGS(CF_, B3_, W_) \
+    if (cf == CF_ && b3 == B3_ && w == W_) return f32p::Shape<CF_, B3_, W_>::WGS;
+    BBR_WGS(1, 16, 16) BBR_WGS(2, 16, 16) BBR_WGS(3, 16, 16) BBR_WGS(4, 16, 16)
+    BBR_WGS(1, 32, 16) BBR_WGS(2, 32, 16) BBR_WGS(3, 32, 16) BBR_WGS(4, 32, 16)
+    BBR_WGS(1, 16, 4) BBR_WGS(2, 16, 4) BBR_WGS(3, 16, 4) BBR_WGS(4, 16, 4)
 #undef BBR_WGS
     return 1;
 }
@@ -426,6 +501,15 @@ hipError_t launch_f32p(int cf, int b3, int c64, const GemmArgs &a, int grid, hip
         return c64 ? f32p::run<CF_, B3_, true>(a, grid, st) : f32p::run<CF_, B3_, false>(a, grid, st);
     BBR_CASE(1, 16) BBR_CASE(2, 16) BBR_CASE(3, 16) BBR_CASE(4, 16)
     BBR_CASE(1, 32) BBR_CASE(2, 32) BBR_CASE(3, 32) BBR_CASE(4, 32)
+#undef BBR_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_f32n(int cf, int c64, const GemmArgs &a, int grid, hipStream_t st)
+{
+#define BBR_CASE(CF_) \
+    if (cf == CF_) return c64 ? f32p::run_narrow<CF_, true>(a, grid, st) : f32p::run_narrow<CF_, false>(a, grid, st);
+    BBR_CASE(1) BBR_CASE(2) BBR_CASE(3) BBR_CASE(4)
 #undef BBR_CASE
     return hipErrorInvalidValue;
 }

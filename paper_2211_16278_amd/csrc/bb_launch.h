@@ -64,14 +64,17 @@ int f64p_lds_bytes(int cf, int b3, int w);
 int f64p_pairs(int cf, int b3, int w);
 hipError_t launch_f64p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
 hipError_t launch_f64n(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
-// FP32 paper-order kernel (plan kernel 7): kernel 6's design in single
-// precision, the momentum projection on v_mfma_f32_16x16x4_f32 with four real
-// products, chunks of 32 sites; 16 cf momenta per tile (cf 1 to 4).  Static
-// LDS bytes and pairs per tile (-1 when no instantiation), launch.
-int f32p_lds_bytes(int cf, int b3);
+// FP32 paper-order kernels (plan kernels 7 and 9): kernel 6's design in
+// single precision, the momentum projection on v_mfma_f32_16x16x4_f32
+// (kernel 7, 16 cf momenta per tile) or v_mfma_f32_4x4x1_16b_f32 (kernel 9,
+// 4 cf), three real products up to cf 2, else four, chunks of 32 sites
+// (cf 1 to 4).  Static LDS bytes and pairs per tile (-1 when no
+// instantiation), launch.
+int f32p_lds_bytes(int cf, int b3, int w);  // w: momenta per fragment, 16 (kernel 7) or 4 (kernel 9)
 int f32p_pairs(int b3);
-int f32p_wgs(int cf, int b3);  // workgroups of kernel 7 per CU
+int f32p_wgs(int cf, int b3, int w);  // workgroups of kernels 7 and 9 per CU
 hipError_t launch_f32p(int cf, int b3, int c64, const GemmArgs &a, int grid, hipStream_t st);
+hipError_t launch_f32n(int cf, int c64, const GemmArgs &a, int grid, hipStream_t st);  // kernel 9: d3 blocks of 16
 int zgemm_shape(int M, int N, int K, int batch);  // index of the wave layout a launch uses
 hipError_t launch_zgemm(const ZgemmArgs &a, hipStream_t st);
 hipError_t launch_reduce(int prec, const ReduceArgs &a, int max_mn, hipStream_t st);

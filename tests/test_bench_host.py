@@ -44,6 +44,9 @@ def test_executed_flops_per_kernel():
     assert bench.executed_flops("fp32", {"kernel": 7, "nb": 3}, V, n, 33) == 8.0 * 48 * vn3
     # Kernel 7 up to two fragments: three real products.
     assert bench.executed_flops("fp32", {"kernel": 7, "nb": 1}, V, n, 7) == 6.0 * 16 * vn3
+    # Kernel 9: 7 momenta pad to 8 in fragments of 4; four real products above two fragments.
+    assert bench.executed_flops("fp32", {"kernel": 9, "nb": 2}, V, n, 7) == 6.0 * 8 * vn3
+    assert bench.executed_flops("fp32", {"kernel": 9, "nb": 3}, V, n, 10) == 8.0 * 12 * vn3
 
 
 def test_zero_momentum_rule():
@@ -72,6 +75,9 @@ def test_kernel_names_match_the_profiled_instantiations():
     assert bench.kernel_name("bf16x3", {"kernel": 3, "nb": 1}, 64, 64, True) == "bb::pord::contract<1, 32, false, true>"
     assert bench.kernel_name("bf16x3", {"kernel": 4, "nb": 7}, 32, 32) == "bb::w3::contract8<7, 32, false>"
     assert bench.kernel_name("fp32", {"kernel": 1, "nb": 7}, 32, 32) == "bb::fast::bb_fast<1, 7, 32, 32, false>"
+    assert bench.kernel_name("fp32", {"kernel": 7, "nb": 1}, 32, 32) == "bb::f32p::contract<1, 16, false, false, 16>"
+    assert bench.kernel_name("fp32", {"kernel": 7, "nb": 3}, 64, 64, True) == "bb::f32p::contract<3, 32, false, true, 16>"
+    assert bench.kernel_name("fp32", {"kernel": 9, "nb": 2}, 32, 32) == "bb::f32p::contract<2, 16, false, false, 4>"
     for name in ("bb::f64p::contract<2, 16, false, false, 4, 2>", "bb::w3::contract8<7, 32, false>",
                  "bb::fast::bb_fast<1, 7, 32, 32, false>"):
         assert bench.sources_of(name)

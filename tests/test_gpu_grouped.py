@@ -81,7 +81,8 @@ def _fields(L, shapes, workload, dtype=np.complex128):
 
 CASES = [("fp32", 1, 7), ("fp32", 1, 4), ("bf16x3", 1, 7), ("bf16x3", 2, 7), ("bf16x3", 4, 5), ("bf16x3", 3, 1),
          ("bf16x3", 3, 2), ("fp32", 0, 4), ("bf16x3", 0, 2), ("fp64", 5, 7), ("fp64", 5, 2), ("fp64", 6, 2),
-         ("fp64", 6, 3), ("fp64", 0, 7), ("fp32", 7, 2), ("fp32", 7, 4), ("fp64", 8, 2), ("fp64", 8, 4)]
+         ("fp64", 6, 3), ("fp64", 0, 7), ("fp32", 7, 2), ("fp32", 7, 4), ("fp64", 8, 2), ("fp64", 8, 4),
+         ("fp32", 9, 2), ("fp32", 9, 4)]
 
 
 @pytest.mark.parametrize("prec,kernel,nb", CASES)

@@ -150,7 +150,7 @@ def _plans(prec):
     if prec != "fp64":
         kernels += [(1, 4), (1, 7)]
     if prec == "fp32":
-        kernels += [(7, 1), (7, 2), (7, 3), (7, 4)]
+        kernels += [(7, 1), (7, 2), (7, 3), (7, 4), (9, 1), (9, 2), (9, 3), (9, 4)]
     if prec == "bf16x3":
         kernels += [(2, 4), (2, 5), (2, 6), (2, 7), (3, 1), (3, 2), (4, 4), (4, 5), (4, 6), (4, 7)]
     for kernel, nb in kernels:
@@ -246,11 +246,12 @@ def test_paper_order_kernel(torch_dev, L, ns, mset, dtype):
                                              (5, (24, 9, 40), "shell4", "c64"), (4, (7, 5, 16), "axis", "c128"),
                                              (3, (9, 11, 50), "zero", "c128")])
 @pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4)),
-                                             ("fp64", 8, (1, 2, 3, 4))])
+                                             ("fp64", 8, (1, 2, 3, 4)), ("fp32", 9, (1, 2, 3, 4))])
 def test_paper_order_fp64_fp32_kernels(torch_dev, prec, kernel, nbs, L, ns, mset, dtype):
     """FP64 paper-order kernels 6 and 8 (fragments of 16 and of 4 momenta)
-    and FP32 kernel 7 (singlet on the vector unit in the MFMA operand
-    layout, momentum GEMM on the matrix cores) for every momentum-fragment
+    and FP32 kernels 7 and 9 (the same, in single precision; singlet on the
+    vector unit in the MFMA operand layout, momentum GEMM on the matrix
+    cores) for every momentum-fragment
     count and both d3 blocks, ragged pair, d3 and
     momentum edges and sites that end inside a chunk, against the oracle at
     the precision's tolerance; persistent and one-tile-per-workgroup
@@ -452,7 +453,7 @@ def test_plan_validation_and_defaults(torch_dev):
             for kernel in (2, 4):
                 with pytest.raises(binding.BBlockError):
                     bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=7, splits=0, persistent=0, grid=0))
-            assert bb.get_plan(n, n, n, 7)["kernel"] == (8 if prec == "fp64" else 7)
+            assert bb.get_plan(n, n, n, 7)["kernel"] == (8 if prec == "fp64" else 9)
             if prec == "fp64":  # kernel 5 up to 4 momenta, kernel 8 from 5 to 12, kernel 6 beyond
                 assert bb.get_plan(n, n, n, 4)["kernel"] == 5
                 for nm in (5, 8, 9, 12):
@@ -473,8 +474,15 @@ def test_plan_validation_and_defaults(torch_dev):
                 for kernel, nb in ((5, 7), (6, 2), (8, 2)):  # kernels 5, 6 and 8 are FP64 only
                     with pytest.raises(binding.BBlockError):
                         bb.set_plan(n, n, n, 7, dict(kernel=kernel, nb=nb, splits=0, persistent=0, grid=0))
-                assert bb.get_plan(n, n, n, 4)["kernel"] == 1  # the paper-order kernel 7 from 5 momenta
-                assert bb.get_plan(n, n, n, 5)["kernel"] == 7
+                # Kernel 1 up to 4 momenta, kernel 9 (fragments of 4) from 5 to 8, kernel 7 beyond.
+                assert bb.get_plan(n, n, n, 4)["kernel"] == 1
+                for nm in (5, 7, 8):
+                    got = bb.get_plan(n, n, n, nm)
+                    assert (got["kernel"], got["nb"]) == (9, -(-nm // 4))
+                assert bb.get_plan(n, n, n, 9)["kernel"] == 7
+                assert bb.get_plan(n, n, 8, 7)["kernel"] != 9  # n3 below kernel 9's d3 block
+                with pytest.raises(binding.BBlockError):  # kernel 9 has 1 to 4 fragments of 4
+                    bb.set_plan(n, n, n, 7, dict(kernel=9, nb=5, splits=0, persistent=0, grid=0))
                 # 33 momenta with the zero one: 32 columns, two fragments.
                 assert (bb.get_plan(n, n, n, 33)["kernel"], bb.get_plan(n, n, n, 33)["nb"]) == (7, 2)
                 with pytest.raises(binding.BBlockError):  # kernel 7 has 1 to 4 momentum fragments

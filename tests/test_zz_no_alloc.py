@@ -90,7 +90,7 @@ def test_noalloc_refuses_what_does_not_fit(torch_dev):
     fill the device twice, so it keeps split partials, and at least 8 splits
     of 4096 x 448 complex FP32 partials (117 MB) exceed the 64 MiB array:
     BBLOCK_ENOMEM, nothing written.  The default plan (the paper-order kernel
-    7, enough tiles to walk) needs no partials and runs in the array, within
+    9, enough tiles to walk) needs no partials and runs in the array, within
     the FP32 contract of the allocating entry point's result."""
     torch, dev = torch_dev
     L, n = 32, 64
