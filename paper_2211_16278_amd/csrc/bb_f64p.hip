@@ -139,6 +139,11 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
     using AccT = std::conditional_t<W == 16, d4_t, double>;
     constexpr int NPAIR = Sh::NPAIR, NC = Sh::NC, PS = Sh::PS, BUF = Sh::BUF, SITES = Sh::SITES, KS = Sh::KS;
     constexpr int ESZ = In<C64>::ESZ;
+    // Singlets one k-step ahead of the MFMAs that take them (the vector
+    // chain's latency then runs behind the previous k-step's MFMAs) where
+    // the extra singlet registers fit: fragments of 4, or one of 16; wider
+    // tiles of 16 would spill.
+    constexpr bool SKEW = W == 4 || CF == 1;
     __shared__ __align__(16) double lds[2 * BUF];
     __shared__ double2 roots[MAX_L];
     __shared__ int s_tile;
@@ -314,11 +319,10 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                     bs[slot][n] = Pl[(2 * SITES + 4 * ks) * PS + n * W];
                 }
             };
-            read_s(0, 0);
-            fast::static_for<0, KS>([&](auto kk_) {
-                constexpr int ks = kk_, slot = ks & 1;
-                // Singlet S = sum_c D_c q3_c (complex) of each row set, its Re + Im.
-                double sr[RS], si[RS], ss[RS];
+            double sr[RS], si[RS], ss[RS];
+            // Singlet S = sum_c D_c q3_c (complex) of each row set from
+            // register set slot, its Re + Im.
+            auto singlet = [&](int slot) {
 #pragma unroll
                 for (int r = 0; r < RS; ++r) {
                     const double2 *dr = dv[slot][r];
@@ -340,8 +344,9 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                         zi[r] += si[r];
                     }
                 }
-                // The next k-step's operands load under this one's MFMAs.
-                if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
+            };
+            // The momentum projection of the current singlets, phases from register set slot.
+            auto project = [&](int slot) {
 #pragma unroll
                 for (int r = 0; r < RS; ++r)
 #pragma unroll
@@ -356,6 +361,27 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                             acc[r][2][n] = __builtin_amdgcn_mfma_f64_4x4x4f64(si[r], bi[slot][n], acc[r][2][n], 0, 0, 0);
                         }
                     }
+            };
+            read_s(0, 0);
+            if constexpr (SKEW) {
+                if constexpr (KS > 1) read_s(1, 1);
+                singlet(0);
+            }
+            fast::static_for<0, KS>([&](auto kk_) {
+                constexpr int ks = kk_, slot = ks & 1;
+                if constexpr (SKEW) {
+                    // This k-step's MFMAs on the singlets formed in the last
+                    // one; the k-step after next loads into this one's
+                    // registers and the next singlet forms after the MFMAs.
+                    project(slot);
+                    if constexpr (ks + 2 < KS) read_s(ks + 2, slot);
+                    if constexpr (ks + 1 < KS) singlet(slot ^ 1);
+                } else {
+                    singlet(slot);
+                    // The next k-step's operands load under this one's MFMAs.
+                    if constexpr (ks + 1 < KS) read_s(ks + 1, slot ^ 1);
+                    project(slot);
+                }
                 if constexpr (ks == 0) {
                     build(b ^ 1);
                     issue(ci_next);  // past the split the loads are out of range (zeros)
