@@ -284,13 +284,14 @@ def _zero_momentum_sets(L):
 
 @pytest.mark.parametrize("mset", ["mid-17", "wrapped-33", "twice-33", "none-17"])
 @pytest.mark.parametrize("prec,kernel,nbs", [("fp64", 6, (1, 2, 3)), ("fp32", 7, (1, 2, 3, 4)),
-                                             ("fp64", 8, (1, 2, 3, 4)), ("bf16x3", 3, (1, 2))])
+                                             ("fp64", 8, (1, 2, 3, 4)), ("fp32", 9, (1, 2, 3, 4)),
+                                             ("bf16x3", 3, (1, 2))])
 def test_zero_momentum_on_vector_unit(torch_dev, prec, kernel, nbs, mset):
     """The zero momentum of a 16 k + 1 set summed on the vector unit (wherever
     it sits in the set, also as a multiple of L, once when repeated): every
     column width, split partials, both schedules bitwise equal, and the
-    oracle at the precision's tolerance.  Kernel 8 (fragments of 4) keeps
-    the zero momentum a column of its own in the same sets; BF16X3 kernel 3
+    oracle at the precision's tolerance.  Kernels 8 and 9 (fragments of 4)
+    keep the zero momentum a column of its own in the same sets; BF16X3 kernel 3
     takes it off its one fragment of 32 at 33 momenta."""
     L, ns = 5, (19, 21, 40)
     qs = fields(L, ns, workload=117)
