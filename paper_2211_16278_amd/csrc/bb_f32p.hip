@@ -398,35 +398,35 @@ __global__ void __launch_bounds__(WG, (2 * Shape<CF, B3, W>::WGS)) contract(Gemm
                     put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, col, d3, 0, (double)re);
                     put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, col, d3, 1, (double)im);
                 }
-                return;
-            }
+            } else {
 #pragma unroll
-            for (int n = 0; n < CF; ++n) {
-                const int col = p0 + n * 16 + li;
-                if (col >= n_col) continue;
-                const int p = col + (Z && col >= ps ? 1 : 0);
+                for (int n = 0; n < CF; ++n) {
+                    const int col = p0 + n * 16 + li;
+                    if (col >= n_col) continue;
+                    const int p = col + (Z && col >= ps ? 1 : 0);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int r = wave * 16 + 4 * kg + e;
-                    const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
-                    if (mo >= M12 || d3 >= bd.n3) continue;
-                    const int nu = p * bd.n3 + d3;
-                    float re = acc[0][n][e], im = acc[1][n][e];
-                    if constexpr (Sh::G3) {  // Re = P2 - P3, Im = P1 - P2 - P3
-                        const float p3 = acc[NACC - 1][n][e];
-                        re = acc[1][n][e] - p3;
-                        im = (acc[0][n][e] - acc[1][n][e]) - p3;
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = wave * 16 + 4 * kg + e;
+                        const int mo = m12_0 + r / B3, d3 = d3_0 + r % B3;
+                        if (mo >= M12 || d3 >= bd.n3) continue;
+                        const int nu = p * bd.n3 + d3;
+                        float re = acc[0][n][e], im = acc[1][n][e];
+                        if constexpr (Sh::G3) {  // Re = P2 - P3, Im = P1 - P2 - P3
+                            const float p3 = acc[NACC - 1][n][e];
+                            re = acc[1][n][e] - p3;
+                            im = (acc[0][n][e] - acc[1][n][e]) - p3;
+                        }
+                        put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 0, (double)re);
+                        put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 1, (double)im);
                     }
-                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 0, (double)re);
-                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, p, d3, 1, (double)im);
                 }
-            }
-            if (Z && zsum && kg == 0) {
-                const int mo = m12_0 + pair_l, d3 = d3_0 + d3_l;
-                if (mo < M12 && d3 < bd.n3) {
-                    const int nu = ps * bd.n3 + d3;
-                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, ps, d3, 0, (double)zr);
-                    put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, ps, d3, 1, (double)zi);
+                if (Z && zsum && kg == 0) {
+                    const int mo = m12_0 + pair_l, d3 = d3_0 + d3_l;
+                    if (mo < M12 && d3 < bd.n3) {
+                        const int nu = ps * bd.n3 + d3;
+                        put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, ps, d3, 0, (double)zr);
+                        put_result<decltype(mode)::value, float>(bd, tl.w, mo, nu, ps, d3, 1, (double)zi);
+                    }
                 }
             }
         });
