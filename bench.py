@@ -794,12 +794,17 @@ def main() -> int:
                          "flops_per_launch": f_roof,
                          "executed_flops_per_launch": f_exec,
                          "executed_frac": f_exec / (g_avg * 1e-3) / 1e12 / PEAK_TFLOPS[pname],
+                         # The paper's operation count against this path's peak: comparable
+                         # across kernels whose executed flops differ (padding, real
+                         # products, work on the vector unit).
+                         "alg_frac": f_alg / (g_avg * 1e-3) / 1e12 / PEAK_TFLOPS[pname],
                          "note": ("achieved = the paper-order algorithmic flops F_alg = 42 V n^2 + (22 + 8 n_mom) V "
                                   "n^3 per launch, on the FP64 issue rate the kernel's matrix and vector work share, "
                                   "/ mean event-timed duration of the contraction kernel; executed_frac counts the "
                                   "flops it executes (%s); step_frac uses the whole step" if paper_order else
                                   "achieved = flops one launch executes (%s) / mean event-timed duration of the "
-                                  "contraction kernel; step_frac uses the whole step") % flops_note(pname, plan)},
+                                  "contraction kernel; step_frac uses the whole step") % flops_note(pname, plan)
+                                 + "; alg_frac = F_alg per launch / mean kernel duration / peak"},
         }
         print("# %-6s %.3f ms/block  %.1f blocks/s  contraction %.3f ms  reduce %.3f ms  w-image %.3f ms  "
               "MFMA %.1f TF (%.1f%% kernel, %.1f%% step)  err %s" % (
