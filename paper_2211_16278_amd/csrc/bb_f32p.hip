@@ -1,11 +1,14 @@
-// FP32 paper-order contraction kernel of libbblock.so (gfx950, plan kernel 7).
+// FP32 paper-order contraction kernels of libbblock.so (gfx950, plan kernels
+// 7 and 9).
 //
 // The block of the paper (Sec. 2, eq. (3)) in the order of Algorithm 1, as
 // FP64 kernel 6 does it, in single precision: per site the singlet
 //   S[x; (d1,d2), d3] = sum_c D_c[x; d1,d2] q3_c[x; d3],  D_c = eps_abc q1_a q2_b,
 // formed per lane in the MFMA operand layout, then the momentum projection
 //   B[p][(d1,d2)][d3] = sum_x S[x; (d1,d2), d3] exp(-i p.x)
-// on v_mfma_f32_16x16x4_f32 with three real products up to two momentum
+// on v_mfma_f32_16x16x4_f32 (kernel 7, fragments of 16 momenta) or
+// v_mfma_f32_4x4x1_16b_f32 (kernel 9, fragments of 4: few momenta pad to a
+// multiple of 4, not of 16) with three real products up to two momentum
 // fragments (P1 = (Sr + Si)(er + ei), P2 = Sr er, P3 = Si ei; Re = P2 - P3,
 // Im = P1 - P2 - P3) and the real embedding above (four: Re += Sr er -
 // Si ei, Im += Sr ei + Si er), FP32 accumulation over a site split of at
@@ -16,13 +19,15 @@
 //
 // Workgroup: eight wave64, two per SIMD (two workgroups per CU for tiles
 // of one or two momentum fragments and d3 blocks of 16).  Tile: 128 rows = NPAIR (d1,d2)
-// pairs x a block of B3 d3 values, 16 CF momenta, one site split; wave w
+// pairs x a block of B3 d3 values, W CF momenta, one site split; wave w
 // owns rows 16 w to 16 w + 15 (16 d3 values of one pair) and all momenta:
-// 2 x CF accumulator fragments (Re, Im).  Chunks of 32 sites, double
+// CF accumulator fragments per real product.  With W = 4 each of the 16
+// blocks of an MFMA holds 4 rows at one site of the k-step; the epilogue
+// adds the four sites' blocks across lanes.  Chunks of 32 sites, double
 // buffered in LDS: the diquark of the tile's pairs, q3 of its d3 block, the
 // phases of its momenta, built from registers loaded a chunk earlier.
 //
-// Zero momentum (instantiation Z, a.p_skip >= 0), as in kernel 6: summed
+// Zero momentum (instantiation Z, kernel 7 only, a.p_skip >= 0), as in kernel 6: summed
 // per lane on the vector unit, reduced across the k-groups at the end and
 // written by the tiles of column block 0; the columns hold the other
 // momenta.  Z kernels of two workgroups per CU are held to 128 VGPRs by
