@@ -27,7 +27,11 @@
 // A operand of a k-step (4 sites) is the singlet itself: lane l forms S of
 // row l % 16 of each row set at site l / 16 from the diquark and q3 tiles in
 // LDS, in registers, and feeds it to the MFMAs (both MFMA forms take A[i][k]
-// from lane i + 16 k).  Per chunk of 32 sites (16 where two
+// from lane i + 16 k).  Where the registers allow (W = 4, or one fragment
+// of 16) the singlets run one k-step ahead: a k-step's MFMAs take the
+// singlets formed in the previous one, and the next singlets form after
+// them, so the vector chain's latency is not in front of the MFMAs that
+// wait for it.  Per chunk of 32 sites (16 where two
 // buffers of 32 would not fit the LDS) the
 // workgroup builds the next chunk's tiles (the diquark of its pairs, q3 of
 // its d3 block, the phases of its momenta with their Re + Im plane) into the
