@@ -114,15 +114,19 @@ struct In<true> {
 };
 
 template <bool C64>
-__device__ __forceinline__ double2 ldq(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+__device__ __forceinline__ std::conditional_t<C64, float2, double2> ldq(__amdgpu_buffer_rsrc_t rs, uint32_t off)
 {
-    if constexpr (C64) {
-        const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-        return make_double2(v.x, v.y);
-    } else {
+    // As loaded: a complex64 value is widened where it is used (to_f64), so
+    // that the load is waited for there, a chunk after its issue, and stays
+    // in two registers meanwhile.
+    if constexpr (C64)
+        return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    else
         return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-    }
 }
+
+__device__ __forceinline__ double2 to_f64(double2 v) { return v; }
+__device__ __forceinline__ double2 to_f64(float2 v) { return make_double2(v.x, v.y); }
 
 // Resource over sites [x0, x0 + SITES) of a field [V][3][n] (bytes in range:
 // the sites below xe only; none when x0 >= xe).
@@ -216,7 +220,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
         }
         const int krec = a.n_mom * a.kstride;
 
-        double2 u[3], v[3], w[Sh::JQ];
+        std::conditional_t<C64, float2, double2> u[3], v[3], w[Sh::JQ];
         uint32_t kk[Sh::JP];
         auto issue = [&](int ci) {
             const int x0 = __builtin_amdgcn_readfirstlane(xs + ci * SITES);
@@ -249,8 +253,8 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
             if (has_d) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const double2 ua = u[(c + 1) % 3], ub = u[(c + 2) % 3];
-                    const double2 va = v[(c + 1) % 3], vb = v[(c + 2) % 3];
+                    const double2 ua = to_f64(u[(c + 1) % 3]), ub = to_f64(u[(c + 2) % 3]);
+                    const double2 va = to_f64(v[(c + 1) % 3]), vb = to_f64(v[(c + 2) % 3]);
                     const double re = __builtin_fma(ua.x, vb.x, __builtin_fma(-ua.y, vb.y, __builtin_fma(-ub.x, va.x, ub.y * va.y)));
                     const double im = __builtin_fma(ua.x, vb.y, __builtin_fma(ua.y, vb.x, __builtin_fma(-ub.x, va.y, -(ub.y * va.x))));
                     Dt[(c * SITES + ds) * Sh::DST + dp] = make_double2(re, im);
@@ -261,7 +265,7 @@ __global__ void __launch_bounds__(WG, 1) contract(GemmArgs a)
                 const int q = tid + WG * j;
                 if (q < Sh::NQ) {
                     const int d = q % B3, sc = q / B3, s = sc / 3, c = sc - 3 * s;
-                    Qt[(c * SITES + s) * B3 + d] = w[j];
+                    Qt[(c * SITES + s) * B3 + d] = to_f64(w[j]);
                 }
             }
 #pragma unroll
